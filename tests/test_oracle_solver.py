@@ -1,0 +1,188 @@
+"""Pins of the oracle's ProxSkip-SVRG loop (Algorithm 1, ProxSVRGSkip row) and its random
+streams (no GPU).
+
+The paper prints no iterate values, so the loop is pinned by the reductions the paper and the
+mathematics fix: p = 1 is proximal gradient (ProxSVRG); a trivial prox leaves h at zero and
+gives plain SVRG descent; N = 1 gives deterministic ProxSkip with G = grad f; and with both,
+the iterates are gradient descent on least squares, whose k-th iterate has a closed form.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _problem(orc, nx=12, ny=12, A=24, B=18, N=4, seed=0):
+    g = orc.Geometry(nx, ny, n_angles=A, n_bins=B, n_subsets=N)
+    rng = np.random.default_rng(seed)
+    b = np.abs(rng.standard_normal((1, A, B))) * 5.0
+    return g, b
+
+
+# ---------------------------------------------------------------------------------------------
+# Random streams.
+# ---------------------------------------------------------------------------------------------
+
+def test_splitmix64_published_outputs(orc):
+    spec = json.load(open(os.path.join(GOLDEN, "splitmix64_seed0.json")))
+    for j, hx in enumerate(spec["outputs_hex"]):
+        assert orc.splitmix64(spec["seed"], j) == int(hx, 16)
+
+
+def test_sequences_statistics(orc):
+    n = 1_000_000
+    for p in (0.5, 0.1, 0.02):
+        _, coin = orc.sequences(12345, 0, n, 20, p)
+        sd = np.sqrt(n * p * (1 - p))
+        assert abs(int(coin.sum()) - n * p) <= 5 * sd
+    _, coin = orc.sequences(7, 0, 10000, 5, 1.0)
+    assert coin.all()
+    sub, _ = orc.sequences(99, 0, n, 20, 0.1)
+    assert sub.min() == 0 and sub.max() == 19
+    counts = np.bincount(sub, minlength=20)
+    chi2 = float(np.sum((counts - n / 20) ** 2 / (n / 20)))
+    assert chi2 < 60.0   # 19 dof; P(chi2 > 60) ~ 3e-6
+
+
+def test_sequences_are_counter_based(orc):
+    s_all, c_all = orc.sequences(5, 0, 300, 7, 0.3)
+    s_tail, c_tail = orc.sequences(5, 140, 160, 7, 0.3)
+    assert np.array_equal(s_all[140:], s_tail) and np.array_equal(c_all[140:], c_tail)
+
+
+# ---------------------------------------------------------------------------------------------
+# Reductions of Algorithm 1.
+# ---------------------------------------------------------------------------------------------
+
+def test_p1_equals_proximal_svrg(orc):
+    # p = 1: every iteration applies the prox and x+ = prox_{gamma g}(x - gamma G)  (Sec. 1.1).
+    g, b = _problem(orc)
+    gamma = 1.0 / orc.lipschitz(g, 300)
+    kw = dict(gamma=gamma, alpha=2.0, fgp_inner=20, n_epochs=5, nonneg=True, seed=11)
+    xs1, h1, d1, st1, _ = orc.proxskip_svrg(g, b, p=1.0, **kw)
+    assert st1["prox_calls"] == st1["iters_done"] == 20
+    xs2, _, d2, st2, _ = orc.proxskip_svrg(g, b, p=1.0, plain=True, **kw)
+    assert np.max(np.abs(xs1 - xs2)) <= 1e-12 * np.max(np.abs(xs2))
+    # and the same proximal-SVRG iteration composed here from oracle primitives
+    N = g.n_subsets
+    sub, _ = orc.sequences(11, 0, 20, N, 1.0)
+    x = np.zeros((1, 12, 12))
+    dual = np.zeros((2, 1, 12, 12))
+    for k in range(20):
+        if k % N == 0:
+            snap = x.copy()
+            gs = orc.grad_full(g, snap, b)
+        i = sub[k]
+        G = N * (orc.grad_subset(g, x, b, i) - orc.grad_subset(g, snap, b, i)) + gs
+        x = orc.tv_prox_fgp(x - gamma * G, gamma * 2.0, 20, nonneg=True, dual=dual)
+    assert np.max(np.abs(xs1 - x)) <= 1e-12 * np.max(np.abs(x))
+
+
+@pytest.mark.parametrize("p", [0.3, 1.0])
+def test_trivial_prox_is_plain_svrg_descent(orc, p):
+    # alpha = 0 and no constraint: the prox is the identity, h stays exactly zero and the
+    # iterates are SVRG gradient steps, bit for bit.
+    g, b = _problem(orc, seed=1)
+    gamma = 1.0 / orc.lipschitz(g, 300)
+    N = g.n_subsets
+    x_o, h_o, _, st, _ = orc.proxskip_svrg(g, b, gamma=gamma, p=p, alpha=0.0, fgp_inner=5,
+                                           n_epochs=4, nonneg=False, seed=3)
+    assert np.array_equal(h_o, np.zeros_like(h_o))
+    sub, _ = orc.sequences(3, 0, 4 * N, N, p)
+    x = np.zeros((1, 12, 12))
+    for k in range(4 * N):
+        if k % N == 0:
+            snap = x.copy()
+            gs = orc.grad_full(g, snap, b)
+        i = sub[k]
+        G = N * (orc.grad_subset(g, x, b, i) - orc.grad_subset(g, snap, b, i)) + gs
+        x = x - gamma * G
+    assert np.array_equal(x_o, x)
+
+
+def test_single_subset_is_deterministic_proxskip(orc):
+    # N = 1: the snapshot is refreshed every iteration, so G = grad f(x_k) exactly.
+    g, b = _problem(orc, N=1, seed=2)
+    gamma = 1.0 / orc.lipschitz(g, 300)
+    p, alpha = 0.4, 1.5
+    x_o, h_o, _, st, _ = orc.proxskip_svrg(g, b, gamma=gamma, p=p, alpha=alpha, fgp_inner=15,
+                                           n_epochs=25, nonneg=True, seed=8)
+    _, coin = orc.sequences(8, 0, 25, 1, p)
+    assert st["prox_calls"] == int(coin.sum())
+    x = np.zeros((1, 12, 12))
+    h = np.zeros_like(x)
+    dual = np.zeros((2, 1, 12, 12))
+    for k in range(25):
+        xh = x - gamma * (orc.grad_full(g, x, b) - h)
+        if coin[k]:
+            xn = orc.tv_prox_fgp(xh - (gamma / p) * h, gamma * alpha / p, 15, nonneg=True,
+                                 dual=dual)
+        else:
+            xn = xh
+        h = h + (p / gamma) * (xn - xh)
+        x = xn
+    assert np.max(np.abs(x_o - x)) <= 1e-14 * np.max(np.abs(x))
+    assert np.max(np.abs(h_o - h)) <= 1e-12 * max(np.max(np.abs(h)), 1e-300)
+
+
+def test_gradient_descent_closed_form(orc):
+    # alpha = 0, no constraint, N = 1, p = 1: gradient descent on 1/2||Ax - b||^2 from x0 = 0,
+    # x_k = x* - V diag((1 - gamma lambda)^k) V^T x*  with A^T A = V diag(lambda) V^T.
+    n, A, B = 10, 24, 16
+    g = orc.Geometry(n, n, n_angles=A, n_bins=B, n_subsets=1)
+    M = np.zeros((A * B, n * n))
+    for e in range(n * n):
+        v = np.zeros(n * n)
+        v[e] = 1.0
+        M[:, e] = orc.project(g, v.reshape(1, n, n)).ravel()
+    lam, V = np.linalg.eigh(M.T @ M)
+    assert lam[0] > 0.0
+    rng = np.random.default_rng(4)
+    b = rng.standard_normal((1, A, B))
+    xstar = np.linalg.lstsq(M, b.ravel(), rcond=None)[0]
+    gamma = 1.0 / lam[-1]
+    K = 150
+    x_o, h_o, _, _, _ = orc.proxskip_svrg(g, b, gamma=gamma, p=1.0, alpha=0.0, fgp_inner=1,
+                                          n_epochs=K, nonneg=False, seed=0)
+    xk = xstar - V @ (((1.0 - gamma * lam) ** K) * (V.T @ xstar))
+    assert np.linalg.norm(x_o.ravel() - xk) <= 1e-10 * np.linalg.norm(xk)
+    assert np.max(np.abs(h_o)) <= 1e-9 * np.max(np.abs(M.T @ b.ravel()))
+
+
+def test_resume_is_bit_identical(orc):
+    g, b = _problem(orc, seed=5)
+    gamma = 1.0 / orc.lipschitz(g, 300)
+    kw = dict(gamma=gamma, p=0.3, alpha=1.0, fgp_inner=10, nonneg=True, seed=21)
+    x4, h4, d4, st4, rel4 = orc.proxskip_svrg(g, b, n_epochs=4, **kw)
+    x2, h2, d2, st2, rel2 = orc.proxskip_svrg(g, b, n_epochs=2, **kw)
+    x2b, h2b, d2b, st2b, rel2b = orc.proxskip_svrg(g, b, n_epochs=2, k0=2 * g.n_subsets, x=x2,
+                                                    h=h2, dual=d2, **kw)
+    assert np.array_equal(x4, x2b) and np.array_equal(h4, h2b) and np.array_equal(d4, d2b)
+    assert np.array_equal(rel4, np.concatenate([rel2, rel2b]))
+    assert st4["prox_calls"] == st2["prox_calls"] + st2b["prox_calls"]
+
+
+def test_tolerance_stop(orc):
+    g, b = _problem(orc, seed=6)
+    gamma = 1.0 / orc.lipschitz(g, 300)
+    kw = dict(gamma=gamma, p=0.5, alpha=0.5, fgp_inner=10, nonneg=True, seed=2)
+    _, _, _, st, rel = orc.proxskip_svrg(g, b, n_epochs=40, **kw)
+    tol = float(rel[10]) * 1.0000001
+    first = int(np.argmax(rel < tol))
+    _, _, _, st_t, rel_t = orc.proxskip_svrg(g, b, n_epochs=40, tol=tol, **kw)
+    assert st_t["epochs_done"] == first + 1
+    assert np.array_equal(rel_t, rel[: first + 1])
+    assert st_t["iters_done"] == (first + 1) * g.n_subsets
+
+
+def test_invalid_arguments(orc):
+    g, b = _problem(orc)
+    with pytest.raises(ValueError):
+        orc.proxskip_svrg(g, b, gamma=1e-3, p=0.0, alpha=0.1, fgp_inner=5, n_epochs=1)
+    with pytest.raises(ValueError):
+        orc.proxskip_svrg(g, b, gamma=-1.0, p=0.5, alpha=0.1, fgp_inner=5, n_epochs=1)
+    with pytest.raises(ValueError):
+        orc.proxskip_svrg(g, b, gamma=1e-3, p=0.5, alpha=0.1, fgp_inner=5, n_epochs=1, k0=1)
