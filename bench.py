@@ -1,0 +1,226 @@
+"""Benchmark: ProxSkip-SVRG epochs per second on one MI355X.
+
+Workload (default): the single 512^2 solve -- 720 angles x 768 bins, 20 interleaved subsets,
+p = 0.1, alpha = 0.005, 50 warm-started FGP iterations per prox, seeded random-ellipse phantom
+with exact line-integral data and 1% Gaussian noise.  One step = one epoch (N = 20 iterations:
+the SVRG snapshot with its full projection/backprojection, 20 subset projection/backprojection
+pairs with the fused SVRG/ProxSkip update, and the FGP prox on the coin flips that hit).
+
+Prints one JSON line.  Besides the timed epochs it reports:
+  roofline      the dominant kernel's algorithmic rate against the chip's peak, its duration
+                measured here with HIP events on the launching stream;
+  cpu_baseline  the FP64 oracle timed on the host cores over a short sample of the same solve;
+  parity        the GPU iterate against the oracle's after that sample;
+  sweep         epochs/s and prox calls at p in {1, 0.1, 0.02} and non-skipped ProxSVRG.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "epochs/s to 1e-4 rel-err vs oracle; projector HBM GB/s; p50/p99 recon latency"
+HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--p", type=float, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--cpu-epochs", type=int, default=3)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 256 MiB device copy (for HBM counter scaling)")
+    return ap.parse_args()
+
+
+def calibrate_copy():
+    import torch
+    n = 64 * 1024 * 1024  # 256 MiB of float32
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes_each_way": 4 * n, "launches": 3}), flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+    from paper_2602_09527_amd import api, synth, workloads
+
+    w = workloads.SINGLE_2D
+    p = w.p if args.p is None else args.p
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    log(f"bench: workload {w.name}: {w.nx}x{w.ny}, {w.n_angles} angles x {w.n_bins} bins, "
+        f"N={w.n_subsets}, p={p}, alpha={w.alpha}, fgp_inner={w.fgp_inner}")
+    t0 = time.time()
+    prob = synth.make_problem(w.nx, w.ny, w.n_angles, w.n_bins, seed=w.seed, noise=w.noise,
+                              with_phantom=False)
+    log(f"bench: synthetic data in {time.time() - t0:.1f} s")
+    g = api.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=w.n_subsets, device=dev)
+    b = torch.from_numpy(prob.b).to(device=dev, dtype=torch.float32)
+    L_gpu = api.lipschitz(g, 50)
+    gamma = 1.0 / L_gpu
+    log(f"bench: L (GPU power method) = {L_gpu:.6f}")
+
+    def params(n_epochs, **kw):
+        d = dict(gamma=gamma, p=p, alpha=w.alpha, fgp_inner=w.fgp_inner, n_epochs=n_epochs,
+                 nonneg=w.nonneg, seed=w.seed + 2)
+        d.update(kw)
+        return api.SolverParams(**d)
+
+    # ---- timed region: K epochs of one continuing solve ------------------------------------
+    K, W = args.steps, args.warmup
+    s = api.Solver(g, b, params(W + K))
+    s.epochs(W)
+    s.query()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.epochs(K)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = s.query()
+    eps = K / el
+    log(f"bench: {K} epochs in {el:.4f} s -> {eps:.1f} epochs/s; prox calls {st['prox_calls']}, "
+        f"last rel change {st['last_rel_change']:.3e}")
+
+    # ---- dominant kernels: HIP events around their launches on the current stream ---------
+    def event_time(fn, reps=30):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3  # seconds per launch
+
+    x = s.x
+    ysub = torch.empty(g.sino_shape(0), dtype=torch.float32, device=dev)
+    yfull = torch.empty(g.sino_shape(-1), dtype=torch.float32, device=dev)
+    img = torch.empty_like(x)
+    t_bp_full = event_time(lambda: api.backproject(g, yfull, -1, out=img))
+    t_bp_sub = event_time(lambda: api.backproject(g, ysub, 0, out=img))
+    t_fp_full = event_time(lambda: api.project(g, x, -1, out=yfull))
+    t_fp_sub = event_time(lambda: api.project(g, x, 0, out=ysub))
+    n = w.nx * w.ny
+    a_sub = g.subset_size(0)
+    # algorithmic work: 7 flops per interpolation (position step, fraction, 1 - w, two products,
+    # two adds); the backprojector does the same per pixel-angle-sample (2 samples per pair).
+    fp_full_flops = 7.0 * w.n_angles * w.n_bins * max(w.nx, w.ny)
+    bp_full_flops = 7.0 * 2 * w.n_angles * n
+    bytes_fp_full = 4.0 * (n + w.n_angles * w.n_bins)
+    bytes_fp_sub = 4.0 * (2 * n + a_sub * w.n_bins)
+    bytes_bp_full = 4.0 * (w.n_angles * w.n_bins + n)
+    kern = {
+        "backproject_full": {"s": t_bp_full, "tflops": bp_full_flops / t_bp_full / 1e12,
+                             "gbs": bytes_bp_full / t_bp_full / 1e9},
+        "project_full": {"s": t_fp_full, "tflops": fp_full_flops / t_fp_full / 1e12,
+                         "gbs": bytes_fp_full / t_fp_full / 1e9},
+        "backproject_subset": {"s": t_bp_sub},
+        "project_subset": {"s": t_fp_sub, "gbs": bytes_fp_sub / t_fp_sub / 1e9},
+    }
+    for k_, v in kern.items():
+        log(f"bench: {k_}: {v['s'] * 1e6:.1f} us/launch " +
+            " ".join(f"{kk}={vv:.3f}" for kk, vv in v.items() if kk != "s"))
+    dom = "backproject_full" if t_bp_full >= t_fp_full else "project_full"
+    dk = kern[dom]
+    roofline = {"kernel": "k_backproject (all angles)" if dom == "backproject_full" else
+                "k_project (all angles)",
+                "bound": "alu", "achieved": round(dk["tflops"], 4), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(dk["tflops"] / FP32_VECTOR_PEAK_TFLOPS, 5),
+                "traffic": None, "us_per_launch": round(dk["s"] * 1e6, 2)}
+
+    out = {
+        "metric": METRIC, "value": round(eps, 3), "unit": "epochs/s", "n_gpus": 1, "steps": K,
+        "warmup": W, "ms_per_step": round(1e3 * el / K, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w.name, "image": f"{w.nx}x{w.ny}", "angles": w.n_angles,
+                   "bins": w.n_bins, "subsets": w.n_subsets, "p": p, "alpha": w.alpha,
+                   "fgp_inner": w.fgp_inner, "method": "ProxSkip-SVRG"},
+        "roofline": roofline,
+        "projector_hbm_gbs": round(kern["project_full"]["gbs"], 2),
+        "kernels_us": {k_: round(v["s"] * 1e6, 2) for k_, v in kern.items()},
+    }
+
+    # ---- p sweep (same data), short runs ---------------------------------------------------
+    if not args.no_sweep:
+        sweep = []
+        for label, kw in (("p=1", dict(p=1.0)), ("p=0.1", dict(p=0.1)), ("p=0.02", dict(p=0.02)),
+                          ("ProxSVRG", dict(p=1.0, plain_prox_svrg=True))):
+            E = 20
+            sv = api.Solver(g, b, params(E + 2, **kw))
+            sv.epochs(2)
+            sv.query()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            sv.epochs(E)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+            q = sv.query()
+            sweep.append({"run": label, "epochs_per_s": round(E / dt, 2),
+                          "prox_calls": q["prox_calls"], "rel_change": q["last_rel_change"]})
+            log(f"bench: sweep {label}: {E / dt:.1f} epochs/s, prox calls {q['prox_calls']}")
+        out["sweep"] = sweep
+
+    # ---- CPU oracle baseline on a bounded sample + parity of that sample -------------------
+    if not args.no_cpu_baseline:
+        import oracle
+        E = args.cpu_epochs
+        og = oracle.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=w.n_subsets)
+        # step size from the oracle's own power method (stored by tests/golden/make_lipschitz.py),
+        # the same double on both sides of the parity check
+        with open(os.path.join(ROOT, "tests", "golden", "lipschitz.json")) as f:
+            gamma_o = 1.0 / json.load(f)[w.key]["L"]
+        kw = dict(gamma=gamma_o, p=p, alpha=w.alpha, fgp_inner=w.fgp_inner, n_epochs=E,
+                  nonneg=w.nonneg, seed=w.seed + 2)
+        t1 = time.perf_counter()
+        c0 = time.process_time()
+        xo, _, _, so, _ = oracle.proxskip_svrg(og, prob.b, **kw)
+        cpu_wall = time.perf_counter() - t1
+        cpu_proc = time.process_time() - c0
+        threads = oracle.num_threads()
+        xg, _, _, sg = api.solve(g, b, api.SolverParams(**kw))
+        torch.cuda.synchronize()
+        xg = xg.cpu().numpy().astype(np.float64)
+        rel = float(np.linalg.norm(xg - xo) / np.linalg.norm(xo))
+        out["cpu_baseline"] = {"value": round(E / cpu_wall, 4), "unit": "epochs/s",
+                               "cores": threads, "kind": "oracle",
+                               "sample": f"{E} epochs of the same solve from x0 = 0 "
+                                         f"(FP64, OpenMP over output elements); "
+                                         f"{cpu_wall:.1f} s wall, {cpu_proc:.1f} s CPU"}
+        out["parity"] = {"epochs": E, "rel_l2_vs_oracle": rel, "bar": 1e-4,
+                         "prox_calls_gpu": sg["prox_calls"], "prox_calls_oracle": so["prox_calls"]}
+        log(f"bench: oracle {E} epochs in {cpu_wall:.1f} s ({threads} threads); "
+            f"GPU vs oracle rel L2 = {rel:.3e}")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

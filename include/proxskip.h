@@ -1,0 +1,193 @@
+/*
+ * proxskip.h -- C ABI of the MI355X (gfx950) library for TV-regularised parallel-beam tomography
+ * solved by ProxSkip with the SVRG gradient estimator (ProxSVRGSkip).
+ *
+ * Problem (Sec. 2.1, Eq. 4, an instance of Eq. 1):
+ *     min_x  1/2 ||A x - b||^2 + alpha TV(x) + I_{x >= 0}(x)
+ * with A the discrete Radon transform, split into N subsets of interleaved angles
+ * (A_i, b_i), i = 0..N-1, subset i holding the angles {i, i+N, i+2N, ...} (Sec. 1.2, the
+ * data-splitting figure of Sec. 1.3).
+ *
+ * Conventions shared by every call:
+ *   - Image x: [nz][ny][nx] row-major.  Pixel (i, j) has centre (j - (nx-1)/2, i - (ny-1)/2) in
+ *     pixel units.  Slices are independent for the projector (parallel beam, rotation axis z).
+ *   - Angles theta_k = k*pi/A (k = 0..A-1) unless a table is given.  Detector bin u has centre
+ *     s_u = (u - (B-1)/2) * bin_width + det_offset; ray (k, u) is {x cos + y sin = s_u}.
+ *   - Sinogram b: [nz][A][B].  A subset sinogram y_i: [nz][a_i][B], its angles in increasing
+ *     order, a_i = number of k < A with k mod N == i.
+ *   - Dual field (TV prox warm start): [d][nz][ny][nx], d = 2 when nz == 1 and d = 3 otherwise
+ *     (3D TV couples slices).
+ *   - Every floating-point buffer has the geometry's dtype (float or double).
+ *   - Device pointers are HIP device memory owned by the caller, contiguous, aligned to at least
+ *     the dtype size.  The library never allocates or frees device memory: work buffers are
+ *     passed in as a caller-owned workspace whose size the *_workspace_bytes queries return.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls that launch kernels return
+ *     as soon as the work is queued (stream-ordered); asynchronous faults surface at the next
+ *     synchronisation.
+ *   - Every call returns a ps_status; on failure last_error_message() (per thread) describes it.
+ *     Argument checks run on the host before anything is queued.
+ */
+#ifndef PROXSKIP_H
+#define PROXSKIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__) || defined(__clang__)
+#define PS_API __attribute__((visibility("default")))
+#else
+#define PS_API
+#endif
+
+typedef enum {
+    PS_OK = 0,
+    PS_EINVAL = -1,       /* invalid argument or workspace too small                         */
+    PS_ENOMEM = -2,       /* host allocation failed                                           */
+    PS_EHIP = -3,         /* a HIP runtime call or kernel launch failed                       */
+    PS_EBUDGET = -4,      /* reserved for admission control above this library                */
+    PS_ENONFINITE = -5,   /* a non-finite iterate was detected at an epoch end                */
+    PS_ECANCELLED = -6,   /* the solver handle was cancelled                                  */
+    PS_EUNSUPPORTED = -7  /* shape outside what the kernels support (a side > 4096, B > 2048) */
+} ps_status;
+
+typedef enum { PS_F32 = 0, PS_F64 = 1 } ps_dtype;
+
+/* Parallel-beam geometry (Sec. 2.1: discrete Radon transform; Sec. 1.2: angle subsets). */
+typedef struct {
+    int32_t nx, ny, nz;      /* image columns, rows, slices (nz = 1 for 2D)                    */
+    int32_t n_angles;        /* A >= 1                                                          */
+    const double *angles;    /* optional host table of A angles in radians (copied); NULL =>   */
+                             /* uniform k*pi/A                                                  */
+    int32_t n_bins;          /* B >= 1                                                          */
+    double bin_width;        /* detector bin width in pixel units, > 0 (1.0 = pixel width)      */
+    double det_offset;       /* detector centre offset in pixel units                           */
+    int32_t n_subsets;       /* N >= 1, at most A                                               */
+    ps_dtype dtype;          /* precision of every buffer and of the arithmetic                 */
+} ps_geometry_desc;
+
+typedef struct ps_geometry ps_geometry;  /* opaque; immutable after geometry_upload            */
+
+/* Validate `desc` and build the host-side geometry (per-angle tables, launch plans).
+ * No device work.  Errors: PS_EINVAL (bad sizes, N > A, bin_width <= 0), PS_EUNSUPPORTED. */
+PS_API ps_status make_geometry(const ps_geometry_desc *desc, ps_geometry **out);
+PS_API void free_geometry(ps_geometry *geom);
+
+/* Bytes of device memory the geometry's per-angle tables need. */
+PS_API size_t geometry_device_bytes(const ps_geometry *geom);
+
+/* Copy the per-angle tables into caller-owned device memory `dev_buf` (at least
+ * geometry_device_bytes bytes, 256-byte aligned), stream-ordered.  The geometry keeps the
+ * pointer: `dev_buf` must outlive every call made with this geometry. */
+PS_API ps_status geometry_upload(ps_geometry *geom, void *dev_buf, size_t bytes, void *stream);
+
+/* a_i, the number of angles in subset i; subset = -1 => A.  Returns -1 for a bad subset. */
+PS_API int32_t subset_size(const ps_geometry *geom, int32_t subset);
+
+/* Forward projection y = A_i x (Sec. 1.2: the subset operator A_i), ray-driven Joseph
+ * interpolation.  subset = -1 projects all A angles (y = [nz][A][B]).
+ * x: device [nz][ny][nx]; y: device [nz][a_i][B], overwritten.
+ * workspace: device scratch of at least project_workspace_bytes(geom, subset) bytes (may be
+ * NULL when that is 0).  Errors: PS_EINVAL, PS_EHIP. */
+PS_API size_t project_workspace_bytes(const ps_geometry *geom, int32_t subset);
+PS_API ps_status project_subset(const ps_geometry *geom, int32_t subset, const void *x, void *y,
+                         void *workspace, size_t ws_bytes, void *stream);
+
+/* Backprojection x = A_i^T y (accumulate = 0) or x += A_i^T y (accumulate = 1): the exact
+ * adjoint of project_subset, computed pixel by pixel (gather) with the same interpolation
+ * weights.  y: device [nz][a_i][B]; x: device [nz][ny][nx].  Errors: PS_EINVAL, PS_EHIP. */
+PS_API ps_status backproject_subset(const ps_geometry *geom, int32_t subset, const void *y, void *x,
+                             int32_t accumulate, void *stream);
+
+/* Proximal operator of g = TV + I_C (Eq. 3 with the regulariser of Eq. 4), with weight tau:
+ *     z = argmin_z 1/2 ||z - v||^2 + tau TV(z) + I_C(z),   C = {z >= 0} if nonneg else R^n,
+ * isotropic TV with forward differences (zero last difference), solved by n_inner iterations of
+ * FGP (Beck & Teboulle 2009), warm-started from `dual` (Sec. 2.1: a fixed number of
+ * warm-started inner iterations).
+ * v, z: device [nz][ny][nx]; z may alias v.  dual: device [d][nz][ny][nx], in = warm start,
+ * out = final dual; NULL => cold start from zeros and not returned.  tau == 0 => z = P_C(v),
+ * dual untouched.  workspace: at least tv_prox_workspace_bytes(geom) bytes.
+ * Errors: PS_EINVAL (tau < 0, n_inner < 0, workspace too small), PS_EHIP. */
+PS_API size_t tv_prox_workspace_bytes(const ps_geometry *geom);
+PS_API ps_status tv_prox_fgp(const ps_geometry *geom, const void *v, void *z, double tau,
+                      int32_t n_inner, int32_t nonneg, void *dual, void *workspace,
+                      size_t ws_bytes, void *stream);
+
+/* Parameters of Algorithm 1 (Sec. 1.3) with the SVRG estimator. */
+typedef struct {
+    double gamma;             /* step size > 0 (the paper uses 1/L, L = ||A||^2)                */
+    double p;                 /* prox probability, 0 < p <= 1                                   */
+    double alpha;             /* TV weight >= 0                                                  */
+    int32_t fgp_inner;        /* FGP iterations per prox call >= 0                              */
+    int32_t nonneg;           /* 1 => g includes I_{x >= 0}                                      */
+    int32_t n_epochs;         /* epochs to run (1 epoch = N iterations = one data pass)         */
+    int32_t plain_prox_svrg;  /* 1 => non-skipped ProxSVRG: x+ = prox_{gamma g}(x - gamma G),   */
+                              /*      h untouched                                                */
+    uint64_t seed;            /* seed of the subset and coin streams                            */
+    int64_t k0;               /* first iteration index (resume point), a multiple of N          */
+    double tol_rel_change;    /* > 0 => stop at the first epoch end with                        */
+                              /*   ||x_e - x_{e-1}|| / ||x_e|| < tol; 0 => run n_epochs         */
+} ps_solver_params;
+
+typedef struct {
+    int32_t epochs_done;      /* epochs completed by the last run / since solver_init           */
+    int32_t iters_done;       /* iterations completed (k - k0)                                  */
+    int32_t prox_calls;       /* prox evaluations (coin flips theta_k = 1)                      */
+    double last_rel_change;   /* ||x_e - x_{e-1}|| / ||x_e|| at the last completed epoch end   */
+} ps_solver_stats;
+
+/* ProxSkip-SVRG (Algorithm 1, ProxSVRGSkip row of its table):
+ *   every N iterations (k mod N == 0): snapshot xs = x_k, gs = grad f(xs) = A^T (A xs - b)
+ *   G_k  = N (grad f_i(x_k) - grad f_i(xs)) + gs,   i = i_k uniform on {0..N-1}
+ *   xh   = x_k - gamma (G_k - h_k)
+ *   theta_k ~ Bernoulli(p): x_{k+1} = prox_{(gamma/p) g}(xh - (gamma/p) h_k) if theta_k = 1,
+ *                           else x_{k+1} = xh
+ *   h_{k+1} = h_k + (p/gamma)(x_{k+1} - xh)
+ * with g = alpha TV + I_C, the prox by tv_prox_fgp with fgp_inner warm-started iterations, and
+ * i_k, theta_k from sample_sequences(seed, ...).
+ * b: device [nz][A][B].  x, h, dual: device, in = state at k0 (zeros for a fresh run),
+ * out = state after the run.  (x, h, dual, k) is the complete resumable state.
+ * workspace: at least proxskip_workspace_bytes(geom, params) bytes.  stats_out may be NULL.
+ * Synchronises `stream` once at the end (and at every epoch end when tol_rel_change > 0).
+ * Errors: PS_EINVAL, PS_EHIP, PS_ENONFINITE. */
+PS_API size_t proxskip_workspace_bytes(const ps_geometry *geom, const ps_solver_params *params);
+PS_API ps_status proxskip_svrg_run(const ps_geometry *geom, const void *b, void *x, void *h,
+                            void *dual, const ps_solver_params *params,
+                            ps_solver_stats *stats_out, void *workspace, size_t ws_bytes,
+                            void *stream);
+
+/* Resumable solver handles (the same iteration as proxskip_svrg_run, split into calls).
+ * solver_init binds caller-owned buffers (they must outlive the handle; the workspace must be
+ * proxskip_workspace_bytes(geom, params) bytes and may not be shared between live handles).
+ * solver_epochs queues n_epochs further epochs of every handle on `stream`, interleaving the
+ * handles epoch by epoch; handles that already met their tolerance or epoch budget are skipped.
+ * solver_query synchronises the handle's stream and reports its progress.
+ * solver_cancel makes later solver_epochs calls on the handle return PS_ECANCELLED. */
+typedef struct ps_solver ps_solver;
+PS_API ps_status solver_init(const ps_geometry *geom, const void *b, void *x, void *h, void *dual,
+                      const ps_solver_params *params, void *workspace, size_t ws_bytes,
+                      ps_solver **out);
+PS_API ps_status solver_epochs(ps_solver *const *handles, int32_t n_handles, int32_t n_epochs,
+                        void *stream);
+PS_API ps_status solver_query(ps_solver *handle, ps_solver_stats *stats_out);
+PS_API ps_status solver_cancel(ps_solver *handle);
+PS_API void solver_free(ps_solver *handle);
+
+/* Host-side random streams (the library's own counter-based SplitMix64):
+ *   u(seed, j) = mix64(seed + (j + 1) * 0x9e3779b97f4a7c15)   (Steele, Lea & Flood 2014)
+ *   i_k = ((u(seed, 2k) >> 32) * N) >> 32,  theta_k = (u(seed, 2k+1) >> 11) < floor(p * 2^53)
+ * for k = k0 .. k0+count-1 (Sec. 1.2 "sampling i_k"; Algorithm 1: theta_k ~ Bernoulli(p)).
+ * Either output may be NULL.  Errors: PS_EINVAL. */
+PS_API ps_status sample_sequences(uint64_t seed, int64_t k0, int64_t count, int32_t n_subsets,
+                           double p, int32_t *subset_out, uint8_t *coin_out);
+
+/* Description of the last error on the calling thread ("" if none). */
+PS_API const char *last_error_message(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PROXSKIP_H */

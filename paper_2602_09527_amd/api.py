@@ -1,0 +1,295 @@
+"""Python binding over the C ABI: torch tensors in, torch tensors out.
+
+PyTorch only provides device memory and streams here; every step runs in the library's HIP
+kernels.  Buffers follow the layouts of include/proxskip.h: image [nz][ny][nx], sinogram
+[nz][A][B], subset sinogram [nz][a_i][B], dual [d][nz][ny][nx].
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import math
+
+import numpy as np
+import torch
+
+from . import _native as nat
+
+_DTYPES = {torch.float32: nat.PS_F32, torch.float64: nat.PS_F64}
+
+
+def _stream(device: torch.device) -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr() if t is not None else None)
+
+
+class Geometry:
+    """Parallel-beam geometry with its per-angle tables resident on ``device``."""
+
+    def __init__(self, nx: int, ny: int, n_angles: int, n_bins: int, n_subsets: int = 1,
+                 nz: int = 1, bin_width: float = 1.0, det_offset: float = 0.0,
+                 angles=None, dtype: torch.dtype = torch.float32, device="cuda"):
+        if dtype not in _DTYPES:
+            raise TypeError(f"dtype must be float32 or float64, got {dtype}")
+        self.lib = nat.load()
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.n_angles, self.n_bins, self.n_subsets = int(n_angles), int(n_bins), int(n_subsets)
+        self.bin_width, self.det_offset = float(bin_width), float(det_offset)
+        self.dtype = dtype
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise ValueError("the library runs on the GPU only; device must be a cuda device")
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self._angles = None
+        ang_ptr = None
+        if angles is not None:
+            self._angles = np.ascontiguousarray(angles, dtype=np.float64)
+            if self._angles.shape != (self.n_angles,):
+                raise ValueError("angles must have n_angles entries")
+            ang_ptr = self._angles.ctypes.data_as(C.POINTER(C.c_double))
+        desc = nat.GeometryDesc(self.nx, self.ny, self.nz, self.n_angles, ang_ptr, self.n_bins,
+                                self.bin_width, self.det_offset, self.n_subsets, _DTYPES[dtype])
+        h = C.c_void_p()
+        nat.check(self.lib.make_geometry(C.byref(desc), C.byref(h)), "make_geometry")
+        self.handle = h
+        nbytes = self.lib.geometry_device_bytes(h)
+        with torch.cuda.device(self.device):
+            self._tables = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=self.device)
+            nat.check(self.lib.geometry_upload(h, _ptr(self._tables), nbytes, _stream(self.device)),
+                      "geometry_upload")
+        self._ws = {}
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                self.lib.free_geometry(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    # -- shapes -----------------------------------------------------------------------------
+    @property
+    def n(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    @property
+    def tv_dims(self) -> int:
+        return 3 if self.nz > 1 else 2
+
+    @property
+    def image_shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    def subset_size(self, subset: int) -> int:
+        a = self.lib.subset_size(self.handle, int(subset))
+        if a < 0:
+            raise ValueError(f"subset {subset} out of range")
+        return a
+
+    def sino_shape(self, subset: int = -1):
+        return (self.nz, self.subset_size(subset), self.n_bins)
+
+    def dual_shape(self):
+        return (self.tv_dims, self.nz, self.ny, self.nx)
+
+    # -- buffers ----------------------------------------------------------------------------
+    def check(self, t: torch.Tensor, shape, what: str) -> torch.Tensor:
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{what} must be a torch.Tensor")
+        if t.device != self.device:
+            raise ValueError(f"{what} is on {t.device}, geometry is on {self.device}")
+        if t.dtype != self.dtype:
+            raise TypeError(f"{what} has dtype {t.dtype}, geometry uses {self.dtype}")
+        if tuple(t.shape) != tuple(shape):
+            t = t.reshape(shape) if t.numel() == math.prod(shape) else None
+            if t is None:
+                raise ValueError(f"{what} must have shape {tuple(shape)}")
+        if not t.is_contiguous():
+            raise ValueError(f"{what} must be contiguous")
+        return t
+
+    def workspace(self, key, nbytes: int) -> torch.Tensor | None:
+        if nbytes == 0:
+            return None
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < nbytes:
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self._ws[key] = ws
+        return ws
+
+    def empty_image(self):
+        return torch.empty(self.image_shape, dtype=self.dtype, device=self.device)
+
+    def zeros_image(self):
+        return torch.zeros(self.image_shape, dtype=self.dtype, device=self.device)
+
+
+def project(g: Geometry, x: torch.Tensor, subset: int = -1, out: torch.Tensor | None = None):
+    """y = A_i x (subset = -1: all angles)."""
+    x = g.check(x, g.image_shape, "x")
+    shape = g.sino_shape(subset)
+    y = torch.empty(shape, dtype=g.dtype, device=g.device) if out is None else g.check(out, shape, "out")
+    nbytes = g.lib.project_workspace_bytes(g.handle, int(subset))
+    ws = g.workspace(("proj", shape[1]), nbytes)
+    nat.check(g.lib.project_subset(g.handle, int(subset), _ptr(x), _ptr(y), _ptr(ws), nbytes,
+                                   _stream(g.device)), "project_subset")
+    return y
+
+
+def backproject(g: Geometry, y: torch.Tensor, subset: int = -1, out: torch.Tensor | None = None,
+                accumulate: bool = False):
+    """x = A_i^T y, or out += A_i^T y with accumulate=True."""
+    y = g.check(y, g.sino_shape(subset), "y")
+    if accumulate and out is None:
+        raise ValueError("accumulate=True needs out")
+    x = g.empty_image() if out is None else g.check(out, g.image_shape, "out")
+    nat.check(g.lib.backproject_subset(g.handle, int(subset), _ptr(y), _ptr(x), int(bool(accumulate)),
+                                       _stream(g.device)), "backproject_subset")
+    return x
+
+
+def tv_prox(g: Geometry, v: torch.Tensor, tau: float, n_inner: int, nonneg: bool = True,
+            dual: torch.Tensor | None = None, out: torch.Tensor | None = None):
+    """z = prox_{tau (TV + I_C)}(v) by FGP; ``dual`` (in/out) is the warm start."""
+    v = g.check(v, g.image_shape, "v")
+    z = g.empty_image() if out is None else g.check(out, g.image_shape, "out")
+    if dual is not None:
+        dual = g.check(dual, g.dual_shape(), "dual")
+    nbytes = g.lib.tv_prox_workspace_bytes(g.handle)
+    ws = g.workspace("fgp", nbytes)
+    nat.check(g.lib.tv_prox_fgp(g.handle, _ptr(v), _ptr(z), float(tau), int(n_inner), int(bool(nonneg)),
+                                _ptr(dual), _ptr(ws), nbytes, _stream(g.device)), "tv_prox_fgp")
+    return z
+
+
+@dataclasses.dataclass
+class SolverParams:
+    """Algorithm 1 parameters (gamma, p), TV weight, FGP inner iterations, stopping rule."""
+    gamma: float
+    p: float
+    alpha: float
+    fgp_inner: int
+    n_epochs: int
+    nonneg: bool = True
+    plain_prox_svrg: bool = False
+    seed: int = 0
+    k0: int = 0
+    tol_rel_change: float = 0.0
+
+    def c(self) -> nat.SolverParams:
+        return nat.SolverParams(float(self.gamma), float(self.p), float(self.alpha),
+                                int(self.fgp_inner), int(bool(self.nonneg)), int(self.n_epochs),
+                                int(bool(self.plain_prox_svrg)), int(self.seed), int(self.k0),
+                                float(self.tol_rel_change))
+
+
+def _stats(s: nat.SolverStats) -> dict:
+    return dict(epochs_done=s.epochs_done, iters_done=s.iters_done, prox_calls=s.prox_calls,
+                last_rel_change=s.last_rel_change)
+
+
+def solve(g: Geometry, b: torch.Tensor, params: SolverParams, x=None, h=None, dual=None):
+    """Run ProxSkip-SVRG; x, h, dual (in/out, zeros if omitted) are updated in place.
+
+    Returns (x, h, dual, stats)."""
+    b = g.check(b, (g.nz, g.n_angles, g.n_bins), "b")
+    x = g.zeros_image() if x is None else g.check(x, g.image_shape, "x")
+    h = g.zeros_image() if h is None else g.check(h, g.image_shape, "h")
+    dual = (torch.zeros(g.dual_shape(), dtype=g.dtype, device=g.device) if dual is None
+            else g.check(dual, g.dual_shape(), "dual"))
+    prm = params.c()
+    nbytes = g.lib.proxskip_workspace_bytes(g.handle, C.byref(prm))
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=g.device)
+    st = nat.SolverStats()
+    nat.check(g.lib.proxskip_svrg_run(g.handle, _ptr(b), _ptr(x), _ptr(h), _ptr(dual), C.byref(prm),
+                                      C.byref(st), _ptr(ws), nbytes, _stream(g.device)),
+              "proxskip_svrg_run")
+    return x, h, dual, _stats(st)
+
+
+class Solver:
+    """Resumable ProxSkip-SVRG handle: owns its state tensors and workspace."""
+
+    def __init__(self, g: Geometry, b: torch.Tensor, params: SolverParams, x=None, h=None,
+                 dual=None):
+        self.g = g
+        self.b = g.check(b, (g.nz, g.n_angles, g.n_bins), "b")
+        self.x = g.zeros_image() if x is None else g.check(x, g.image_shape, "x")
+        self.h = g.zeros_image() if h is None else g.check(h, g.image_shape, "h")
+        self.dual = (torch.zeros(g.dual_shape(), dtype=g.dtype, device=g.device) if dual is None
+                     else g.check(dual, g.dual_shape(), "dual"))
+        self.params = params
+        self._prm = params.c()
+        nbytes = g.lib.proxskip_workspace_bytes(g.handle, C.byref(self._prm))
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=g.device)
+        h_ = C.c_void_p()
+        nat.check(g.lib.solver_init(g.handle, _ptr(self.b), _ptr(self.x), _ptr(self.h),
+                                    _ptr(self.dual), C.byref(self._prm), _ptr(self.ws), nbytes,
+                                    C.byref(h_)), "solver_init")
+        self.handle = h_
+
+    def epochs(self, n: int, stream=None):
+        run_epochs([self], n, stream)
+
+    def query(self) -> dict:
+        st = nat.SolverStats()
+        nat.check(self.g.lib.solver_query(self.handle, C.byref(st)), "solver_query")
+        return _stats(st)
+
+    def cancel(self):
+        nat.check(self.g.lib.solver_cancel(self.handle), "solver_cancel")
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self.g.lib.solver_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def run_epochs(solvers, n_epochs: int, stream=None):
+    """Queue ``n_epochs`` more epochs of every solver, interleaved epoch by epoch."""
+    if not solvers:
+        return
+    arr = (C.c_void_p * len(solvers))(*[s.handle for s in solvers])
+    dev = solvers[0].g.device
+    st = C.c_void_p(stream.cuda_stream) if stream is not None else _stream(dev)
+    nat.check(solvers[0].g.lib.solver_epochs(arr, len(solvers), int(n_epochs), st), "solver_epochs")
+
+
+def sample_sequences(seed: int, k0: int, count: int, n_subsets: int, p: float):
+    """The library's host-side subset and coin streams (int32, uint8 numpy arrays)."""
+    lib = nat.load()
+    sub = np.zeros(max(count, 1), dtype=np.int32)
+    coin = np.zeros(max(count, 1), dtype=np.uint8)
+    nat.check(lib.sample_sequences(int(seed), int(k0), int(count), int(n_subsets), float(p),
+                                   sub.ctypes.data_as(C.c_void_p), coin.ctypes.data_as(C.c_void_p)),
+              "sample_sequences")
+    return sub[:count], coin[:count]
+
+
+def lipschitz(g: Geometry, iters: int = 100, seed: int = 0) -> float:
+    """L = lambda_max(A^T A) by the power method on the GPU (step size gamma = 1/L).
+
+    Starts from the all-ones image (A^T A is entrywise non-negative, so it overlaps the top
+    eigenvector) and returns the last Rayleigh quotient, computed in float64."""
+    v = torch.ones(g.image_shape, dtype=g.dtype, device=g.device)
+    v /= torch.linalg.vector_norm(v.double()).to(g.dtype)
+    lam = 0.0
+    for _ in range(iters):
+        w = backproject(g, project(g, v))
+        lam = float(torch.sum(v.double() * w.double()))
+        nrm = torch.linalg.vector_norm(w.double())
+        if float(nrm) == 0.0:
+            break
+        v = (w.double() / nrm).to(g.dtype)
+    return lam

@@ -1,0 +1,427 @@
+// fgp.hip -- proximal operator of tau (TV + I_C) by FGP (Beck & Teboulle 2009), K4/K5.
+//
+// Dual form: z(p) = P_C(v - tau D^T p); ascend the dual with step 1/(4 d tau) (||D||^2 <= 4d),
+// project each pixel's d-vector onto the unit ball, and extrapolate with the FISTA momentum
+// r_k = p_{k-1} + c_k (p_{k-1} - p_{k-2}),  c_k = (t_{k-1} - 1)/t_k,  t_1 = 1.
+// The momentum is rebuilt from the last two duals wherever it is needed, so an iteration reads
+// v, p_{k-1}, p_{k-2} and writes p_k.
+//
+// 2D (one slice): temporal blocking.  A workgroup loads a 32 x 16 tile plus a halo of H = T + 1
+// pixels into LDS and runs T inner iterations there before writing back; every iteration only
+// reaches one pixel further, so the tile's pixels are computed exactly as one global iteration
+// at a time would.  This cuts HBM traffic and launches by T.
+// 3D (slices coupled): one launch per half-iteration over global memory (HBM-bound volumes).
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "internal.h"
+
+namespace ps {
+
+constexpr int kFgpTX = 32, kFgpTY = 16;
+constexpr int kFgpMaxIters = 8;
+
+template <typename T>
+struct FgpCoef {
+    T c[kFgpMaxIters];
+};
+
+template <typename T>
+struct FgpFinal {
+    int mode;      // 0: intermediate (write pa/pb), 1: z, 2: proxskip (x, h), 3: plain (x)
+    T *z, *x, *h;
+    T hscale;
+    T *dual_out;
+};
+
+template <typename T>
+__device__ inline void project_ball2(T &px, T &py) {
+    const T nrm = sqrt(px * px + py * py);
+    if (nrm > T(1)) {
+        px /= nrm;
+        py /= nrm;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fgp2d(
+    const T *__restrict__ v, const T *__restrict__ pa_in, const T *__restrict__ pb_in,
+    T *__restrict__ pa_out, T *__restrict__ pb_out, int nx, int ny, int iters, int halo,
+    FgpCoef<T> cf, T tau, T step, int nonneg, FgpFinal<T> fin) {
+    extern __shared__ unsigned char smem_raw[];
+    const int EX = kFgpTX + 2 * halo, EY = kFgpTY + 2 * halo, EN = EX * EY;
+    T *vL = reinterpret_cast<T *>(smem_raw);
+    T *ax = vL + EN, *ay = ax + EN, *bx = ay + EN, *by = bx + EN, *zL = by + EN;
+    const size_t n = static_cast<size_t>(nx) * ny;
+    const int i0 = blockIdx.y * kFgpTY - halo, j0 = blockIdx.x * kFgpTX - halo;
+
+    for (int e = threadIdx.x; e < EN; e += kBlock) {
+        const int ey = e / EX, ex = e - ey * EX;
+        const int gi = i0 + ey, gj = j0 + ex;
+        if (gi >= 0 && gi < ny && gj >= 0 && gj < nx) {
+            const size_t p = static_cast<size_t>(gi) * nx + gj;
+            vL[e] = v[p];
+            ax[e] = pa_in[p];
+            ay[e] = pa_in[p + n];
+            bx[e] = pb_in[p];
+            by[e] = pb_in[p + n];
+        } else {
+            vL[e] = ax[e] = ay[e] = bx[e] = by[e] = T(0);
+        }
+    }
+    __syncthreads();
+
+    for (int it = 0; it < iters; ++it) {
+        const T c = cf.c[it];
+        // z_k = P_C(v - tau D^T r_k)
+        for (int e = threadIdx.x; e < EN; e += kBlock) {
+            const int ey = e / EX, ex = e - ey * EX;
+            const int gi = i0 + ey, gj = j0 + ex;
+            T zv = T(0);
+            if (gi >= 0 && gi < ny && gj >= 0 && gj < nx) {
+                const T rx_here = (gj < nx - 1) ? fma(c, ax[e] - bx[e], ax[e]) : T(0);
+                const T rx_left = (gj > 0 && ex > 0) ? fma(c, ax[e - 1] - bx[e - 1], ax[e - 1]) : T(0);
+                const T ry_here = (gi < ny - 1) ? fma(c, ay[e] - by[e], ay[e]) : T(0);
+                const T ry_up = (gi > 0 && ey > 0) ? fma(c, ay[e - EX] - by[e - EX], ay[e - EX]) : T(0);
+                const T dt = (rx_left - rx_here) + (ry_up - ry_here);
+                zv = vL[e] - tau * dt;
+                if (nonneg && zv < T(0)) zv = T(0);
+            }
+            zL[e] = zv;
+        }
+        __syncthreads();
+        // p_k = P_P(r_k + step D z_k); shift p_{k-1} -> p_{k-2}
+        for (int e = threadIdx.x; e < EN; e += kBlock) {
+            const int ey = e / EX, ex = e - ey * EX;
+            const int gi = i0 + ey, gj = j0 + ex;
+            if (gi >= 0 && gi < ny && gj >= 0 && gj < nx) {
+                const T dzx = (gj < nx - 1 && ex < EX - 1) ? zL[e + 1] - zL[e] : T(0);
+                const T dzy = (gi < ny - 1 && ey < EY - 1) ? zL[e + EX] - zL[e] : T(0);
+                const T rx = fma(c, ax[e] - bx[e], ax[e]);
+                const T ry = fma(c, ay[e] - by[e], ay[e]);
+                T px = fma(step, dzx, rx), py = fma(step, dzy, ry);
+                project_ball2(px, py);
+                bx[e] = ax[e];
+                by[e] = ay[e];
+                ax[e] = px;
+                ay[e] = py;
+            }
+        }
+        __syncthreads();
+    }
+
+    // write back the tile's own pixels
+    for (int e = threadIdx.x; e < kFgpTX * kFgpTY; e += kBlock) {
+        const int ty = e / kFgpTX, tx = e - ty * kFgpTX;
+        const int gi = blockIdx.y * kFgpTY + ty, gj = blockIdx.x * kFgpTX + tx;
+        if (gi >= ny || gj >= nx) continue;
+        const int le = (ty + halo) * EX + (tx + halo);
+        const size_t p = static_cast<size_t>(gi) * nx + gj;
+        if (fin.mode == 0) {
+            pa_out[p] = ax[le];
+            pa_out[p + n] = ay[le];
+            pb_out[p] = bx[le];
+            pb_out[p + n] = by[le];
+        } else {
+            // z = P_C(v - tau D^T p_K)
+            const T px_here = (gj < nx - 1) ? ax[le] : T(0);
+            const T px_left = (gj > 0) ? ax[le - 1] : T(0);
+            const T py_here = (gi < ny - 1) ? ay[le] : T(0);
+            const T py_up = (gi > 0) ? ay[le - EX] : T(0);
+            const T dt = (px_left - px_here) + (py_up - py_here);
+            T zv = vL[le] - tau * dt;
+            if (nonneg && zv < T(0)) zv = T(0);
+            if (fin.mode == 1) {
+                fin.z[p] = zv;
+            } else {
+                fin.x[p] = zv;
+                if (fin.mode == 2) fin.h[p] = fin.hscale * (zv - vL[le]);
+            }
+            fin.dual_out[p] = ax[le];
+            fin.dual_out[p + n] = ay[le];
+        }
+    }
+}
+
+// ---- 3D: global-memory half-iterations ------------------------------------------------------
+
+template <typename T>
+__device__ inline T mom(const T *pa, const T *pb, size_t q, T c) {
+    return fma(c, pa[q] - pb[q], pa[q]);
+}
+
+// zbuf = P_C(v - tau D^T r), r = pa + c (pa - pb); with c = 0 and pa = p this is z(p).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fgp3d_primal(
+    const T *__restrict__ v, const T *__restrict__ pa, const T *__restrict__ pb, T c, int nx,
+    int ny, int nz, T tau, int nonneg, T *__restrict__ zbuf, FgpFinal<T> fin) {
+    const size_t plane = static_cast<size_t>(nx) * ny, n = plane * nz;
+    for (size_t e = blockIdx.x * static_cast<size_t>(kBlock) + threadIdx.x; e < n;
+         e += static_cast<size_t>(gridDim.x) * kBlock) {
+        const int j = static_cast<int>(e % nx);
+        const int i = static_cast<int>((e / nx) % ny);
+        const int zz = static_cast<int>(e / plane);
+        const T *pax = pa, *pay = pa + n, *paz = pa + 2 * n;
+        const T *pbx = pb, *pby = pb + n, *pbz = pb + 2 * n;
+        const T tx = ((j > 0) ? mom(pax, pbx, e - 1, c) : T(0)) - ((j < nx - 1) ? mom(pax, pbx, e, c) : T(0));
+        const T ty = ((i > 0) ? mom(pay, pby, e - nx, c) : T(0)) - ((i < ny - 1) ? mom(pay, pby, e, c) : T(0));
+        const T tz = ((zz > 0) ? mom(paz, pbz, e - plane, c) : T(0)) - ((zz < nz - 1) ? mom(paz, pbz, e, c) : T(0));
+        T zv = v[e] - tau * ((tx + ty) + tz);
+        if (nonneg && zv < T(0)) zv = T(0);
+        if (fin.mode == 0) {
+            zbuf[e] = zv;
+        } else {
+            if (fin.mode == 1) {
+                fin.z[e] = zv;
+            } else {
+                fin.x[e] = zv;
+                if (fin.mode == 2) fin.h[e] = fin.hscale * (zv - v[e]);
+            }
+            if (fin.dual_out) {
+                fin.dual_out[e] = pa[e];
+                fin.dual_out[e + n] = pa[e + n];
+                fin.dual_out[e + 2 * n] = pa[e + 2 * n];
+            }
+        }
+    }
+}
+
+// pn = P_P(r + step D z), r = pa + c (pa - pb).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fgp3d_dual(
+    const T *__restrict__ zbuf, const T *__restrict__ pa, const T *__restrict__ pb, T c, int nx,
+    int ny, int nz, T step, T *__restrict__ pn) {
+    const size_t plane = static_cast<size_t>(nx) * ny, n = plane * nz;
+    for (size_t e = blockIdx.x * static_cast<size_t>(kBlock) + threadIdx.x; e < n;
+         e += static_cast<size_t>(gridDim.x) * kBlock) {
+        const int j = static_cast<int>(e % nx);
+        const int i = static_cast<int>((e / nx) % ny);
+        const int zz = static_cast<int>(e / plane);
+        const T z0 = zbuf[e];
+        const T dx = (j < nx - 1) ? zbuf[e + 1] - z0 : T(0);
+        const T dy = (i < ny - 1) ? zbuf[e + nx] - z0 : T(0);
+        const T dz = (zz < nz - 1) ? zbuf[e + plane] - z0 : T(0);
+        T px = fma(step, dx, mom(pa, pb, e, c));
+        T py = fma(step, dy, mom(pa + n, pb + n, e, c));
+        T pz = fma(step, dz, mom(pa + 2 * n, pb + 2 * n, e, c));
+        const T nrm = sqrt(px * px + py * py + pz * pz);
+        if (nrm > T(1)) {
+            px /= nrm;
+            py /= nrm;
+            pz /= nrm;
+        }
+        pn[e] = px;
+        pn[e + n] = py;
+        pn[e + 2 * n] = pz;
+    }
+}
+
+// tau = 0: z = P_C(v) (and the ProxSkip outputs).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prox_identity(const T *__restrict__ v, size_t n, int nonneg,
+                                                          FgpFinal<T> fin) {
+    for (size_t e = blockIdx.x * static_cast<size_t>(kBlock) + threadIdx.x; e < n;
+         e += static_cast<size_t>(gridDim.x) * kBlock) {
+        const T vv = v[e];
+        const T zv = (nonneg && vv < T(0)) ? T(0) : vv;
+        if (fin.mode == 1) {
+            fin.z[e] = zv;
+        } else {
+            fin.x[e] = zv;
+            if (fin.mode == 2) fin.h[e] = fin.hscale * (zv - vv);
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fill(T *__restrict__ p, size_t n, T val) {
+    for (size_t e = blockIdx.x * static_cast<size_t>(kBlock) + threadIdx.x; e < n;
+         e += static_cast<size_t>(gridDim.x) * kBlock)
+        p[e] = val;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_copy(T *__restrict__ dst, const T *__restrict__ src, size_t n) {
+    for (size_t e = blockIdx.x * static_cast<size_t>(kBlock) + threadIdx.x; e < n;
+         e += static_cast<size_t>(gridDim.x) * kBlock)
+        dst[e] = src[e];
+}
+
+static unsigned grid_for(size_t n) {
+    return static_cast<unsigned>(std::max<size_t>(1, std::min<size_t>((n + kBlock - 1) / kBlock, 8192)));
+}
+
+// FISTA momentum coefficients c_k (k = 1..K): c_1 = c_2 = 0, c_k = (t_{k-1} - 1)/t_k.
+static std::vector<double> momentum(int K) {
+    std::vector<double> c(K + 1, 0.0), t(K + 1, 1.0);
+    for (int k = 2; k <= K; ++k) {
+        t[k] = (1.0 + std::sqrt(1.0 + 4.0 * t[k - 1] * t[k - 1])) / 2.0;
+        c[k] = (t[k - 1] - 1.0) / t[k];
+    }
+    return c;
+}
+
+size_t fgp_workspace(const ps_geometry *g) {
+    const size_t n = static_cast<size_t>(g->desc.nx) * g->desc.ny * g->desc.nz;
+    const size_t dn = static_cast<size_t>(g->tv_dims) * n;
+    return align_up(dn * g->elem) * 4 + align_up(n * g->elem) * 2;
+}
+
+template <typename T>
+static ps_status fgp_t(const ps_geometry *g, const T *v, T *dual, double tau_d, int K, int nonneg,
+                       const FgpOut &o, void *ws, size_t ws_bytes, hipStream_t st) {
+    const auto &d = g->desc;
+    const size_t n = static_cast<size_t>(d.nx) * d.ny * d.nz;
+    const int dims = g->tv_dims;
+    const size_t dn = static_cast<size_t>(dims) * n;
+    FgpFinal<T> fin{};
+    fin.mode = o.proxskip == 0 ? 1 : (o.proxskip == 1 ? 2 : 3);
+    fin.z = static_cast<T *>(o.z);
+    fin.x = static_cast<T *>(o.x);
+    fin.h = static_cast<T *>(o.h);
+    fin.hscale = static_cast<T>(o.hscale);
+
+    if (tau_d == 0.0) {
+        hipLaunchKernelGGL((k_prox_identity<T>), dim3(grid_for(n)), dim3(kBlock), 0, st, v, n, nonneg, fin);
+        PS_LAUNCHED("k_prox_identity");
+        return PS_OK;
+    }
+    const size_t need = fgp_workspace(g);
+    if (!ws || ws_bytes < need)
+        return fail(PS_EINVAL, "TV prox workspace: %zu bytes given, %zu needed", ws_bytes, need);
+    unsigned char *w = static_cast<unsigned char *>(ws);
+    const size_t sd = align_up(dn * g->elem), sn = align_up(n * g->elem);
+    T *buf[4] = {reinterpret_cast<T *>(w), reinterpret_cast<T *>(w + sd),
+                 reinterpret_cast<T *>(w + 2 * sd), reinterpret_cast<T *>(w + 3 * sd)};
+    T *vcopy = reinterpret_cast<T *>(w + 4 * sd);
+    T *zscratch = reinterpret_cast<T *>(w + 4 * sd + sn);
+
+    // z may alias v: the halo reads of v must not see finished pixels of another workgroup
+    const T *vin = v;
+    if (fin.mode == 1 && static_cast<const void *>(fin.z) == static_cast<const void *>(v)) {
+        hipLaunchKernelGGL((k_copy<T>), dim3(grid_for(n)), dim3(kBlock), 0, st, vcopy, v, n);
+        PS_LAUNCHED("k_copy");
+        vin = vcopy;
+    }
+    // cold start: zero dual in the workspace, final dual discarded
+    const T *dual_in = dual;
+    if (!dual) {
+        hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(dn)), dim3(kBlock), 0, st, buf[3], dn, T(0));
+        PS_LAUNCHED("k_fill");
+        dual_in = buf[3];
+    }
+    const std::vector<double> cs = momentum(std::max(K, 1));
+    const T tauT = static_cast<T>(tau_d);
+    const T stepT = static_cast<T>(1.0 / (4.0 * dims * tau_d));
+
+    if (dims == 2) {
+        const int tmax = g->elem == sizeof(double) ? 4 : kFgpMaxIters;
+        const int launches = std::max(1, (K + tmax - 1) / tmax);
+        const dim3 grid((d.nx + kFgpTX - 1) / kFgpTX, (d.ny + kFgpTY - 1) / kFgpTY);
+        int done = 0;
+        const T *in_a = dual_in, *in_b = dual_in;
+        for (int L = 0; L < launches; ++L) {
+            const int iters = std::min(tmax, K - done);
+            const int halo = iters + 1;
+            const size_t lds = static_cast<size_t>(6) * (kFgpTX + 2 * halo) * (kFgpTY + 2 * halo) * g->elem;
+            FgpCoef<T> cf{};
+            for (int t = 0; t < iters; ++t) cf.c[t] = static_cast<T>(cs[done + t + 1]);
+            const bool last = (L == launches - 1);
+            FgpFinal<T> f = fin;
+            T *out_a = buf[2 * (L % 2)], *out_b = buf[2 * (L % 2) + 1];
+            bool copy_back = false;
+            if (last) {
+                // the final dual must not land in a buffer this launch still reads as halo
+                if (!dual) {
+                    f.dual_out = out_a;  // cold start: dual discarded
+                } else if (L == 0) {
+                    f.dual_out = out_a;  // single launch reading the caller's dual: copy after
+                    copy_back = true;
+                } else {
+                    f.dual_out = dual;
+                }
+            } else {
+                f.mode = 0;
+            }
+            hipLaunchKernelGGL((k_fgp2d<T>), grid, dim3(kBlock), lds, st, vin, in_a, in_b, out_a,
+                               out_b, d.nx, d.ny, iters, halo, cf, tauT, stepT, nonneg, f);
+            PS_LAUNCHED("k_fgp2d");
+            if (copy_back) {
+                hipLaunchKernelGGL((k_copy<T>), dim3(grid_for(dn)), dim3(kBlock), 0, st, dual, out_a, dn);
+                PS_LAUNCHED("k_copy");
+            }
+            in_a = out_a;
+            in_b = out_b;
+            done += iters;
+        }
+        return PS_OK;
+    }
+
+    // 3D: rotate three dual buffers p_{k-2}, p_{k-1}, p_k; buf[3] may hold the zero cold start.
+    const unsigned gr = grid_for(n);
+    FgpFinal<T> mid{};
+    mid.mode = 0;
+    const T *pb = dual_in, *pa = dual_in;
+    T *rot[3] = {buf[0], buf[1], buf[2]};
+    int next = 0;
+    for (int k = 1; k <= K; ++k) {
+        const T c = static_cast<T>(cs[k]);
+        hipLaunchKernelGGL((k_fgp3d_primal<T>), dim3(gr), dim3(kBlock), 0, st, vin, pa, pb, c, d.nx,
+                           d.ny, d.nz, tauT, nonneg, zscratch, mid);
+        PS_LAUNCHED("k_fgp3d_primal");
+        T *pn = rot[next];
+        if (pn == pa || pn == pb) pn = rot[(next + 1) % 3];
+        if (pn == pa || pn == pb) pn = rot[(next + 2) % 3];
+        hipLaunchKernelGGL((k_fgp3d_dual<T>), dim3(gr), dim3(kBlock), 0, st, zscratch, pa, pb, c,
+                           d.nx, d.ny, d.nz, stepT, pn);
+        PS_LAUNCHED("k_fgp3d_dual");
+        pb = pa;
+        pa = pn;
+        next = (next + 1) % 3;
+    }
+    // z = P_C(v - tau D^T p_K); the final dual p_K sits in `pa`
+    FgpFinal<T> f = fin;
+    f.dual_out = nullptr;
+    hipLaunchKernelGGL((k_fgp3d_primal<T>), dim3(gr), dim3(kBlock), 0, st, vin, pa, pa, T(0), d.nx,
+                       d.ny, d.nz, tauT, nonneg, zscratch, f);
+    PS_LAUNCHED("k_fgp3d_primal(final)");
+    if (dual && K > 0) {
+        hipLaunchKernelGGL((k_copy<T>), dim3(grid_for(dn)), dim3(kBlock), 0, st, dual, pa, dn);
+        PS_LAUNCHED("k_copy");
+    }
+    return PS_OK;
+}
+
+ps_status launch_fgp(const ps_geometry *g, const void *v, void *dual, double tau, int n_inner,
+                     int nonneg, const FgpOut &out, void *ws, size_t ws_bytes, hipStream_t st) {
+    if (g->desc.dtype == PS_F64)
+        return fgp_t<double>(g, static_cast<const double *>(v), static_cast<double *>(dual), tau,
+                             n_inner, nonneg, out, ws, ws_bytes, st);
+    return fgp_t<float>(g, static_cast<const float *>(v), static_cast<float *>(dual), tau, n_inner,
+                        nonneg, out, ws, ws_bytes, st);
+}
+
+}  // namespace ps
+
+using namespace ps;
+
+extern "C" size_t tv_prox_workspace_bytes(const ps_geometry *g) { return g ? fgp_workspace(g) : 0; }
+
+extern "C" ps_status tv_prox_fgp(const ps_geometry *g, const void *v, void *z, double tau,
+                                 int32_t n_inner, int32_t nonneg, void *dual, void *workspace,
+                                 size_t ws_bytes, void *stream) {
+    clear_error();
+    if (!g) return fail(PS_EINVAL, "geometry is null");
+    PS_TRY(check_ptr(v, "v", g->elem));
+    PS_TRY(check_ptr(z, "z", g->elem));
+    if (dual) PS_TRY(check_ptr(dual, "dual", g->elem));
+    if (!(tau >= 0.0) || !std::isfinite(tau)) return fail(PS_EINVAL, "tau must be finite and >= 0");
+    if (n_inner < 0) return fail(PS_EINVAL, "n_inner must be >= 0");
+    if (nonneg != 0 && nonneg != 1) return fail(PS_EINVAL, "nonneg must be 0 or 1");
+    FgpOut o{};
+    o.z = z;
+    o.proxskip = 0;
+    return launch_fgp(g, v, dual, tau, n_inner, nonneg, o, workspace, ws_bytes,
+                      static_cast<hipStream_t>(stream));
+}

@@ -1,0 +1,175 @@
+// internal.h -- shared declarations of the HIP library's translation units (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "proxskip.h"
+
+namespace ps {
+
+// ---------------------------------------------------------------------------------------------
+// Errors: every exported call returns a ps_status and records a message per thread.
+// ---------------------------------------------------------------------------------------------
+ps_status fail(ps_status s, const char *fmt, ...);
+void clear_error();
+
+#define PS_HIP(call)                                                                            \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return ::ps::fail(PS_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));          \
+    } while (0)
+
+#define PS_LAUNCHED(name)                                                                       \
+    do {                                                                                        \
+        hipError_t e_ = hipGetLastError();                                                      \
+        if (e_ != hipSuccess)                                                                   \
+            return ::ps::fail(PS_EHIP, "launch of %s failed: %s", name, hipGetErrorString(e_)); \
+    } while (0)
+
+#define PS_TRY(expr)                                                                            \
+    do {                                                                                        \
+        ps_status s_ = (expr);                                                                  \
+        if (s_ != PS_OK) return s_;                                                             \
+    } while (0)
+
+constexpr int kBlock = 256;        // threads per block of every 1D-shaped kernel
+constexpr int kMaxDim = 4096;      // largest nx, ny supported by the LDS plans
+constexpr int kMaxBins = 2048;     // largest B (8 rays per thread x 256 threads)
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
+
+// Per-angle constants of the Joseph walk, in the arithmetic type T.
+//   row-walked angle (|cos| >= |sin|): fractional column at (bin u, row i) is
+//       q = a0 + u a1 + i a2,  a1 = du/c, a2 = -s/c,
+//       a0 = (off - (B-1)/2 du + (ny-1)/2 s)/c + (nx-1)/2,     inv = 1/|c|
+//   column-walked angle: fractional row at (bin u, column j) is
+//       q = a0 + u a1 + j a2,  a1 = du/s, a2 = -c/s,
+//       a0 = (off - (B-1)/2 du + (nx-1)/2 c)/s + (ny-1)/2,     inv = 1/|s|
+//   ia1 = 1/a1 (bins per unit of q), row = 1 for row-walked angles.
+//   q0, q1, q2: a0, a1, a2 in signed 32.32 fixed point (round(a * 2^32)).  The FP32 kernels
+//   evaluate q = q0 + u q1 + t q2 exactly in 64-bit integers: floor(q) is the high word and the
+//   interpolation weight the low word, so positions keep 2^-32 resolution at any image size
+//   (an FP32 q near 1000 would only resolve 6e-5).
+template <typename T>
+struct AngleTab {
+    const T *a0, *a1, *a2, *inv, *ia1;
+    const int32_t *row;
+    const int64_t *q0, *q1, *q2;
+};
+
+// Launch plan of the forward projector for one subset size.
+struct ProjPlan {
+    int split;      // S: blocks along the ray (partial sums reduced in a second pass when > 1)
+    int strip;      // steps of the image staged in LDS at a time
+    int stride;     // LDS row stride (elements)
+    int rpt;        // rays per thread: 1, 2, 4 or 8
+    size_t lds_bytes;
+};
+
+// Launch plan of the backprojector.
+struct BackPlan {
+    int tx, ty;     // pixel tile
+    int chunk;      // angles staged in LDS at a time
+    int slot;       // bins staged per angle (footprint of a tile, with margins)
+    int ncand;      // candidate bins per pixel and angle
+    size_t lds_bytes;
+};
+
+}  // namespace ps
+
+struct ps_geometry {
+    ps_geometry_desc desc;                // angles pointer re-pointed at `angles`
+    std::vector<double> angles;           // A angles (radians)
+    int tv_dims;                          // 2 or 3
+    size_t elem;                          // sizeof(dtype)
+    // host image of the device tables, in the dtype; offsets into it
+    std::vector<unsigned char> host_tab;
+    size_t off_a0, off_a1, off_a2, off_inv, off_ia1, off_row, off_q0, off_q1, off_q2, tab_bytes;
+    void *dev;                            // uploaded tables (caller-owned), or null
+    double max_half_width;                // max |ia1| over angles (tent half-width in bins)
+    ps::BackPlan bplan;
+};
+
+namespace ps {
+
+int subset_count(const ps_geometry *g, int subset);  // a_i, or -1 if subset is invalid
+int max_subset_count(const ps_geometry *g);
+ps_status check_ready(const ps_geometry *g);
+ps_status check_ptr(const void *p, const char *what, size_t align);
+
+template <typename T>
+AngleTab<T> angle_tab(const ps_geometry *g) {
+    const unsigned char *b = static_cast<const unsigned char *>(g->dev);
+    return AngleTab<T>{reinterpret_cast<const T *>(b + g->off_a0),
+                       reinterpret_cast<const T *>(b + g->off_a1),
+                       reinterpret_cast<const T *>(b + g->off_a2),
+                       reinterpret_cast<const T *>(b + g->off_inv),
+                       reinterpret_cast<const T *>(b + g->off_ia1),
+                       reinterpret_cast<const int32_t *>(b + g->off_row),
+                       reinterpret_cast<const int64_t *>(b + g->off_q0),
+                       reinterpret_cast<const int64_t *>(b + g->off_q1),
+                       reinterpret_cast<const int64_t *>(b + g->off_q2)};
+}
+
+// ---------------------------------------------------------------------------------------------
+// Projector (project.hip).
+// ---------------------------------------------------------------------------------------------
+ProjPlan proj_plan(const ps_geometry *g, int na);
+size_t proj_workspace(const ps_geometry *g, int na);
+// y = A_sub (x - xs) [ - b_sub ]: xs and b may be null.  y is [nz][na][B].
+ps_status launch_project(const ps_geometry *g, int subset, const void *x, const void *xs,
+                         const void *b, void *y, void *ws, size_t ws_bytes, hipStream_t st);
+
+// ---------------------------------------------------------------------------------------------
+// Backprojector with fused epilogues (backproject.hip).
+// ---------------------------------------------------------------------------------------------
+enum BackMode { BP_OVERWRITE = 0, BP_ACCUMULATE = 1, BP_SVRG = 2, BP_SNAPSHOT = 3 };
+
+// SVRG/ProxSkip epilogue operands (BP_SVRG, BP_SNAPSHOT), all [nz][ny][nx]:
+//   d = A^T y at the pixel
+//   BP_SVRG:     G = nsub * d + gs
+//   BP_SNAPSHOT: gs = d (stored), G = d         (iteration at the snapshot: x = xs)
+//   plain:       v = x - gamma G                 -> vout
+//   coin = 1:    v = x - gamma (G - h) - (gamma/p) h  -> vout
+//   coin = 0:    x = x - gamma (G - h)           (in place)
+struct UpdateArgs {
+    void *x;
+    const void *h;
+    void *gs;
+    void *vout;
+    double gamma, gamma_over_p, nsub;
+    int coin, plain;
+};
+ps_status launch_backproject(const ps_geometry *g, int subset, const void *y, void *out, int mode,
+                             const UpdateArgs *upd, hipStream_t st);
+
+// ---------------------------------------------------------------------------------------------
+// TV prox by FGP (fgp.hip).
+// ---------------------------------------------------------------------------------------------
+size_t fgp_workspace(const ps_geometry *g);
+// Finalise modes: write z (FGP_Z) or the ProxSkip update x = z, h = hscale (z - v) (FGP_PROXSKIP).
+struct FgpOut {
+    void *z;        // FGP_Z: output image (may alias v)
+    void *x, *h;    // FGP_PROXSKIP
+    double hscale;  // p / gamma
+    int proxskip;   // 0: z, 1: proxskip update (h written), 2: plain (x = z, h untouched)
+};
+ps_status launch_fgp(const ps_geometry *g, const void *v, void *dual, double tau, int n_inner,
+                     int nonneg, const FgpOut &out, void *ws, size_t ws_bytes, hipStream_t st);
+
+// ---------------------------------------------------------------------------------------------
+// Solver pieces (solver.hip).
+// ---------------------------------------------------------------------------------------------
+uint64_t splitmix64(uint64_t seed, uint64_t j);
+void draw_sequences(uint64_t seed, int64_t k0, int64_t count, int n_subsets, double p,
+                    int32_t *subset_out, uint8_t *coin_out);
+
+}  // namespace ps

@@ -1,0 +1,120 @@
+"""The C-ABI library loads, exports every symbol include/proxskip.h declares, and rejects bad
+arguments on the host before any device work (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_symbols():
+    text = open(os.path.join(ROOT, "include", "proxskip.h")).read()
+    return re.findall(r"^PS_API\s+[\w\s\*]+?\b(\w+)\(", text, flags=re.M)
+
+
+@pytest.fixture(scope="module")
+def nat():
+    from paper_2602_09527_amd import _native
+    _native.load()
+    return _native
+
+
+def test_exports_every_declared_symbol(nat):
+    declared = _header_symbols()
+    assert len(declared) >= 19
+    assert set(declared) == set(nat.EXPORTS)
+    lib = C.CDLL(nat.LIB_PATH)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def _desc(nat, **kw):
+    d = dict(nx=16, ny=16, nz=1, n_angles=12, angles=None, n_bins=20, bin_width=1.0,
+             det_offset=0.0, n_subsets=3, dtype=nat.PS_F32)
+    d.update(kw)
+    return nat.GeometryDesc(**d)
+
+
+@pytest.mark.parametrize("bad", [dict(nx=0), dict(ny=-1), dict(nz=0), dict(n_angles=0),
+                                 dict(n_bins=0), dict(bin_width=0.0), dict(bin_width=float("nan")),
+                                 dict(n_subsets=0), dict(n_subsets=13), dict(dtype=7),
+                                 dict(det_offset=float("inf"))])
+def test_make_geometry_rejects(nat, bad):
+    lib = nat.load()
+    h = C.c_void_p()
+    st = lib.make_geometry(C.byref(_desc(nat, **bad)), C.byref(h))
+    assert st == nat.PS_EINVAL
+    assert lib.last_error_message()
+
+
+def test_make_geometry_unsupported(nat):
+    lib = nat.load()
+    h = C.c_void_p()
+    assert lib.make_geometry(C.byref(_desc(nat, nx=5000)), C.byref(h)) == nat.PS_EUNSUPPORTED
+    assert lib.make_geometry(C.byref(_desc(nat, n_bins=4096)), C.byref(h)) == nat.PS_EUNSUPPORTED
+
+
+def test_geometry_queries_and_not_uploaded(nat):
+    lib = nat.load()
+    h = C.c_void_p()
+    assert lib.make_geometry(C.byref(_desc(nat, n_angles=14, n_subsets=4)), C.byref(h)) == nat.PS_OK
+    try:
+        assert [lib.subset_size(h, i) for i in range(4)] == [4, 4, 3, 3]
+        assert lib.subset_size(h, -1) == 14 and lib.subset_size(h, 4) == -1
+        assert lib.geometry_device_bytes(h) > 0
+        assert lib.tv_prox_workspace_bytes(h) > 0
+        # upload needs a 256-byte aligned device buffer of the right size
+        assert lib.geometry_upload(h, None, 1 << 20, None) == nat.PS_EINVAL
+        assert lib.geometry_upload(h, C.c_void_p(256), 1, None) == nat.PS_EINVAL
+        # nothing is queued before the tables are uploaded
+        assert lib.project_subset(h, 0, C.c_void_p(256), C.c_void_p(256), None, 0, None) == nat.PS_EINVAL
+        assert lib.backproject_subset(h, 0, C.c_void_p(256), C.c_void_p(256), 0, None) == nat.PS_EINVAL
+        assert lib.project_subset(h, 9, C.c_void_p(256), C.c_void_p(256), None, 0, None) == nat.PS_EINVAL
+        # tv prox argument checks
+        assert lib.tv_prox_fgp(h, C.c_void_p(256), C.c_void_p(256), -1.0, 5, 1, None, None, 0, None) == nat.PS_EINVAL
+        assert lib.tv_prox_fgp(h, C.c_void_p(256), C.c_void_p(256), 0.1, -5, 1, None, None, 0, None) == nat.PS_EINVAL
+        assert lib.tv_prox_fgp(h, C.c_void_p(256), C.c_void_p(256), 0.1, 5, 2, None, None, 0, None) == nat.PS_EINVAL
+        assert lib.tv_prox_fgp(h, C.c_void_p(2), C.c_void_p(256), 0.1, 5, 1, None, None, 0, None) == nat.PS_EINVAL
+    finally:
+        lib.free_geometry(h)
+
+
+@pytest.mark.parametrize("bad", [dict(gamma=0.0), dict(gamma=float("inf")), dict(p=0.0), dict(p=1.5),
+                                 dict(alpha=-1.0), dict(fgp_inner=-1), dict(nonneg=2),
+                                 dict(n_epochs=-1), dict(plain_prox_svrg=3), dict(k0=1),
+                                 dict(k0=-3), dict(tol_rel_change=-1.0)])
+def test_solver_params_rejected(nat, bad):
+    lib = nat.load()
+    h = C.c_void_p()
+    assert lib.make_geometry(C.byref(_desc(nat)), C.byref(h)) == nat.PS_OK
+    try:
+        prm = dict(gamma=1e-3, p=0.5, alpha=0.1, fgp_inner=5, nonneg=1, n_epochs=2,
+                   plain_prox_svrg=0, seed=1, k0=0, tol_rel_change=0.0)
+        prm.update(bad)
+        P = nat.SolverParams(**prm)
+        s = C.c_void_p()
+        fake = C.c_void_p(256)
+        st = lib.solver_init(h, fake, fake, fake, fake, C.byref(P), fake, 1 << 30, C.byref(s))
+        assert st == nat.PS_EINVAL
+        assert not s.value
+    finally:
+        lib.free_geometry(h)
+
+
+def test_sequences_match_oracle_bitwise(nat, orc):
+    from paper_2602_09527_amd import api
+    for seed, k0, count, N, p in [(0, 0, 1_000_000, 20, 0.1), (2**63 + 12345, 400, 100_000, 7, 0.02),
+                                  (101, 0, 300, 10, 0.1), (5, 30, 1000, 1, 1.0), (9, 0, 5000, 30, 0.05)]:
+        s1, c1 = api.sample_sequences(seed, k0, count, N, p)
+        s2, c2 = orc.sequences(seed, k0, count, N, p)
+        assert np.array_equal(s1, s2) and np.array_equal(c1, c2)
+
+
+def test_sequences_reject(nat):
+    lib = nat.load()
+    assert lib.sample_sequences(0, 0, 10, 0, 0.5, None, None) == nat.PS_EINVAL
+    assert lib.sample_sequences(0, 0, 10, 4, 0.0, None, None) == nat.PS_EINVAL
+    assert lib.sample_sequences(0, -1, 10, 4, 0.5, None, None) == nat.PS_EINVAL
