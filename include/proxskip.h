@@ -97,10 +97,14 @@ PS_API ps_status project_subset(const ps_geometry *geom, int32_t subset, const v
                          void *workspace, size_t ws_bytes, void *stream);
 
 /* Backprojection x = A_i^T y (accumulate = 0) or x += A_i^T y (accumulate = 1): the exact
- * adjoint of project_subset, computed pixel by pixel (gather) with the same interpolation
- * weights.  y: device [nz][a_i][B]; x: device [nz][ny][nx].  Errors: PS_EINVAL, PS_EHIP. */
+ * adjoint of project_subset -- every ray deposits its value times the projector's own two
+ * interpolation weights along the same walk (results reproducible bit for bit).
+ * y: device [nz][a_i][B]; x: device [nz][ny][nx].  workspace: device scratch of at least
+ * backproject_workspace_bytes(geom, subset) bytes (partial images).
+ * Errors: PS_EINVAL (bad subset, pointers, workspace too small), PS_EHIP. */
+PS_API size_t backproject_workspace_bytes(const ps_geometry *geom, int32_t subset);
 PS_API ps_status backproject_subset(const ps_geometry *geom, int32_t subset, const void *y, void *x,
-                             int32_t accumulate, void *stream);
+                             int32_t accumulate, void *workspace, size_t ws_bytes, void *stream);
 
 /* Proximal operator of g = TV + I_C (Eq. 3 with the regulariser of Eq. 4), with weight tau:
  *     z = argmin_z 1/2 ||z - v||^2 + tau TV(z) + I_C(z),   C = {z >= 0} if nonneg else R^n,

@@ -20,7 +20,8 @@ PS_F32, PS_F64 = 0, 1
 # Every symbol include/proxskip.h declares.
 EXPORTS = (
     "make_geometry", "free_geometry", "geometry_device_bytes", "geometry_upload", "subset_size",
-    "project_workspace_bytes", "project_subset", "backproject_subset", "tv_prox_workspace_bytes",
+    "project_workspace_bytes", "project_subset", "backproject_workspace_bytes",
+    "backproject_subset", "tv_prox_workspace_bytes",
     "tv_prox_fgp", "proxskip_workspace_bytes", "proxskip_svrg_run", "solver_init",
     "solver_epochs", "solver_query", "solver_cancel", "solver_free", "sample_sequences",
     "last_error_message",
@@ -80,7 +81,8 @@ def load():
         "subset_size": (i32, [vp, i32]),
         "project_workspace_bytes": (sz, [vp, i32]),
         "project_subset": (st, [vp, i32, vp, vp, vp, sz, vp]),
-        "backproject_subset": (st, [vp, i32, vp, vp, i32, vp]),
+        "backproject_workspace_bytes": (sz, [vp, i32]),
+        "backproject_subset": (st, [vp, i32, vp, vp, i32, vp, sz, vp]),
         "tv_prox_workspace_bytes": (sz, [vp]),
         "tv_prox_fgp": (st, [vp, vp, vp, d, i32, i32, vp, vp, sz, vp]),
         "proxskip_workspace_bytes": (sz, [vp, C.POINTER(SolverParams)]),

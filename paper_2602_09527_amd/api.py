@@ -148,8 +148,10 @@ def backproject(g: Geometry, y: torch.Tensor, subset: int = -1, out: torch.Tenso
     if accumulate and out is None:
         raise ValueError("accumulate=True needs out")
     x = g.empty_image() if out is None else g.check(out, g.image_shape, "out")
+    nbytes = g.lib.backproject_workspace_bytes(g.handle, int(subset))
+    ws = g.workspace(("bp", int(subset) if subset < 0 else 0), nbytes)
     nat.check(g.lib.backproject_subset(g.handle, int(subset), _ptr(y), _ptr(x), int(bool(accumulate)),
-                                       _stream(g.device)), "backproject_subset")
+                                       _ptr(ws), nbytes, _stream(g.device)), "backproject_subset")
     return x
 
 

@@ -1,18 +1,209 @@
-// backproject.hip -- adjoint x = A_i^T y, voxel-driven gather (K2), with the SVRG / ProxSkip
-// gradient step fused into its epilogue.
+// backproject.hip -- adjoint x = A_i^T y (K2): the projector's ray walk run backwards.
 //
-// A workgroup owns a tx x ty pixel tile of one slice, one thread per pixel.  Angles are taken in
-// chunks: for each angle of a chunk the detector bins that can touch the tile (its footprint,
-// a short run of bins) are staged in LDS, already scaled by the path length 1/|cos| or 1/|sin|.
-// A pixel then reads the few bins whose Joseph walk passes within one pixel of it: along the
-// walk's interpolation axis the pixel's weight in ray u is the tent max(0, 1 - |q_u - j|),
-// where q_u is computed with exactly the expression the projector uses, so both kernels apply
-// the same interpolation weights.  Every pixel is summed by one thread in a fixed angle order.
+// Every ray deposits, at every step, its value y_u / |cos| (or / |sin|) times the two Joseph
+// weights (1 - w, w) on the pixels j0, j0 + 1 it interpolates -- the same fixed-point walk as
+// the projector, so A^T is the projector's transpose weight for weight.
+//
+// Work split.  Row-walked angles deposit along image rows, column-walked angles along columns.
+// A workgroup owns a strip of R image rows (row class) or R image columns (column class) of one
+// slice, and one of G groups of the subset's angles of that class.  Each of its waves keeps a
+// private accumulator strip in LDS and walks whole ray chunks of its angles through the strip:
+// 64 lanes = 64 rays that are P bins apart (one "pass"), so the 2 x 64 deposits of one step never
+// share a pixel and a plain LDS read-add-write needs no atomics.  The workgroup then adds its
+// waves' strips in a fixed order and writes one partial image per (class, group); a combine pass
+// adds the 2G partials in a fixed order and applies the epilogue (overwrite, accumulate, or the
+// fused SVRG / ProxSkip gradient step).  Results are bitwise reproducible.
 #include <algorithm>
 
 #include "internal.h"
 
 namespace ps {
+
+constexpr int kWave = 64;
+
+BackPlan back_plan(const ps_geometry *g, int subset) {
+    const auto &d = g->desc;
+    BackPlan p{};
+    const int ext = std::max(d.nx, d.ny);
+    p.stride = ext + 4;
+    p.waves = 4;
+    p.strip = 8;
+    const size_t budget = 80 * 1024;  // two workgroups per CU (160 KB of LDS)
+    while (p.strip > 1 && static_cast<size_t>(p.waves) * p.strip * p.stride * g->elem > budget)
+        p.strip >>= 1;
+    while (p.waves > 1 && static_cast<size_t>(p.waves) * p.strip * p.stride * g->elem > budget)
+        p.waves >>= 1;
+    p.s_row = (d.ny + p.strip - 1) / p.strip;
+    p.s_col = (d.nx + p.strip - 1) / p.strip;
+    const int na = subset_count(g, subset);
+    const int nrow = subset < 0 ? g->nrow_full : g->nrow_sub[subset];
+    const int most = std::max(nrow, na - nrow);
+    const long per_group = static_cast<long>(p.s_row + p.s_col) * d.nz;
+    long G = (512 + per_group - 1) / per_group;
+    G = std::max(1L, std::min<long>(G, std::min(16, std::max(1, most))));
+    p.groups = static_cast<int>(G);
+    p.lds_bytes = static_cast<size_t>(p.waves) * p.strip * p.stride * g->elem;
+    p.part_elems = static_cast<size_t>(2) * p.groups * d.nx * d.ny * d.nz;
+    return p;
+}
+
+size_t back_workspace(const ps_geometry *g, int subset) {
+    return align_up(back_plan(g, subset).part_elems * g->elem);
+}
+
+template <typename T, int NP, int kStrip>
+__global__ __launch_bounds__(kBlock) void k_backproject(
+    const T *__restrict__ y, AngleTab<T> tab, int subset, int nsub, int na, int nx, int ny,
+    int nbins, int strip, int stride, int s_row, int groups, int passes, const int32_t *order,
+    int nrow, T *__restrict__ part) {
+    extern __shared__ unsigned char smem_raw[];
+    T *acc_all = reinterpret_cast<T *>(smem_raw);
+    constexpr bool kFixed = std::is_same<T, float>::value;
+    const int nw = blockDim.x / kWave;
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int z = blockIdx.z, grp = blockIdx.y;
+    const bool rowc = static_cast<int>(blockIdx.x) < s_row;
+    const int s = rowc ? blockIdx.x : blockIdx.x - s_row;
+    const int nsteps = rowc ? ny : nx;   // stepping axis of this class
+    const int ext = rowc ? nx : ny;      // deposit axis
+    const int t_lo = s * strip;
+    const int nt = min(strip, nsteps - t_lo);
+    const size_t plane = static_cast<size_t>(nx) * ny;
+    const T *yz = y + static_cast<size_t>(z) * na * nbins;
+
+    // this class's angles, and this group's share of them
+    const int cls_lo = rowc ? 0 : nrow, cls_cnt = rowc ? nrow : na - nrow;
+    const int per = (cls_cnt + groups - 1) / groups;
+    const int e_lo = cls_lo + grp * per;
+    const int e_hi = cls_lo + min(cls_cnt, (grp + 1) * per);
+
+    for (int e = threadIdx.x; e < nw * strip * stride; e += blockDim.x) acc_all[e] = T(0);
+    __syncthreads();
+    T *acc = acc_all + static_cast<size_t>(wave) * strip * stride;
+
+    const int span = kWave * passes;               // rays per chunk
+    const int chunks = (nbins + span - 1) / span;
+    const int units = max(0, e_hi - e_lo) * chunks;
+    const uint32_t lim = static_cast<uint32_t>(ext + 2);
+
+    // ray values (y / |cos| or y / |sin|) of one work unit, for up to NP passes
+    auto fetch = [&](int unit, T *yv) {
+        const int e = e_lo + unit / chunks, c = unit % chunks;
+        const int l = order[e];
+        const int k = subset < 0 ? l : subset + l * nsub;
+        const T inv = tab.inv[k];
+        const T *yl = yz + static_cast<size_t>(l) * nbins;
+#pragma unroll
+        for (int pass = 0; pass < (NP > 0 ? NP : 1); ++pass) {
+            const int u = c * span + pass + passes * lane;
+            yv[pass] = u < nbins ? yl[u] * inv : T(0);
+        }
+    };
+    // deposit one pass of one unit: rays u = c * span + pass + passes * lane
+    auto deposit = [&](int unit, int pass, T y0) {
+        const int e = e_lo + unit / chunks, c = unit % chunks;
+        const int l = order[e];
+        const int k = subset < 0 ? l : subset + l * nsub;
+        const int u = c * span + pass + passes * lane;
+        if constexpr (kFixed) {
+            const T y1 = y0 * T(0x1p-32f);
+            const int64_t q2 = tab.q2[k];
+            int64_t q = tab.q0[k] + (static_cast<int64_t>(2) << 32) + static_cast<int64_t>(u) * tab.q1[k] +
+                        static_cast<int64_t>(t_lo) * q2;
+            if (nt == kStrip) {
+                // all reads of the strip's rows first (rows never alias), then the writes
+                T *cell[kStrip];
+                T c0[kStrip], c1[kStrip], m[kStrip];
+#pragma unroll
+                for (int t = 0; t < kStrip; ++t) {
+                    cell[t] = acc + t * stride + min(static_cast<uint32_t>(q >> 32), lim);
+                    m[t] = static_cast<T>(static_cast<uint32_t>(q)) * y1;  // w y
+                    q += q2;
+                }
+#pragma unroll
+                for (int t = 0; t < kStrip; ++t) {
+                    c0[t] = cell[t][0];
+                    c1[t] = cell[t][1];
+                }
+#pragma unroll
+                for (int t = 0; t < kStrip; ++t) {
+                    cell[t][0] = c0[t] + (y0 - m[t]);
+                    cell[t][1] = c1[t] + m[t];
+                }
+            } else {
+                for (int t = 0; t < nt; ++t) {
+                    const uint32_t idx = min(static_cast<uint32_t>(q >> 32), lim);
+                    const T mm = static_cast<T>(static_cast<uint32_t>(q)) * y1;
+                    T *cl = acc + t * stride + idx;
+                    const T a = cl[0], b = cl[1];
+                    cl[0] = a + (y0 - mm);
+                    cl[1] = b + mm;
+                    q += q2;
+                }
+            }
+        } else {
+            const T a0 = tab.a0[k], a1 = tab.a1[k], a2 = tab.a2[k];
+            for (int t = 0; t < nt; ++t) {
+                const T q = fma(static_cast<T>(u), a1, fma(static_cast<T>(t_lo + t), a2, a0));
+                const T fl = floor(q);
+                const uint32_t idx = min(static_cast<uint32_t>(static_cast<int>(fl) + 2), lim);
+                const T m = (q - fl) * y0;
+                T *cell = acc + t * stride + idx;
+                const T c0 = cell[0], c1 = cell[1];
+                cell[0] = c0 + (y0 - m);
+                cell[1] = c1 + m;
+            }
+        }
+    };
+
+    if constexpr (NP > 0) {
+        // software pipeline: the next unit's ray values are in flight while this one deposits
+        T ynext[NP];
+        int unit = wave;
+        if (unit < units) fetch(unit, ynext);
+        while (unit < units) {
+            T ycur[NP];
+#pragma unroll
+            for (int q = 0; q < NP; ++q) ycur[q] = ynext[q];
+            const int nxt = unit + nw;
+            if (nxt < units) fetch(nxt, ynext);
+#pragma unroll
+            for (int pass = 0; pass < NP; ++pass) deposit(unit, pass, ycur[pass]);
+            unit = nxt;
+        }
+    } else {
+        for (int unit = wave; unit < units; unit += nw) {
+            const int e = e_lo + unit / chunks, c = unit % chunks;
+            const int l = order[e];
+            const int k = subset < 0 ? l : subset + l * nsub;
+            const T inv = tab.inv[k];
+            const T *yl = yz + static_cast<size_t>(l) * nbins;
+            for (int pass = 0; pass < passes; ++pass) {
+                const int u = c * span + pass + passes * lane;
+                deposit(unit, pass, u < nbins ? yl[u] * inv : T(0));
+            }
+        }
+    }
+    __syncthreads();
+
+    // sum the waves' strips (fixed order) and write this (class, group) partial image
+    T *pz = part + (static_cast<size_t>(rowc ? 0 : 1) * groups + grp) * (plane * gridDim.z) + z * plane;
+    if (rowc) {
+        for (int e = threadIdx.x; e < nt * ext; e += blockDim.x) {
+            const int t = e / ext, j = e - t * ext;
+            T v = T(0);
+            for (int w = 0; w < nw; ++w) v += acc_all[(static_cast<size_t>(w) * strip + t) * stride + j + 2];
+            pz[static_cast<size_t>(t_lo + t) * nx + j] = v;
+        }
+    } else {
+        for (int e = threadIdx.x; e < nt * ext; e += blockDim.x) {
+            const int i = e / nt, t = e - i * nt;   // nt adjacent columns of one row
+            T v = T(0);
+            for (int w = 0; w < nw; ++w) v += acc_all[(static_cast<size_t>(w) * strip + t) * stride + i + 2];
+            pz[static_cast<size_t>(i) * nx + t_lo + t] = v;
+        }
+    }
+}
 
 template <typename T>
 struct UpdateT {
@@ -24,128 +215,82 @@ struct UpdateT {
     int coin, plain;
 };
 
+// d = sum of the 2G partial images (fixed order), then the epilogue of `mode`.
 template <typename T, int MODE>
-__global__ __launch_bounds__(kBlock) void k_backproject(
-    const T *__restrict__ y, AngleTab<T> tab, int subset, int nsub_angles, int na, int nx, int ny,
-    int nbins, int chunk, int slot, int ncand, T *__restrict__ out, UpdateT<T> upd) {
-    extern __shared__ unsigned char smem_raw[];
-    T *ys = reinterpret_cast<T *>(smem_raw);
-    __shared__ int ulo_s[64];
-
-    const int tx = blockDim.x, ty = blockDim.y;
-    const int tid = threadIdx.y * tx + threadIdx.x;
-    const int j = blockIdx.x * tx + threadIdx.x;
-    const int i = blockIdx.y * ty + threadIdx.y;
-    const int z = blockIdx.z;
-    const int j_lo = blockIdx.x * tx, j_hi = min(j_lo + tx, nx) - 1;
-    const int i_lo = blockIdx.y * ty, i_hi = min(i_lo + ty, ny) - 1;
-    const bool inside = (i < ny) && (j < nx);
-    const T *yz = y + static_cast<size_t>(z) * na * nbins;
-
-    T acc = T(0);
-    for (int c0 = 0; c0 < na; c0 += chunk) {
-        const int nca = min(chunk, na - c0);
-        if (tid < nca) {
-            // footprint of the tile in detector bins for angle c0 + tid
-            const int l = c0 + tid;
-            const int k = subset < 0 ? l : subset + l * nsub_angles;
-            const bool row = tab.row[k] != 0;
-            const T a0 = tab.a0[k], a2 = tab.a2[k], ia1 = tab.ia1[k];
-            const T t_lo = static_cast<T>(row ? j_lo : i_lo), t_hi = static_cast<T>(row ? j_hi : i_hi);
-            const T s_lo = static_cast<T>(row ? i_lo : j_lo), s_hi = static_cast<T>(row ? i_hi : j_hi);
-            const T b_lo = fma(s_lo, a2, a0), b_hi = fma(s_hi, a2, a0);
-            const T u1 = (t_lo - b_lo) * ia1, u2 = (t_hi - b_lo) * ia1;
-            const T u3 = (t_lo - b_hi) * ia1, u4 = (t_hi - b_hi) * ia1;
-            const T umin = min(min(u1, u2), min(u3, u4));
-            ulo_s[tid] = static_cast<int>(floor(umin - fabs(ia1))) - 2;
+__global__ __launch_bounds__(kBlock) void k_backproject_combine(
+    const T *__restrict__ part, int groups, size_t n, T *__restrict__ out, UpdateT<T> upd) {
+    for (size_t p = blockIdx.x * static_cast<size_t>(kBlock) + threadIdx.x; p < n;
+         p += static_cast<size_t>(gridDim.x) * kBlock) {
+        T d = T(0);
+        for (int q0 = 0; q0 < 2 * groups; q0 += 8) {
+            T v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = q0 + q < 2 * groups ? part[(q0 + q) * n + p] : T(0);
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (q0 + q < 2 * groups) d += v[q];
         }
-        __syncthreads();
-        for (int e = tid; e < nca * slot; e += tx * ty) {
-            const int a = e / slot, o = e - a * slot;
-            const int l = c0 + a;
-            const int k = subset < 0 ? l : subset + l * nsub_angles;
-            const int u = ulo_s[a] + o;
-            ys[e] = (u >= 0 && u < nbins) ? yz[static_cast<size_t>(l) * nbins + u] * tab.inv[k] : T(0);
-        }
-        __syncthreads();
-        if (inside) {
-            for (int a = 0; a < nca; ++a) {
-                const int l = c0 + a;
-                const int k = subset < 0 ? l : subset + l * nsub_angles;
-                const bool row = tab.row[k] != 0;
-                const T a0 = tab.a0[k], a1 = tab.a1[k], a2 = tab.a2[k], ia1 = tab.ia1[k];
-                const T along = static_cast<T>(row ? i : j);
-                const T target = static_cast<T>(row ? j : i);
-                const T bi = fma(along, a2, a0);
-                const T ustar = (target - bi) * ia1;
-                const int first = static_cast<int>(floor(ustar - fabs(ia1))) + 1;
-                const T *slot_a = ys + a * slot;
-                const int base = first - ulo_s[a];
-                if constexpr (std::is_same<T, float>::value) {
-                    // D = q(u) - target in 32.32 fixed point, exactly as the projector walks it:
-                    // D in [0, 1): the pixel is the left sample (weight 1 - w); D in [-1, 0): the
-                    // right sample (weight w); w = the projector's truncated low word.
-                    const int64_t q1 = tab.q1[k];
-                    const int64_t bt = tab.q0[k] + static_cast<int64_t>(row ? i : j) * tab.q2[k];
-                    int64_t D = bt + static_cast<int64_t>(first) * q1 -
-                                (static_cast<int64_t>(row ? j : i) << 32);
-                    for (int c = 0; c < ncand; ++c) {
-                        const int hi = static_cast<int>(D >> 32);
-                        const float w = static_cast<float>(static_cast<uint32_t>(D) >> 8) * 0x1p-24f;
-                        const float wt = hi == 0 ? 1.0f - w : (hi == -1 ? w : 0.0f);
-                        const int o = min(max(base + c, 0), slot - 1);
-                        acc = fma(wt, slot_a[o], acc);
-                        D += q1;
-                    }
-                } else {
-                    for (int c = 0; c < ncand; ++c) {
-                        const int u = first + c;
-                        const T q = fma(static_cast<T>(u), a1, bi);
-                        const T wt = max(T(0), T(1) - fabs(q - target));
-                        const int o = min(max(base + c, 0), slot - 1);
-                        acc = fma(wt, slot_a[o], acc);
-                    }
-                }
+        if (MODE == BP_OVERWRITE) {
+            out[p] = d;
+        } else if (MODE == BP_ACCUMULATE) {
+            out[p] += d;
+        } else {
+            T G;
+            if (MODE == BP_SNAPSHOT) {
+                upd.gs[p] = d;
+                G = d;
+            } else {
+                G = fma(upd.nsub, d, upd.gs[p]);
             }
-        }
-        __syncthreads();
-    }
-
-    if (!inside) return;
-    const size_t p = (static_cast<size_t>(z) * ny + i) * nx + j;
-    if (MODE == BP_OVERWRITE) {
-        out[p] = acc;
-    } else if (MODE == BP_ACCUMULATE) {
-        out[p] += acc;
-    } else {
-        T G;
-        if (MODE == BP_SNAPSHOT) {
-            upd.gs[p] = acc;
-            G = acc;
-        } else {
-            G = fma(upd.nsub, acc, upd.gs[p]);
-        }
-        const T xv = upd.x[p];
-        if (upd.plain) {
-            upd.vout[p] = xv - upd.gamma * G;
-        } else {
-            const T hv = upd.h[p];
-            const T xh = xv - upd.gamma * (G - hv);
-            if (upd.coin)
-                upd.vout[p] = xh - upd.gamma_over_p * hv;
-            else
-                upd.x[p] = xh;
+            const T xv = upd.x[p];
+            if (upd.plain) {
+                upd.vout[p] = xv - upd.gamma * G;
+            } else {
+                const T hv = upd.h[p];
+                const T xh = xv - upd.gamma * (G - hv);
+                if (upd.coin)
+                    upd.vout[p] = xh - upd.gamma_over_p * hv;
+                else
+                    upd.x[p] = xh;
+            }
         }
     }
 }
 
 template <typename T>
 static ps_status backproject_t(const ps_geometry *g, int subset, const T *y, T *out, int mode,
-                               const UpdateArgs *u, hipStream_t st) {
+                               const UpdateArgs *u, void *ws, size_t ws_bytes, hipStream_t st) {
     const auto &d = g->desc;
     const int na = subset_count(g, subset);
-    const BackPlan &bp = g->bplan;
+    const BackPlan bp = back_plan(g, subset);
+    const size_t need = back_workspace(g, subset);
+    if (!ws || ws_bytes < need)
+        return fail(PS_EINVAL, "backprojector workspace: %zu bytes given, %zu needed", ws_bytes, need);
+    T *part = static_cast<T *>(ws);
     const AngleTab<T> tab = angle_tab<T>(g);
+    const int32_t *order = subset < 0 ? tab.ord_full : tab.ord_sub + g->sub_off[subset];
+    const int nrow = subset < 0 ? g->nrow_full : g->nrow_sub[subset];
+    const dim3 grid(bp.s_row + bp.s_col, bp.groups, d.nz);
+#define PS_BPK_ARGS                                                                              \
+    grid, dim3(kWave * bp.waves), bp.lds_bytes, st, y, tab, subset, d.n_subsets, na, d.nx, d.ny,  \
+        d.n_bins, bp.strip, bp.stride, bp.s_row, bp.groups, g->bp_passes, order, nrow, part
+#define PS_BPK_S(NP)                                                                             \
+    switch (bp.strip) {                                                                          \
+        case 8: hipLaunchKernelGGL((k_backproject<T, NP, 8>), PS_BPK_ARGS); break;               \
+        case 4: hipLaunchKernelGGL((k_backproject<T, NP, 4>), PS_BPK_ARGS); break;               \
+        default: hipLaunchKernelGGL((k_backproject<T, NP, 1>), PS_BPK_ARGS); break;              \
+    }
+    switch (g->bp_passes) {
+        case 1: PS_BPK_S(1) break;
+        case 2: PS_BPK_S(2) break;
+        case 3: PS_BPK_S(3) break;
+        case 4: PS_BPK_S(4) break;
+        default: PS_BPK_S(0) break;
+    }
+#undef PS_BPK_S
+#undef PS_BPK_ARGS
+    PS_LAUNCHED("k_backproject");
+
     UpdateT<T> ut{};
     if (u) {
         ut.x = static_cast<T *>(u->x);
@@ -158,15 +303,13 @@ static ps_status backproject_t(const ps_geometry *g, int subset, const T *y, T *
         ut.coin = u->coin;
         ut.plain = u->plain;
     }
-    const dim3 block(bp.tx, bp.ty);
-    const dim3 grid((d.nx + bp.tx - 1) / bp.tx, (d.ny + bp.ty - 1) / bp.ty, d.nz);
-    const int chunk = std::min(bp.chunk, 64);
+    const size_t n = static_cast<size_t>(d.nx) * d.ny * d.nz;
+    const unsigned blocks = static_cast<unsigned>(std::max<size_t>(1, std::min<size_t>((n + kBlock - 1) / kBlock, 8192)));
     switch (mode) {
 #define PS_BP_CASE(M)                                                                           \
     case M:                                                                                     \
-        hipLaunchKernelGGL((k_backproject<T, M>), grid, block, bp.lds_bytes, st, y, tab, subset,  \
-                           d.n_subsets, na, d.nx, d.ny, d.n_bins, chunk, bp.slot, bp.ncand, out, \
-                           ut);                                                                  \
+        hipLaunchKernelGGL((k_backproject_combine<T, M>), dim3(blocks), dim3(kBlock), 0, st, part, \
+                           bp.groups, n, out, ut);                                               \
         break;
         PS_BP_CASE(BP_OVERWRITE)
         PS_BP_CASE(BP_ACCUMULATE)
@@ -176,25 +319,31 @@ static ps_status backproject_t(const ps_geometry *g, int subset, const T *y, T *
         default:
             return fail(PS_EINVAL, "backprojector mode %d", mode);
     }
-    PS_LAUNCHED("k_backproject");
+    PS_LAUNCHED("k_backproject_combine");
     return PS_OK;
 }
 
 ps_status launch_backproject(const ps_geometry *g, int subset, const void *y, void *out, int mode,
-                             const UpdateArgs *upd, hipStream_t st) {
+                             const UpdateArgs *upd, void *ws, size_t ws_bytes, hipStream_t st) {
     if (g->desc.dtype == PS_F64)
         return backproject_t<double>(g, subset, static_cast<const double *>(y),
-                                     static_cast<double *>(out), mode, upd, st);
+                                     static_cast<double *>(out), mode, upd, ws, ws_bytes, st);
     return backproject_t<float>(g, subset, static_cast<const float *>(y), static_cast<float *>(out),
-                                mode, upd, st);
+                                mode, upd, ws, ws_bytes, st);
 }
 
 }  // namespace ps
 
 using namespace ps;
 
+extern "C" size_t backproject_workspace_bytes(const ps_geometry *g, int32_t subset) {
+    if (!g || subset_count(g, subset) < 0) return 0;
+    return back_workspace(g, subset);
+}
+
 extern "C" ps_status backproject_subset(const ps_geometry *g, int32_t subset, const void *y,
-                                        void *x, int32_t accumulate, void *stream) {
+                                        void *x, int32_t accumulate, void *workspace,
+                                        size_t ws_bytes, void *stream) {
     clear_error();
     PS_TRY(check_ready(g));
     if (subset_count(g, subset) < 0) return fail(PS_EINVAL, "subset %d out of range", subset);
@@ -202,5 +351,5 @@ extern "C" ps_status backproject_subset(const ps_geometry *g, int32_t subset, co
     PS_TRY(check_ptr(x, "x", g->elem));
     if (accumulate != 0 && accumulate != 1) return fail(PS_EINVAL, "accumulate must be 0 or 1");
     return launch_backproject(g, subset, y, x, accumulate ? BP_ACCUMULATE : BP_OVERWRITE, nullptr,
-                              static_cast<hipStream_t>(stream));
+                              workspace, ws_bytes, static_cast<hipStream_t>(stream));
 }

@@ -2,14 +2,15 @@
 //
 // Dual form: z(p) = P_C(v - tau D^T p); ascend the dual with step 1/(4 d tau) (||D||^2 <= 4d),
 // project each pixel's d-vector onto the unit ball, and extrapolate with the FISTA momentum
-// r_k = p_{k-1} + c_k (p_{k-1} - p_{k-2}),  c_k = (t_{k-1} - 1)/t_k,  t_1 = 1.
-// The momentum is rebuilt from the last two duals wherever it is needed, so an iteration reads
-// v, p_{k-1}, p_{k-2} and writes p_k.
+// r_k = p_{k-1} + c_k (p_{k-1} - p_{k-2}),  c_k = (t_{k-1} - 1)/t_k,  t_1 = 1,  r_1 = p_0.
 //
-// 2D (one slice): temporal blocking.  A workgroup loads a 32 x 16 tile plus a halo of H = T + 1
-// pixels into LDS and runs T inner iterations there before writing back; every iteration only
-// reaches one pixel further, so the tile's pixels are computed exactly as one global iteration
-// at a time would.  This cuts HBM traffic and launches by T.
+// 2D (one slice): temporal blocking in registers.  A workgroup owns a 64-column x EY-row tile
+// (its interior plus a halo of H = T + 1 pixels) and runs T inner iterations on it before writing
+// back; every iteration reaches one pixel further, so the interior is computed exactly as one
+// global iteration at a time would.  Lane = column; each of the 4 waves keeps a contiguous block
+// of RW = EY/4 rows of (v, p, r, z) in registers, takes horizontal neighbours from lane shuffles
+// and exchanges only its first and last rows through LDS.  Between launches the state is
+// (p_k, r_{k+1}), the dual and its extrapolation.
 // 3D (slices coupled): one launch per half-iteration over global memory (HBM-bound volumes).
 #include <algorithm>
 #include <cmath>
@@ -19,128 +20,152 @@
 
 namespace ps {
 
-constexpr int kFgpTX = 32, kFgpTY = 16;
+constexpr int kFgpEX = 64;          // tile width including halos (= one wave)
+constexpr int kFgpWaves = 4;
 constexpr int kFgpMaxIters = 8;
 
 template <typename T>
 struct FgpCoef {
-    T c[kFgpMaxIters];
+    T c[kFgpMaxIters];              // c_{k+1} for the T iterations of this launch
 };
 
 template <typename T>
 struct FgpFinal {
-    int mode;      // 0: intermediate (write pa/pb), 1: z, 2: proxskip (x, h), 3: plain (x)
+    int mode;      // 0: intermediate (write p, r), 1: z, 2: proxskip (x, h), 3: plain (x)
     T *z, *x, *h;
     T hscale;
     T *dual_out;
 };
 
 template <typename T>
-__device__ inline void project_ball2(T &px, T &py) {
-    const T nrm = sqrt(px * px + py * py);
-    if (nrm > T(1)) {
-        px /= nrm;
-        py /= nrm;
-    }
-}
+constexpr int fgp_rw() { return std::is_same<T, double>::value ? 4 : 8; }
+static int fgp_rows(size_t elem) { return kFgpWaves * (elem == sizeof(double) ? 4 : 8); }
+static int fgp_max_iters(size_t elem) { return elem == sizeof(double) ? 4 : kFgpMaxIters; }
 
-template <typename T>
+template <typename T, int RW>
 __global__ __launch_bounds__(kBlock) void k_fgp2d(
-    const T *__restrict__ v, const T *__restrict__ pa_in, const T *__restrict__ pb_in,
-    T *__restrict__ pa_out, T *__restrict__ pb_out, int nx, int ny, int iters, int halo,
+    const T *__restrict__ v, const T *__restrict__ p_in, const T *__restrict__ r_in,
+    T *__restrict__ p_out, T *__restrict__ r_out, int nx, int ny, int iters, int halo,
     FgpCoef<T> cf, T tau, T step, int nonneg, FgpFinal<T> fin) {
-    extern __shared__ unsigned char smem_raw[];
-    const int EX = kFgpTX + 2 * halo, EY = kFgpTY + 2 * halo, EN = EX * EY;
-    T *vL = reinterpret_cast<T *>(smem_raw);
-    T *ax = vL + EN, *ay = ax + EN, *bx = ay + EN, *by = bx + EN, *zL = by + EN;
+    constexpr int EY = kFgpWaves * RW;
+    __shared__ T xch[2][kFgpWaves][kFgpEX];   // last-row values (down) and first-row values (up)
     const size_t n = static_cast<size_t>(nx) * ny;
-    const int i0 = blockIdx.y * kFgpTY - halo, j0 = blockIdx.x * kFgpTX - halo;
+    const int TX = kFgpEX - 2 * halo, TY = EY - 2 * halo;
+    const int lane = threadIdx.x % kFgpEX, wave = threadIdx.x / kFgpEX;
+    const int i0 = blockIdx.y * TY - halo + wave * RW;   // image row of this wave's row 0
+    const int gj = blockIdx.x * TX - halo + lane;
+    const bool col_in = gj >= 0 && gj < nx;
+    const bool has_left = gj > 0 && lane > 0, has_right = gj < nx - 1 && lane < kFgpEX - 1;
 
-    for (int e = threadIdx.x; e < EN; e += kBlock) {
-        const int ey = e / EX, ex = e - ey * EX;
-        const int gi = i0 + ey, gj = j0 + ex;
-        if (gi >= 0 && gi < ny && gj >= 0 && gj < nx) {
-            const size_t p = static_cast<size_t>(gi) * nx + gj;
-            vL[e] = v[p];
-            ax[e] = pa_in[p];
-            ay[e] = pa_in[p + n];
-            bx[e] = pb_in[p];
-            by[e] = pb_in[p + n];
+    T vv[RW], px[RW], py[RW], rx[RW], ry[RW], zz[RW];
+    bool in[RW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+        const int gi = i0 + r;
+        in[r] = col_in && gi >= 0 && gi < ny;
+        if (in[r]) {
+            const size_t q = static_cast<size_t>(gi) * nx + gj;
+            vv[r] = v[q];
+            px[r] = p_in[q];
+            py[r] = p_in[q + n];
+            rx[r] = r_in[q];
+            ry[r] = r_in[q + n];
         } else {
-            vL[e] = ax[e] = ay[e] = bx[e] = by[e] = T(0);
+            vv[r] = px[r] = py[r] = rx[r] = ry[r] = T(0);
         }
     }
-    __syncthreads();
 
     for (int it = 0; it < iters; ++it) {
+        // z = P_C(v - tau D^T r): needs r^x of the left neighbour and r^y of the row above
+        xch[0][wave][lane] = ry[RW - 1];
+        __syncthreads();
+        const T ry_above = wave > 0 ? xch[0][wave - 1][lane] : T(0);
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            const int gi = i0 + r;
+            const T rxl = __shfl_up(rx[r], 1);
+            const T rx_here = (gj < nx - 1) ? rx[r] : T(0);
+            const T rx_left = has_left ? rxl : T(0);
+            const T ry_here = (gi < ny - 1) ? ry[r] : T(0);
+            const T ry_up = (gi > 0) ? (r > 0 ? ry[r - 1] : ry_above) : T(0);
+            T zv = vv[r] - tau * ((rx_left - rx_here) + (ry_up - ry_here));
+            if (nonneg && zv < T(0)) zv = T(0);
+            zz[r] = in[r] ? zv : T(0);
+        }
+        // p+ = P_P(r + step D z); r+ = p+ + c (p+ - p): needs z of the right neighbour and below
+        xch[1][wave][lane] = zz[0];
+        __syncthreads();
+        const T z_below = wave < kFgpWaves - 1 ? xch[1][wave + 1][lane] : T(0);
         const T c = cf.c[it];
-        // z_k = P_C(v - tau D^T r_k)
-        for (int e = threadIdx.x; e < EN; e += kBlock) {
-            const int ey = e / EX, ex = e - ey * EX;
-            const int gi = i0 + ey, gj = j0 + ex;
-            T zv = T(0);
-            if (gi >= 0 && gi < ny && gj >= 0 && gj < nx) {
-                const T rx_here = (gj < nx - 1) ? fma(c, ax[e] - bx[e], ax[e]) : T(0);
-                const T rx_left = (gj > 0 && ex > 0) ? fma(c, ax[e - 1] - bx[e - 1], ax[e - 1]) : T(0);
-                const T ry_here = (gi < ny - 1) ? fma(c, ay[e] - by[e], ay[e]) : T(0);
-                const T ry_up = (gi > 0 && ey > 0) ? fma(c, ay[e - EX] - by[e - EX], ay[e - EX]) : T(0);
-                const T dt = (rx_left - rx_here) + (ry_up - ry_here);
-                zv = vL[e] - tau * dt;
-                if (nonneg && zv < T(0)) zv = T(0);
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            const int gi = i0 + r;
+            const T zr = __shfl_down(zz[r], 1);
+            const T zb = r < RW - 1 ? zz[r + 1] : z_below;
+            const T dzx = has_right ? zr - zz[r] : T(0);
+            const T dzy = (gi < ny - 1) ? zb - zz[r] : T(0);
+            T ax = fma(step, dzx, rx[r]), ay = fma(step, dzy, ry[r]);
+            const T n2 = fma(ax, ax, ay * ay);
+            if (n2 > T(1)) {
+                if constexpr (std::is_same<T, float>::value) {
+                    const T sc = __frsqrt_rn(n2);   // 1 / ||(ax, ay)||
+                    ax *= sc;
+                    ay *= sc;
+                } else {
+                    const T nrm = sqrt(n2);
+                    ax /= nrm;
+                    ay /= nrm;
+                }
             }
-            zL[e] = zv;
-        }
-        __syncthreads();
-        // p_k = P_P(r_k + step D z_k); shift p_{k-1} -> p_{k-2}
-        for (int e = threadIdx.x; e < EN; e += kBlock) {
-            const int ey = e / EX, ex = e - ey * EX;
-            const int gi = i0 + ey, gj = j0 + ex;
-            if (gi >= 0 && gi < ny && gj >= 0 && gj < nx) {
-                const T dzx = (gj < nx - 1 && ex < EX - 1) ? zL[e + 1] - zL[e] : T(0);
-                const T dzy = (gi < ny - 1 && ey < EY - 1) ? zL[e + EX] - zL[e] : T(0);
-                const T rx = fma(c, ax[e] - bx[e], ax[e]);
-                const T ry = fma(c, ay[e] - by[e], ay[e]);
-                T px = fma(step, dzx, rx), py = fma(step, dzy, ry);
-                project_ball2(px, py);
-                bx[e] = ax[e];
-                by[e] = ay[e];
-                ax[e] = px;
-                ay[e] = py;
+            if (in[r]) {
+                rx[r] = fma(c, ax - px[r], ax);
+                ry[r] = fma(c, ay - py[r], ay);
+                px[r] = ax;
+                py[r] = ay;
             }
         }
-        __syncthreads();
     }
 
-    // write back the tile's own pixels
-    for (int e = threadIdx.x; e < kFgpTX * kFgpTY; e += kBlock) {
-        const int ty = e / kFgpTX, tx = e - ty * kFgpTX;
-        const int gi = blockIdx.y * kFgpTY + ty, gj = blockIdx.x * kFgpTX + tx;
-        if (gi >= ny || gj >= nx) continue;
-        const int le = (ty + halo) * EX + (tx + halo);
-        const size_t p = static_cast<size_t>(gi) * nx + gj;
-        if (fin.mode == 0) {
-            pa_out[p] = ax[le];
-            pa_out[p + n] = ay[le];
-            pb_out[p] = bx[le];
-            pb_out[p + n] = by[le];
-        } else {
-            // z = P_C(v - tau D^T p_K)
-            const T px_here = (gj < nx - 1) ? ax[le] : T(0);
-            const T px_left = (gj > 0) ? ax[le - 1] : T(0);
-            const T py_here = (gi < ny - 1) ? ay[le] : T(0);
-            const T py_up = (gi > 0) ? ay[le - EX] : T(0);
-            const T dt = (px_left - px_here) + (py_up - py_here);
-            T zv = vL[le] - tau * dt;
-            if (nonneg && zv < T(0)) zv = T(0);
-            if (fin.mode == 1) {
-                fin.z[p] = zv;
-            } else {
-                fin.x[p] = zv;
-                if (fin.mode == 2) fin.h[p] = fin.hscale * (zv - vL[le]);
-            }
-            fin.dual_out[p] = ax[le];
-            fin.dual_out[p + n] = ay[le];
+    // write back the interior
+    const bool col_int = lane >= halo && lane < halo + TX;
+    if (fin.mode == 0) {
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            const int ey = wave * RW + r;
+            if (!in[r] || !col_int || ey < halo || ey >= halo + TY) continue;
+            const size_t q = static_cast<size_t>(i0 + r) * nx + gj;
+            p_out[q] = px[r];
+            p_out[q + n] = py[r];
+            r_out[q] = rx[r];
+            r_out[q + n] = ry[r];
         }
+        return;
+    }
+    // z = P_C(v - tau D^T p_K)
+    __syncthreads();
+    xch[0][wave][lane] = py[RW - 1];
+    __syncthreads();
+    const T py_above = wave > 0 ? xch[0][wave - 1][lane] : T(0);
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+        const int gi = i0 + r, ey = wave * RW + r;
+        const T pxl = __shfl_up(px[r], 1);
+        if (!in[r] || !col_int || ey < halo || ey >= halo + TY) continue;
+        const T ph = (gj < nx - 1) ? px[r] : T(0);
+        const T pl = (gj > 0) ? pxl : T(0);
+        const T qh = (gi < ny - 1) ? py[r] : T(0);
+        const T qu = (gi > 0) ? (r > 0 ? py[r - 1] : py_above) : T(0);
+        T zv = vv[r] - tau * ((pl - ph) + (qu - qh));
+        if (nonneg && zv < T(0)) zv = T(0);
+        const size_t q = static_cast<size_t>(gi) * nx + gj;
+        if (fin.mode == 1) {
+            fin.z[q] = zv;
+        } else {
+            fin.x[q] = zv;
+            if (fin.mode == 2) fin.h[q] = fin.hscale * (zv - vv[r]);
+        }
+        fin.dual_out[q] = px[r];
+        fin.dual_out[q + n] = py[r];
     }
 }
 
@@ -316,27 +341,28 @@ static ps_status fgp_t(const ps_geometry *g, const T *v, T *dual, double tau_d, 
     const T stepT = static_cast<T>(1.0 / (4.0 * dims * tau_d));
 
     if (dims == 2) {
-        const int tmax = g->elem == sizeof(double) ? 4 : kFgpMaxIters;
+        const int tmax = fgp_max_iters(g->elem), EY = fgp_rows(g->elem);
         const int launches = std::max(1, (K + tmax - 1) / tmax);
-        const dim3 grid((d.nx + kFgpTX - 1) / kFgpTX, (d.ny + kFgpTY - 1) / kFgpTY);
+        const std::vector<double> cn = momentum(K + 1);
         int done = 0;
-        const T *in_a = dual_in, *in_b = dual_in;
+        const T *in_p = dual_in, *in_r = dual_in;  // r_1 = p_0
         for (int L = 0; L < launches; ++L) {
             const int iters = std::min(tmax, K - done);
             const int halo = iters + 1;
-            const size_t lds = static_cast<size_t>(6) * (kFgpTX + 2 * halo) * (kFgpTY + 2 * halo) * g->elem;
+            const int TX = kFgpEX - 2 * halo, TY = EY - 2 * halo;
+            const dim3 grid((d.nx + TX - 1) / TX, (d.ny + TY - 1) / TY);
             FgpCoef<T> cf{};
-            for (int t = 0; t < iters; ++t) cf.c[t] = static_cast<T>(cs[done + t + 1]);
+            for (int t = 0; t < iters; ++t) cf.c[t] = static_cast<T>(cn[done + t + 2]);
             const bool last = (L == launches - 1);
             FgpFinal<T> f = fin;
-            T *out_a = buf[2 * (L % 2)], *out_b = buf[2 * (L % 2) + 1];
+            T *out_p = buf[2 * (L % 2)], *out_r = buf[2 * (L % 2) + 1];
             bool copy_back = false;
             if (last) {
                 // the final dual must not land in a buffer this launch still reads as halo
                 if (!dual) {
-                    f.dual_out = out_a;  // cold start: dual discarded
+                    f.dual_out = out_p;  // cold start: dual discarded
                 } else if (L == 0) {
-                    f.dual_out = out_a;  // single launch reading the caller's dual: copy after
+                    f.dual_out = out_p;  // single launch reading the caller's dual: copy after
                     copy_back = true;
                 } else {
                     f.dual_out = dual;
@@ -344,15 +370,15 @@ static ps_status fgp_t(const ps_geometry *g, const T *v, T *dual, double tau_d, 
             } else {
                 f.mode = 0;
             }
-            hipLaunchKernelGGL((k_fgp2d<T>), grid, dim3(kBlock), lds, st, vin, in_a, in_b, out_a,
-                               out_b, d.nx, d.ny, iters, halo, cf, tauT, stepT, nonneg, f);
+            hipLaunchKernelGGL((k_fgp2d<T, fgp_rw<T>()>), grid, dim3(kBlock), 0, st, vin, in_p, in_r,
+                               out_p, out_r, d.nx, d.ny, iters, halo, cf, tauT, stepT, nonneg, f);
             PS_LAUNCHED("k_fgp2d");
             if (copy_back) {
-                hipLaunchKernelGGL((k_copy<T>), dim3(grid_for(dn)), dim3(kBlock), 0, st, dual, out_a, dn);
+                hipLaunchKernelGGL((k_copy<T>), dim3(grid_for(dn)), dim3(kBlock), 0, st, dual, out_p, dn);
                 PS_LAUNCHED("k_copy");
             }
-            in_a = out_a;
-            in_b = out_b;
+            in_p = out_p;
+            in_r = out_r;
             done += iters;
         }
         return PS_OK;

@@ -1,4 +1,6 @@
 // geometry.hip -- host side: errors, geometry validation and per-angle tables, random streams.
+#include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -142,8 +144,7 @@ extern "C" ps_status make_geometry(const ps_geometry_desc *d, ps_geometry **out)
     std::vector<double> a0(A), a1(A), a2(A), inv(A), ia1(A);
     std::vector<int32_t> row(A);
     const double du = d->bin_width, s_first = d->det_offset - 0.5 * (B - 1) * du;
-    double hw_max = 0.0, slot_max = 0.0;
-    const int tx = 32, ty = 8;
+    double min_a1 = INFINITY;
     for (int k = 0; k < A; ++k) {
         const double c = std::cos(g->angles[k]), s = std::sin(g->angles[k]);
         if (std::fabs(c) >= std::fabs(s)) {
@@ -167,29 +168,41 @@ extern "C" ps_status make_geometry(const ps_geometry_desc *d, ps_geometry **out)
             delete g;
             return fail(PS_EUNSUPPORTED, "detector extends too far from the image (|q| >= 2^30)");
         }
-        const double hw = std::fabs(ia1[k]);
-        hw_max = std::max(hw_max, hw);
-        // bins touched by a tx x ty tile: span of u* over the tile plus the tent support
-        const int t_target = row[k] ? tx : ty, t_along = row[k] ? ty : tx;
-        const double span = (t_target - 1) * hw + (t_along - 1) * std::fabs(a2[k] * ia1[k]);
-        slot_max = std::max(slot_max, span + 2.0 * hw);
+        min_a1 = std::min(min_a1, std::fabs(a1[k]));
     }
-    g->max_half_width = hw_max;
-    BackPlan &bp = g->bplan;
-    bp.tx = tx;
-    bp.ty = ty;
-    bp.chunk = 32;
-    bp.slot = static_cast<int>(std::ceil(slot_max)) + 6;
-    bp.ncand = std::max(1, static_cast<int>(std::ceil(2.0 * hw_max - 1e-12)));
-    bp.lds_bytes = static_cast<size_t>(bp.chunk) * bp.slot * g->elem;
-    if (bp.lds_bytes > 48 * 1024) {
-        // very fine detector bins: fewer angles per LDS pass
-        bp.chunk = std::max(1, static_cast<int>((48 * 1024) / (bp.slot * g->elem)));
-        bp.lds_bytes = static_cast<size_t>(bp.chunk) * bp.slot * g->elem;
-        if (bp.chunk < 1 || bp.lds_bytes > 48 * 1024) {
+    // Backprojector passes: rays P apart in one pass are >= 2 pixels apart, so their two
+    // deposits never share a pixel (checked in the fixed-point units the FP32 kernels use).
+    {
+        int64_t min_q1 = INT64_MAX;
+        for (int k = 0; k < A; ++k) min_q1 = std::min<int64_t>(min_q1, std::llabs(std::llround(std::ldexp(a1[k], 32))));
+        const int64_t two = static_cast<int64_t>(1) << 33;
+        const int pass_fixed = static_cast<int>((two + min_q1 - 1) / min_q1);
+        const int pass_double = static_cast<int>(std::ceil(2.000001 / min_a1));
+        g->bp_passes = d->dtype == PS_F64 ? pass_double : pass_fixed;
+        if (g->bp_passes > 64) {
             delete g;
-            return fail(PS_EUNSUPPORTED, "detector bins too fine for the backprojector tiles");
+            return fail(PS_EUNSUPPORTED, "detector bins finer than 1/32 pixel are not supported");
         }
+    }
+
+    // Angle lists per subset (and for all angles): row-walked angles first, then column-walked.
+    {
+        const int N = d->n_subsets;
+        g->order_full.clear();
+        for (int k = 0; k < A; ++k) if (row[k]) g->order_full.push_back(k);
+        g->nrow_full = static_cast<int>(g->order_full.size());
+        for (int k = 0; k < A; ++k) if (!row[k]) g->order_full.push_back(k);
+        g->order_sub.clear();
+        g->sub_off.assign(N + 1, 0);
+        g->nrow_sub.assign(N, 0);
+        for (int i = 0; i < N; ++i) {
+            g->sub_off[i] = static_cast<int>(g->order_sub.size());
+            const int na = (A - 1 - i) / N + 1;
+            for (int l = 0; l < na; ++l) if (row[i + l * N]) g->order_sub.push_back(l);
+            g->nrow_sub[i] = static_cast<int>(g->order_sub.size()) - g->sub_off[i];
+            for (int l = 0; l < na; ++l) if (!row[i + l * N]) g->order_sub.push_back(l);
+        }
+        g->sub_off[N] = static_cast<int>(g->order_sub.size());
     }
 
     // Device table layout: five T arrays and one int32 array of A entries, each 256-aligned.
@@ -204,12 +217,16 @@ extern "C" ps_status make_geometry(const ps_geometry_desc *d, ps_geometry **out)
     g->off_q0 = take(A * sizeof(int64_t));
     g->off_q1 = take(A * sizeof(int64_t));
     g->off_q2 = take(A * sizeof(int64_t));
+    g->off_ord_full = take(A * sizeof(int32_t));
+    g->off_ord_sub = take(A * sizeof(int32_t));
     g->tab_bytes = off;
     g->host_tab.assign(off, 0);
     if (d->dtype == PS_F64)
         fill_tables<double>(g, a0, a1, a2, inv, ia1, row);
     else
         fill_tables<float>(g, a0, a1, a2, inv, ia1, row);
+    std::memcpy(g->host_tab.data() + g->off_ord_full, g->order_full.data(), A * sizeof(int32_t));
+    std::memcpy(g->host_tab.data() + g->off_ord_sub, g->order_sub.data(), A * sizeof(int32_t));
     *out = g;
     return PS_OK;
 }

@@ -63,6 +63,7 @@ struct AngleTab {
     const T *a0, *a1, *a2, *inv, *ia1;
     const int32_t *row;
     const int64_t *q0, *q1, *q2;
+    const int32_t *ord_full, *ord_sub;
 };
 
 // Launch plan of the forward projector for one subset size.
@@ -74,13 +75,15 @@ struct ProjPlan {
     size_t lds_bytes;
 };
 
-// Launch plan of the backprojector.
+// Launch plan of the backprojector (ray-driven scatter into LDS strips, see backproject.hip).
 struct BackPlan {
-    int tx, ty;     // pixel tile
-    int chunk;      // angles staged in LDS at a time
-    int slot;       // bins staged per angle (footprint of a tile, with margins)
-    int ncand;      // candidate bins per pixel and angle
+    int strip;      // R: image rows (or columns) per workgroup strip
+    int waves;      // waves per workgroup, each with a private accumulator strip
+    int stride;     // LDS row stride (floats): max(nx, ny) + 4
+    int groups;     // G: angle groups, each producing a partial image per angle class
+    int s_row, s_col;  // strips of rows (row-walked angles) and of columns
     size_t lds_bytes;
+    size_t part_elems;  // elements of the partial-image workspace (2 G n)
 };
 
 }  // namespace ps
@@ -94,8 +97,11 @@ struct ps_geometry {
     std::vector<unsigned char> host_tab;
     size_t off_a0, off_a1, off_a2, off_inv, off_ia1, off_row, off_q0, off_q1, off_q2, tab_bytes;
     void *dev;                            // uploaded tables (caller-owned), or null
-    double max_half_width;                // max |ia1| over angles (tent half-width in bins)
-    ps::BackPlan bplan;
+    int bp_passes;                        // backprojector ray passes (see BackPlan)
+    // angle lists, row-walked first: all angles, and subset i at order_sub[sub_off[i]..]
+    std::vector<int32_t> order_full, order_sub, sub_off, nrow_sub;
+    int nrow_full;
+    size_t off_ord_full, off_ord_sub;
 };
 
 namespace ps {
@@ -116,7 +122,9 @@ AngleTab<T> angle_tab(const ps_geometry *g) {
                        reinterpret_cast<const int32_t *>(b + g->off_row),
                        reinterpret_cast<const int64_t *>(b + g->off_q0),
                        reinterpret_cast<const int64_t *>(b + g->off_q1),
-                       reinterpret_cast<const int64_t *>(b + g->off_q2)};
+                       reinterpret_cast<const int64_t *>(b + g->off_q2),
+                       reinterpret_cast<const int32_t *>(b + g->off_ord_full),
+                       reinterpret_cast<const int32_t *>(b + g->off_ord_sub)};
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -148,8 +156,10 @@ struct UpdateArgs {
     double gamma, gamma_over_p, nsub;
     int coin, plain;
 };
+BackPlan back_plan(const ps_geometry *g, int subset);
+size_t back_workspace(const ps_geometry *g, int subset);
 ps_status launch_backproject(const ps_geometry *g, int subset, const void *y, void *out, int mode,
-                             const UpdateArgs *upd, hipStream_t st);
+                             const UpdateArgs *upd, void *ws, size_t ws_bytes, hipStream_t st);
 
 // ---------------------------------------------------------------------------------------------
 // TV prox by FGP (fgp.hip).

@@ -1,30 +1,45 @@
 // project.hip -- forward projector y = A_i x: ray-driven Joseph interpolation (K1).
 //
-// One workgroup owns one angle of one slice and every detector bin of it (each thread carries
-// up to 8 rays in registers).  The image is walked along the ray's stepping axis in strips that
-// are staged in LDS with coalesced loads: rows for row-walked angles, and, for column-walked
-// angles, column strips stored transposed, so that in both cases a ray reads two neighbouring
-// LDS words per step.  When angles x slices alone cannot fill the chip, the stepping axis is
-// also split over `split` workgroups whose partial sums a second pass adds in a fixed order
-// (no atomics: results do not depend on the split).
+// A workgroup owns one angle of one slice and every detector bin of it (each thread carries
+// ceil(B/256) rays in registers).  The image is walked along the ray's stepping axis in strips
+// of R rows (row-walked angles) or R columns (column-walked angles, stored transposed), staged in
+// LDS with 16-byte coalesced loads, four zero words on each side of every staged row.  A ray step
+// is then one two-word LDS read and six VALU operations:
+//     FP32: Q += q2 (32.32 fixed point), idx = min(hi(Q), ext + 4),
+//           acc_v += v0,  acc_d += lo(Q) * (v1 - v0)          (scaled by 2^-32 once at the end)
+//     FP64: q = a0 + u a1 + t a2 in double, floor / fraction.
+// When angles x slices cannot fill the chip, the stepping axis is split over `split`
+// workgroups whose partial sums a second pass adds in a fixed order (no atomics, so results do
+// not depend on timing).  A per-workgroup completion counter with a device-scope fence would
+// save that launch, but on this chip such a fence writes back the XCD's L2 and costs more.
 #include <algorithm>
 
 #include "internal.h"
 
 namespace ps {
 
+constexpr int kPad = 4;  // zero words left of each staged row (keeps 16-byte alignment)
+
+static int strip_rows(int stride, size_t elem) {
+    // largest power of two R in [4, 16] with R staged rows within 34 KB of LDS
+    int r = 16;
+    while (r > 4 && static_cast<size_t>(r) * stride * elem > 34 * 1024) r >>= 1;
+    return r;
+}
+
 ProjPlan proj_plan(const ps_geometry *g, int na) {
     const auto &d = g->desc;
     ProjPlan p{};
     const int ext = std::max(d.nx, d.ny);
-    p.stride = (ext + 4) | 1;  // odd stride: transposed column-strip stores hit distinct banks
-    p.strip = static_cast<int>(std::min<size_t>(32, (64 * 1024) / (p.stride * g->elem)));
-    if (p.strip < 1) p.strip = 1;
-    p.rpt = d.n_bins <= 256 ? 1 : d.n_bins <= 512 ? 2 : d.n_bins <= 1024 ? 4 : 8;
+    // words per staged row: a multiple of 4 (16-byte rows) that is 4 mod 16, so the transposed
+    // stores of a column strip (4 rows x 16 image rows per wave) hit 64 distinct banks
+    p.stride = (ext + 2 * kPad + 3) / 4 * 4;
+    p.stride += ((4 - p.stride % 16) + 16) % 16;
+    p.strip = strip_rows(p.stride, g->elem);
+    p.rpt = std::max(1, (d.n_bins + kBlock - 1) / kBlock);
     const long base = static_cast<long>(std::max(na, 1)) * d.nz;
-    const int steps = std::max(d.nx, d.ny);
-    const int max_split = std::max(1, steps / 16);
-    long want = (2048 + base - 1) / base;
+    const int max_split = std::max(1, ext / (2 * p.strip));
+    const long want = (2048 + base - 1) / base;
     p.split = static_cast<int>(std::max(1L, std::min<long>(want, max_split)));
     p.lds_bytes = static_cast<size_t>(p.strip) * p.stride * g->elem;
     return p;
@@ -36,96 +51,189 @@ size_t proj_workspace(const ps_geometry *g, int na) {
     return align_up(static_cast<size_t>(p.split) * g->desc.nz * na * g->desc.n_bins * g->elem);
 }
 
-// Sum over the ray's steps in [s*rb, (s+1)*rb) of the interpolated samples of u = x - xs.
+template <typename T>
+struct Vec4 {
+    T a, b, c, d;
+};
+
+template <typename T>
+__device__ inline Vec4<T> load4(const T *p) {
+    if constexpr (std::is_same<T, float>::value) {
+        const float4 v = *reinterpret_cast<const float4 *>(p);
+        return Vec4<T>{v.x, v.y, v.z, v.w};
+    } else {
+        return Vec4<T>{p[0], p[1], p[2], p[3]};
+    }
+}
+
 template <typename T, int RPT>
 __global__ __launch_bounds__(kBlock) void k_project(
     const T *__restrict__ x, const T *__restrict__ xs, AngleTab<T> tab, int subset, int nsub,
-    int na, int nx, int ny, int nbins, int split, int strip, int stride,
-    T *__restrict__ out, const T *__restrict__ b, int n_angles) {
+    int na, int nx, int ny, int nbins, int split, int strip, int stride, int vec,
+    T *__restrict__ out, const T *__restrict__ b, int n_angles, T *__restrict__ part) {
     extern __shared__ unsigned char smem_raw[];
     T *lds = reinterpret_cast<T *>(smem_raw);
+    constexpr bool kFixed = std::is_same<T, float>::value;
 
     const int s = blockIdx.x, l = blockIdx.y, z = blockIdx.z;
     const int k = subset < 0 ? l : subset + l * nsub;
     const bool row = tab.row[k] != 0;
-    const T a0 = tab.a0[k], a1 = tab.a1[k], a2 = tab.a2[k];
     const int nsteps = row ? ny : nx;
     const int ext = row ? nx : ny;
-    const int rb = (nsteps + split - 1) / split;
+    // steps of this workgroup: a multiple of the strip, so column strips stay 16-byte aligned
+    const int rb = ((nsteps + split - 1) / split + strip - 1) / strip * strip;
     const int t_lo = s * rb;
     const int t_hi = min(nsteps, t_lo + rb);
     const size_t plane = static_cast<size_t>(nx) * ny;
     const T *xz = x + z * plane;
     const T *xsz = xs ? xs + z * plane : nullptr;
+    const uint32_t lim = static_cast<uint32_t>(ext + kPad);
 
-    const int64_t q0 = tab.q0[k], q1 = tab.q1[k], q2 = tab.q2[k];
-    T acc[RPT];
-    T uf[RPT];
+    // zero pads: kPad words left of each row, everything right of ext
+    {
+        const int npad = stride - ext;  // kPad on the left, the rest on the right
+        for (int e = threadIdx.x; e < strip * npad; e += kBlock) {
+            const int t = e / npad, c = e - t * npad;
+            lds[t * stride + (c < kPad ? c : ext + c)] = T(0);
+        }
+    }
+
+    const int64_t q1 = tab.q1[k], q2 = tab.q2[k];
+    const int64_t q0b = tab.q0[k] + (static_cast<int64_t>(kPad) << 32);  // hi(Q) = j0 + kPad
+    const T a0 = tab.a0[k], a1 = tab.a1[k], a2 = tab.a2[k];
+    T acc_v[RPT], acc_d[RPT];
     int64_t uq[RPT];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
-        acc[r] = T(0);
-        uf[r] = static_cast<T>(threadIdx.x + r * kBlock);
+        acc_v[r] = T(0);
+        acc_d[r] = T(0);
         uq[r] = static_cast<int64_t>(threadIdx.x + r * kBlock) * q1;
     }
 
     for (int t0 = t_lo; t0 < t_hi; t0 += strip) {
         const int nt = min(strip, t_hi - t0);
-        const int cnt = nt * ext;
-        if (row) {
-            // rows t0..t0+nt-1, contiguous in memory
-            for (int e = threadIdx.x; e < cnt; e += kBlock) {
+        if (vec) {
+            // 16-byte loads: x and xs rows are 16-byte aligned (nx % 4 == 0)
+            if (row) {
+                const int q4 = ext / 4, cnt = nt * q4;
+                // element e = t * q4 + c, advanced by 8 x 256 per pass without dividing
+                int t_s = threadIdx.x / q4, c_s = threadIdx.x - t_s * q4;
+                const int adv_t = kBlock / q4, adv_c = kBlock - adv_t * q4;
+                for (int e0 = threadIdx.x; e0 < cnt; e0 += 8 * kBlock) {
+                    Vec4<T> v[8];
+                    int tt[8], cc[8];
+                    int t = t_s, c = c_s;
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        tt[u] = t;
+                        cc[u] = c;
+                        if (e0 + u * kBlock < cnt) {
+                            const size_t gi = static_cast<size_t>(t0 + t) * nx + 4 * c;
+                            v[u] = load4(xz + gi);
+                            if (xsz) {
+                                const Vec4<T> w = load4(xsz + gi);
+                                v[u] = Vec4<T>{v[u].a - w.a, v[u].b - w.b, v[u].c - w.c, v[u].d - w.d};
+                            }
+                        }
+                        t += adv_t;
+                        c += adv_c;
+                        if (c >= q4) {
+                            c -= q4;
+                            ++t;
+                        }
+                    }
+                    t_s = t;
+                    c_s = c;
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        if (e0 + u * kBlock < cnt) {
+                            T *dst = lds + tt[u] * stride + kPad + 4 * cc[u];
+                            dst[0] = v[u].a;
+                            dst[1] = v[u].b;
+                            dst[2] = v[u].c;
+                            dst[3] = v[u].d;
+                        }
+                    }
+                }
+            } else {
+                // column strip: groups of 4 adjacent columns of one image row, stored transposed
+                const int g4 = strip / 4, g4s = __builtin_ctz(g4), cnt = ext * g4;
+                for (int e0 = threadIdx.x; e0 < cnt; e0 += 8 * kBlock) {
+                    Vec4<T> v[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int e = e0 + u * kBlock;
+                        const int i = e >> g4s, cg = e & (g4 - 1);
+                        if (e < cnt && 4 * cg < nt) {
+                            const size_t gi = static_cast<size_t>(i) * nx + t0 + 4 * cg;
+                            v[u] = load4(xz + gi);
+                            if (xsz) {
+                                const Vec4<T> w = load4(xsz + gi);
+                                v[u] = Vec4<T>{v[u].a - w.a, v[u].b - w.b, v[u].c - w.c, v[u].d - w.d};
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int e = e0 + u * kBlock;
+                        const int i = e >> g4s, cg = e & (g4 - 1);
+                        if (e < cnt && 4 * cg < nt) {
+                            T *dst = lds + (4 * cg) * stride + kPad + i;
+                            dst[0] = v[u].a;
+                            dst[stride] = v[u].b;
+                            dst[2 * stride] = v[u].c;
+                            dst[3 * stride] = v[u].d;
+                        }
+                    }
+                }
+            }
+        } else if (row) {
+            for (int e = threadIdx.x; e < nt * ext; e += kBlock) {
                 const int t = e / ext, c = e - t * ext;
                 const size_t gi = static_cast<size_t>(t0 + t) * nx + c;
-                T v = xz[gi];
-                if (xsz) v -= xsz[gi];
-                lds[t * stride + 2 + c] = v;
+                lds[t * stride + kPad + c] = xsz ? xz[gi] - xsz[gi] : xz[gi];
             }
         } else {
-            // columns t0..t0+nt-1: read row segments, store transposed (one LDS row per column)
-            for (int e = threadIdx.x; e < cnt; e += kBlock) {
-                const int c = e / nt, t = e - c * nt;
-                const size_t gi = static_cast<size_t>(c) * nx + (t0 + t);
-                T v = xz[gi];
-                if (xsz) v -= xsz[gi];
-                lds[t * stride + 2 + c] = v;
+            for (int e = threadIdx.x; e < nt * ext; e += kBlock) {
+                const int i = e / nt, t = e - i * nt;
+                const size_t gi = static_cast<size_t>(i) * nx + t0 + t;
+                lds[t * stride + kPad + i] = xsz ? xz[gi] - xsz[gi] : xz[gi];
             }
-        }
-        // two zero words on each side: out-of-image samples read zeros after clamping
-        for (int e = threadIdx.x; e < nt * 4; e += kBlock) {
-            const int t = e >> 2, c = e & 3;
-            lds[t * stride + (c < 2 ? c : ext + c)] = T(0);
         }
         __syncthreads();
 
-        if constexpr (std::is_same<T, float>::value) {
-            // exact 32.32 fixed-point walk: high word = floor(q), low word = weight
+        if constexpr (kFixed) {
+            int64_t q[RPT];
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) q[r] = q0b + static_cast<int64_t>(t0) * q2 + uq[r];
             for (int t = 0; t < nt; ++t) {
-                const int64_t bt = q0 + static_cast<int64_t>(t0 + t) * q2;
-                const T *lrow = lds + t * stride + 2;
+                const T *lrow = lds + t * stride;
+                T v0[RPT], v1[RPT];
 #pragma unroll
                 for (int r = 0; r < RPT; ++r) {
-                    const int64_t q = bt + uq[r];
-                    int j0 = static_cast<int>(q >> 32);
-                    const float w = static_cast<float>(static_cast<uint32_t>(q) >> 8) * 0x1p-24f;
-                    j0 = min(max(j0, -2), ext);
-                    const T v0 = lrow[j0], v1 = lrow[j0 + 1];
-                    acc[r] += fma(w, v1, (T(1) - w) * v0);
+                    const uint32_t idx = min(static_cast<uint32_t>(q[r] >> 32), lim);
+                    v0[r] = lrow[idx];
+                    v1[r] = lrow[idx + 1];
+                }
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) {
+                    acc_v[r] += v0[r];
+                    acc_d[r] = fma(static_cast<T>(static_cast<uint32_t>(q[r])), v1[r] - v0[r], acc_d[r]);
+                    q[r] += q2;
                 }
             }
         } else {
             for (int t = 0; t < nt; ++t) {
                 const T bt = fma(static_cast<T>(t0 + t), a2, a0);
-                const T *lrow = lds + t * stride + 2;
+                const T *lrow = lds + t * stride;
 #pragma unroll
                 for (int r = 0; r < RPT; ++r) {
-                    const T q = fma(uf[r], a1, bt);
+                    const T q = fma(static_cast<T>(threadIdx.x + r * kBlock), a1, bt);
                     const T fl = floor(q);
-                    const T w = q - fl;
-                    int j0 = static_cast<int>(fl);
-                    j0 = min(max(j0, -2), ext);
-                    const T v0 = lrow[j0], v1 = lrow[j0 + 1];
-                    acc[r] += fma(w, v1, (T(1) - w) * v0);
+                    const uint32_t idx = min(static_cast<uint32_t>(static_cast<int>(fl) + kPad), lim);
+                    const T v0 = lrow[idx], v1 = lrow[idx + 1];
+                    acc_v[r] += v0;
+                    acc_d[r] = fma(q - fl, v1 - v0, acc_d[r]);
                 }
             }
         }
@@ -133,21 +241,24 @@ __global__ __launch_bounds__(kBlock) void k_project(
     }
 
     const int nz_ = gridDim.z;
+    const T dscale = kFixed ? T(0x1p-32f) : T(1);
+    const T inv = tab.inv[k];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
         const int u = threadIdx.x + r * kBlock;
         if (u >= nbins) break;
+        const T acc = fma(acc_d[r], dscale, acc_v[r]);
         if (split == 1) {
-            T val = acc[r] * tab.inv[k];
+            T val = acc * inv;
             if (b) val -= b[(static_cast<size_t>(z) * n_angles + k) * nbins + u];
             out[(static_cast<size_t>(z) * na + l) * nbins + u] = val;
         } else {
-            out[((static_cast<size_t>(s) * nz_ + z) * na + l) * nbins + u] = acc[r];
+            part[((static_cast<size_t>(s) * nz_ + z) * na + l) * nbins + u] = acc;
         }
     }
 }
 
-// y = inv_k * sum_s partial[s] (- b): fixed summation order.
+// y = inv_k * sum_s partial[s] (- b): fixed summation order, loads issued eight at a time.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_project_reduce(
     const T *__restrict__ part, AngleTab<T> tab, int subset, int nsub, int na, int nz, int nbins,
@@ -161,7 +272,14 @@ __global__ __launch_bounds__(kBlock) void k_project_reduce(
         const int z = static_cast<int>(zl / na);
         const int k = subset < 0 ? l : subset + l * nsub;
         T acc = T(0);
-        for (int s = 0; s < split; ++s) acc += part[s * total + e];
+        for (int s0 = 0; s0 < split; s0 += 8) {
+            T v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = s0 + q < split ? part[(s0 + q) * total + e] : T(0);
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (s0 + q < split) acc += v[q];
+        }
         T val = acc * tab.inv[k];
         if (b) val -= b[(static_cast<size_t>(z) * n_angles + k) * nbins + u];
         y[e] = val;
@@ -176,24 +294,32 @@ static ps_status project_t(const ps_geometry *g, int subset, const T *x, const T
     if (na <= 0) return PS_OK;
     const ProjPlan p = proj_plan(g, na);
     const AngleTab<T> tab = angle_tab<T>(g);
-    T *out = y;
+    T *part = nullptr;
     if (p.split > 1) {
         const size_t need = proj_workspace(g, na);
         if (!ws || ws_bytes < need)
             return fail(PS_EINVAL, "projector workspace: %zu bytes given, %zu needed", ws_bytes, need);
-        out = static_cast<T *>(ws);
+        part = static_cast<T *>(ws);
     }
+    // 16-byte staging needs rows (and column strips) that start on 16-byte boundaries
+    const bool aligned = reinterpret_cast<uintptr_t>(x) % 16 == 0 &&
+                         (!xs || reinterpret_cast<uintptr_t>(xs) % 16 == 0);
+    const int vec = (d.nx % 4 == 0 && aligned && sizeof(T) == 4) ? 1 : 0;
     const dim3 grid(p.split, na, d.nz);
     switch (p.rpt) {
 #define PS_PROJ_CASE(R)                                                                         \
     case R:                                                                                     \
         hipLaunchKernelGGL((k_project<T, R>), grid, dim3(kBlock), p.lds_bytes, st, x, xs, tab,   \
                            subset, d.n_subsets, na, d.nx, d.ny, d.n_bins, p.split, p.strip,      \
-                           p.stride, out, b, d.n_angles);                                        \
+                           p.stride, vec, y, b, d.n_angles, part);                               \
         break;
         PS_PROJ_CASE(1)
         PS_PROJ_CASE(2)
+        PS_PROJ_CASE(3)
         PS_PROJ_CASE(4)
+        PS_PROJ_CASE(5)
+        PS_PROJ_CASE(6)
+        PS_PROJ_CASE(7)
         PS_PROJ_CASE(8)
 #undef PS_PROJ_CASE
         default:
@@ -203,7 +329,7 @@ static ps_status project_t(const ps_geometry *g, int subset, const T *x, const T
     if (p.split > 1) {
         const size_t total = static_cast<size_t>(d.nz) * na * d.n_bins;
         const unsigned blocks = static_cast<unsigned>(std::min<size_t>((total + kBlock - 1) / kBlock, 65535));
-        hipLaunchKernelGGL((k_project_reduce<T>), dim3(blocks), dim3(kBlock), 0, st, out, tab,
+        hipLaunchKernelGGL((k_project_reduce<T>), dim3(blocks), dim3(kBlock), 0, st, part, tab,
                            subset, d.n_subsets, na, d.nz, d.n_bins, p.split, y, b, d.n_angles);
         PS_LAUNCHED("k_project_reduce");
     }

@@ -85,8 +85,8 @@ static int norm_blocks(size_t n) {
 }
 
 struct Layout {
-    size_t xs, gs, v, sino, pws, fws, npart, stats, total;
-    size_t pws_bytes, fws_bytes;
+    size_t xs, gs, v, sino, pws, bws, fws, npart, stats, total;
+    size_t pws_bytes, bws_bytes, fws_bytes;
 };
 
 static Layout layout(const ps_geometry *g, int n_epochs) {
@@ -102,6 +102,9 @@ static Layout layout(const ps_geometry *g, int n_epochs) {
     L.sino = take(m * g->elem);
     L.pws_bytes = std::max(proj_workspace(g, d.n_angles), proj_workspace(g, max_subset_count(g)));
     L.pws = take(L.pws_bytes);
+    L.bws_bytes = back_workspace(g, -1);
+    for (int i = 0; i < d.n_subsets; ++i) L.bws_bytes = std::max(L.bws_bytes, back_workspace(g, i));
+    L.bws = take(L.bws_bytes);
     L.fws_bytes = fgp_workspace(g);
     L.fws = take(L.fws_bytes);
     L.npart = take(sizeof(double) * 2 * kNormBlocks);
@@ -205,11 +208,13 @@ static ps_status run_epoch(ps_solver *s, hipStream_t st) {
             // r = A xs - b over all angles, then gs = A^T r fused with the step (G = gs)
             PS_TRY(launch_project(g, -1, w + s->L.xs, nullptr, s->b, w + s->L.sino, w + s->L.pws,
                                   s->L.pws_bytes, st));
-            PS_TRY(launch_backproject(g, -1, w + s->L.sino, nullptr, BP_SNAPSHOT, &up, st));
+            PS_TRY(launch_backproject(g, -1, w + s->L.sino, nullptr, BP_SNAPSHOT, &up, w + s->L.bws,
+                                      s->L.bws_bytes, st));
         } else {
             PS_TRY(launch_project(g, i, s->x, w + s->L.xs, nullptr, w + s->L.sino, w + s->L.pws,
                                   s->L.pws_bytes, st));
-            PS_TRY(launch_backproject(g, i, w + s->L.sino, nullptr, BP_SVRG, &up, st));
+            PS_TRY(launch_backproject(g, i, w + s->L.sino, nullptr, BP_SVRG, &up, w + s->L.bws,
+                                      s->L.bws_bytes, st));
         }
         if (prox) {
             PS_TRY(launch_fgp(g, w + s->L.v, s->dual, tau, P.fgp_inner, P.nonneg, fo, w + s->L.fws,

@@ -24,7 +24,7 @@ def nat():
 
 def test_exports_every_declared_symbol(nat):
     declared = _header_symbols()
-    assert len(declared) >= 19
+    assert len(declared) >= 20
     assert set(declared) == set(nat.EXPORTS)
     lib = C.CDLL(nat.LIB_PATH)
     for name in declared:
@@ -71,7 +71,7 @@ def test_geometry_queries_and_not_uploaded(nat):
         assert lib.geometry_upload(h, C.c_void_p(256), 1, None) == nat.PS_EINVAL
         # nothing is queued before the tables are uploaded
         assert lib.project_subset(h, 0, C.c_void_p(256), C.c_void_p(256), None, 0, None) == nat.PS_EINVAL
-        assert lib.backproject_subset(h, 0, C.c_void_p(256), C.c_void_p(256), 0, None) == nat.PS_EINVAL
+        assert lib.backproject_subset(h, 0, C.c_void_p(256), C.c_void_p(256), 0, None, 0, None) == nat.PS_EINVAL
         assert lib.project_subset(h, 9, C.c_void_p(256), C.c_void_p(256), None, 0, None) == nat.PS_EINVAL
         # tv prox argument checks
         assert lib.tv_prox_fgp(h, C.c_void_p(256), C.c_void_p(256), -1.0, 5, 1, None, None, 0, None) == nat.PS_EINVAL
