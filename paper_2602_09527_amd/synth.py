@@ -170,3 +170,45 @@ def perturbed_batch(batch: int, nx: int, ny: int, seed: int) -> np.ndarray:
     for k in range(batch):
         out[k] = rasterize(random_ellipses(seed + 1000 * k, 10), nx, ny)[0]
     return out + rng.standard_normal(out.shape)
+
+
+def analytic_sinogram_torch(ellipses: list[Ellipse], nx: int, ny: int, n_angles: int,
+                            n_bins: int, nz: int = 1, du: float = 1.0, off: float = 0.0,
+                            device="cuda", dtype=None):
+    """Same line integrals as analytic_sinogram, evaluated with torch on ``device`` (float64 by
+    default) -- for volumes too large to generate on the host in reasonable time."""
+    import torch
+    dtype = dtype or torch.float64
+    R = min(nx, ny) / 2.0
+    th = torch.arange(n_angles, device=device, dtype=torch.float64) * (math.pi / n_angles)
+    s = (torch.arange(n_bins, device=device, dtype=torch.float64) - (n_bins - 1) / 2.0) * du + off
+    ct, st = torch.cos(th)[:, None], torch.sin(th)[:, None]
+    out = torch.zeros((nz, n_angles, n_bins), device=device, dtype=dtype)
+    for z in range(nz):
+        acc = torch.zeros((n_angles, n_bins), device=device, dtype=torch.float64)
+        for e in ellipses:
+            sc = _slice_ellipse(e, nz, z)
+            if sc is None:
+                continue
+            A, Bq = e.a * sc[0] * R, e.b * sc[1] * R
+            s0 = e.cx * R * ct + e.cy * R * st
+            a2 = ((A * torch.cos(th - e.phi)) ** 2 + (Bq * torch.sin(th - e.phi)) ** 2)[:, None]
+            t = s[None, :] - s0
+            chord = 2.0 * A * Bq * torch.sqrt(torch.clamp(a2 - t * t, min=0.0)) / a2
+            acc += e.rho * chord
+        out[z] = acc.to(dtype)
+    return out
+
+
+def poisson_log_noise_torch(sino, seed: int, photons: float = 1e4, max_attenuation: float = 2.0):
+    """Transmission noise of add_poisson_log_noise, drawn with a seeded torch generator on the
+    sinogram's device (in place on a float copy)."""
+    import torch
+    gen = torch.Generator(device=sino.device).manual_seed(seed)
+    mu = max_attenuation / max(float(sino.max()), 1e-30)
+    out = torch.empty_like(sino)
+    for z in range(sino.shape[0]):  # slice by slice: bounded temporaries
+        lam = photons * torch.exp(-mu * sino[z].double())
+        counts = torch.poisson(lam, generator=gen)
+        out[z] = (-torch.log(torch.clamp(counts, min=1.0) / photons) / mu).to(sino.dtype)
+    return out

@@ -137,3 +137,17 @@ def test_handles_and_tolerance(orc):
     s3.cancel()
     with pytest.raises(Exception):
         s3.epochs(1)
+
+
+def test_volume_3d_reduced_10_epochs(orc):
+    # 8 slices of 128^2 coupled by 3D TV, 180 angles x 192 bins, 10 subsets, p = 0.05,
+    # Poisson-log noise, 50 FGP iterations, 10 epochs (the volume workload at reduced size)
+    from paper_2602_09527_amd import workloads
+    w = workloads.VOLUME_3D_REDUCED
+    g, o, b, b_dev, kw = _setup(orc, w, torch.float32)
+    assert g.tv_dims == 3
+    xo, ho, do, so, _ = orc.proxskip_svrg(o, b, **kw)
+    x, h, d, st = _gpu_run(g, b_dev, kw)
+    assert st["prox_calls"] == so["prox_calls"] > 0
+    assert _rel(x, xo) <= 1e-4, _rel(x, xo)
+    assert _rel(d, do) <= 1e-3, _rel(d, do)

@@ -1,0 +1,90 @@
+"""The volume workload at full size -- 256 slices of 1024^2, 1800 angles x 1448 bins, 30
+subsets -- in the launch configuration the solver uses: projector and backprojector outputs
+sampled ray by ray and pixel by pixel against the FP64 oracle, and the 3D FGP prox on a
+16 x 256^2 sub-volume."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def vol():
+    from paper_2602_09527_amd import api, workloads
+    w = workloads.VOLUME_3D
+    g = api.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=w.n_subsets, nz=w.nz)
+    gen = torch.Generator(device="cuda").manual_seed(404)
+    x = torch.rand(g.image_shape, device="cuda", generator=gen)
+    return w, g, x
+
+
+def _slices(zs):
+    uz = sorted(set(int(z) for z in zs))
+    return uz, {z: i for i, z in enumerate(uz)}
+
+
+def test_full_size_projection_sampled(orc, vol):
+    from paper_2602_09527_amd import api
+    w, g, x = vol
+    rng = np.random.default_rng(21)
+    for subset in (0, 17, -1):
+        if subset == -1:
+            # all 1800 angles on a 2-slice volume of the same 1024^2 x 1448 geometry
+            g2 = api.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=w.n_subsets, nz=2)
+            xs = x[100:102].contiguous()
+            y = api.project(g2, xs, -1)
+            zsel = [100, 101]
+        else:
+            y = api.project(g, x, subset)
+            zsel = None
+        torch.cuda.synchronize()
+        na = y.shape[1]
+        n = 256
+        zs = rng.choice(rng.choice(y.shape[0], min(6, y.shape[0]), replace=False), n)
+        ls = rng.integers(0, na, n)
+        us = rng.integers(0, w.n_bins, n)
+        got = y[zs, ls, us].double().cpu().numpy()
+        uz, pos = _slices(zs if zsel is None else [zsel[z] for z in zs])
+        ximg = (x[uz] if zsel is None else x[uz]).double().cpu().numpy()
+        o = orc.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=w.n_subsets, nz=len(uz))
+        ks = ls if subset == -1 else subset + ls * w.n_subsets
+        zz = np.array([pos[int(z) if zsel is None else zsel[int(z)]] for z in zs], dtype=np.int32)
+        ref = orc.project_rays(o, ximg, zz, ks, us)
+        assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref), subset
+
+
+def test_full_size_backprojection_sampled(orc, vol):
+    from paper_2602_09527_amd import api
+    w, g, x = vol
+    rng = np.random.default_rng(22)
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    for subset in (3, 29):
+        y = torch.randn(g.sino_shape(subset), device="cuda", generator=gen)
+        img = api.backproject(g, y, subset)
+        torch.cuda.synchronize()
+        n = 200
+        zs = rng.choice(rng.choice(w.nz, 6, replace=False), n)
+        is_, js = rng.integers(0, w.ny, n), rng.integers(0, w.nx, n)
+        got = img[zs, is_, js].double().cpu().numpy()
+        uz, pos = _slices(zs)
+        ysel = y[uz].double().cpu().numpy()
+        o = orc.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=w.n_subsets, nz=len(uz))
+        ref = orc.backproject_pixels(o, ysel, np.array([pos[int(z)] for z in zs], dtype=np.int32),
+                                     is_, js, subset)
+        assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref), subset
+
+
+def test_3d_fgp_subvolume(orc):
+    from paper_2602_09527_amd import api, synth
+    g = api.Geometry(256, 256, 4, 8, nz=16)
+    ells = synth.random_ellipses(404, 10, dims=3)
+    v = synth.rasterize(ells, 256, 256, nz=16)
+    v = v + 0.05 * np.random.default_rng(23).standard_normal(v.shape)
+    dual = np.zeros((3, 16, 256, 256))
+    zo = orc.tv_prox_fgp(v, 3e-3, 50, nonneg=True, dual=dual)
+    dg = torch.zeros(g.dual_shape(), device="cuda")
+    z = api.tv_prox(g, torch.from_numpy(v).float().cuda(), 3e-3, 50, nonneg=True, dual=dg)
+    assert np.linalg.norm(z.cpu().numpy() - zo) <= 1e-5 * np.linalg.norm(zo)
+    assert np.linalg.norm(dg.cpu().numpy() - dual) <= 1e-3 * np.linalg.norm(dual)
