@@ -163,11 +163,19 @@ PS_API ps_status proxskip_svrg_run(const ps_geometry *geom, const void *b, void 
                             ps_solver_stats *stats_out, void *workspace, size_t ws_bytes,
                             void *stream);
 
-/* Resumable solver handles (the same iteration as proxskip_svrg_run, split into calls).
+/* Resumable solver handles (the same iteration as proxskip_svrg_run, split into calls), and
+ * batching of independent problems.
  * solver_init binds caller-owned buffers (they must outlive the handle; the workspace must be
  * proxskip_workspace_bytes(geom, params) bytes and may not be shared between live handles).
- * solver_epochs queues n_epochs further epochs of every handle on `stream`, interleaving the
- * handles epoch by epoch; handles that already met their tolerance or epoch budget are skipped.
+ * solver_epochs runs up to n_epochs further epochs of every handle on `stream`.  The handles may
+ * have different geometries, sizes, subset counts, dtypes and parameters: they advance in
+ * lockstep, one iteration each per step, and every stage of a step (snapshot copies,
+ * projections, backprojections with the fused update, FGP launches, epoch-end norms) is one
+ * launch over a work list of up to 16 handles.  Each handle computes exactly what it computes
+ * alone (bit for bit).  A handle with tol_rel_change > 0 pauses at each epoch end until its
+ * norms reach the host (pinned host memory behind an event) while the others continue; handles
+ * that met their tolerance or epoch budget are skipped.  Returns once every handle is done with
+ * this call's epochs (synchronising only for tolerance checks).  A handle may appear once.
  * solver_query synchronises the handle's stream and reports its progress.
  * solver_cancel makes later solver_epochs calls on the handle return PS_ECANCELLED. */
 typedef struct ps_solver ps_solver;

@@ -14,6 +14,7 @@
 // adds the 2G partials in a fixed order and applies the epilogue (overwrite, accumulate, or the
 // fused SVRG / ProxSkip gradient step).  Results are bitwise reproducible.
 #include <algorithm>
+#include <vector>
 
 #include "internal.h"
 
@@ -51,19 +52,37 @@ size_t back_workspace(const ps_geometry *g, int subset) {
     return align_up(back_plan(g, subset).part_elems * g->elem);
 }
 
+// One backprojector application: partial images of A_sub^T y, one per (angle class, group).
+template <typename T>
+struct BackItem {
+    const T *y;
+    T *part;
+    const int32_t *order;
+    AngleTab<T> tab;
+    int subset, nsub, na, nx, ny, nz, nbins, strip, stride, s_row, s_col, groups, passes, nrow;
+};
+
 template <typename T, int NP, int kStrip>
-__global__ __launch_bounds__(kBlock) void k_backproject(
-    const T *__restrict__ y, AngleTab<T> tab, int subset, int nsub, int na, int nx, int ny,
-    int nbins, int strip, int stride, int s_row, int groups, int passes, const int32_t *order,
-    int nrow, T *__restrict__ part) {
+__global__ __launch_bounds__(kBlock) void k_backproject(WorkList<BackItem<T>> wl) {
     extern __shared__ unsigned char smem_raw[];
     T *acc_all = reinterpret_cast<T *>(smem_raw);
     constexpr bool kFixed = std::is_same<T, float>::value;
+    int local;
+    const BackItem<T> &it = wl.item[work_item(wl, local)];
+    const T *__restrict__ y = it.y;
+    T *__restrict__ part = it.part;
+    const int32_t *__restrict__ order = it.order;
+    const AngleTab<T> &tab = it.tab;
+    const int subset = it.subset, nsub = it.nsub, na = it.na, nx = it.nx, ny = it.ny;
+    const int nbins = it.nbins, strip = it.strip, stride = it.stride, s_row = it.s_row;
+    const int groups = it.groups, passes = it.passes, nrow = it.nrow;
     const int nw = blockDim.x / kWave;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int z = blockIdx.z, grp = blockIdx.y;
-    const bool rowc = static_cast<int>(blockIdx.x) < s_row;
-    const int s = rowc ? blockIdx.x : blockIdx.x - s_row;
+    // workgroup -> (strip index, angle group, slice), strip fastest
+    const int nstrips = s_row + it.s_col;
+    const int sx = local % nstrips, grp = (local / nstrips) % groups, z = local / (nstrips * groups);
+    const bool rowc = sx < s_row;
+    const int s = rowc ? sx : sx - s_row;
     const int nsteps = rowc ? ny : nx;   // stepping axis of this class
     const int ext = rowc ? nx : ny;      // deposit axis
     const int t_lo = s * strip;
@@ -187,7 +206,7 @@ __global__ __launch_bounds__(kBlock) void k_backproject(
     __syncthreads();
 
     // sum the waves' strips (fixed order) and write this (class, group) partial image
-    T *pz = part + (static_cast<size_t>(rowc ? 0 : 1) * groups + grp) * (plane * gridDim.z) + z * plane;
+    T *pz = part + (static_cast<size_t>(rowc ? 0 : 1) * groups + grp) * (plane * it.nz) + z * plane;
     if (rowc) {
         for (int e = threadIdx.x; e < nt * ext; e += blockDim.x) {
             const int t = e / ext, j = e - t * ext;
@@ -216,11 +235,26 @@ struct UpdateT {
 };
 
 // d = sum of the 2G partial images (fixed order), then the epilogue of `mode`.
-template <typename T, int MODE>
-__global__ __launch_bounds__(kBlock) void k_backproject_combine(
-    const T *__restrict__ part, int groups, size_t n, T *__restrict__ out, UpdateT<T> upd) {
-    for (size_t p = blockIdx.x * static_cast<size_t>(kBlock) + threadIdx.x; p < n;
-         p += static_cast<size_t>(gridDim.x) * kBlock) {
+template <typename T>
+struct CombineItem {
+    const T *part;
+    T *out;
+    UpdateT<T> upd;
+    size_t n;
+    int groups, mode, blocks;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_backproject_combine(WorkList<CombineItem<T>> wl) {
+    int local;
+    const CombineItem<T> &it = wl.item[work_item(wl, local)];
+    const T *__restrict__ part = it.part;
+    T *__restrict__ out = it.out;
+    const UpdateT<T> &upd = it.upd;
+    const size_t n = it.n;
+    const int groups = it.groups, mode = it.mode;
+    for (size_t p = local * static_cast<size_t>(kBlock) + threadIdx.x; p < n;
+         p += static_cast<size_t>(it.blocks) * kBlock) {
         T d = T(0);
         for (int q0 = 0; q0 < 2 * groups; q0 += 8) {
             T v[8];
@@ -230,13 +264,13 @@ __global__ __launch_bounds__(kBlock) void k_backproject_combine(
             for (int q = 0; q < 8; ++q)
                 if (q0 + q < 2 * groups) d += v[q];
         }
-        if (MODE == BP_OVERWRITE) {
+        if (mode == BP_OVERWRITE) {
             out[p] = d;
-        } else if (MODE == BP_ACCUMULATE) {
+        } else if (mode == BP_ACCUMULATE) {
             out[p] += d;
         } else {
             T G;
-            if (MODE == BP_SNAPSHOT) {
+            if (mode == BP_SNAPSHOT) {
                 upd.gs[p] = d;
                 G = d;
             } else {
@@ -257,79 +291,159 @@ __global__ __launch_bounds__(kBlock) void k_backproject_combine(
     }
 }
 
-template <typename T>
-static ps_status backproject_t(const ps_geometry *g, int subset, const T *y, T *out, int mode,
-                               const UpdateArgs *u, void *ws, size_t ws_bytes, hipStream_t st) {
-    const auto &d = g->desc;
-    const int na = subset_count(g, subset);
-    const BackPlan bp = back_plan(g, subset);
-    const size_t need = back_workspace(g, subset);
-    if (!ws || ws_bytes < need)
-        return fail(PS_EINVAL, "backprojector workspace: %zu bytes given, %zu needed", ws_bytes, need);
-    T *part = static_cast<T *>(ws);
-    const AngleTab<T> tab = angle_tab<T>(g);
-    const int32_t *order = subset < 0 ? tab.ord_full : tab.ord_sub + g->sub_off[subset];
-    const int nrow = subset < 0 ? g->nrow_full : g->nrow_sub[subset];
-    const dim3 grid(bp.s_row + bp.s_col, bp.groups, d.nz);
-#define PS_BPK_ARGS                                                                              \
-    grid, dim3(kWave * bp.waves), bp.lds_bytes, st, y, tab, subset, d.n_subsets, na, d.nx, d.ny,  \
-        d.n_bins, bp.strip, bp.stride, bp.s_row, bp.groups, g->bp_passes, order, nrow, part
-#define PS_BPK_S(NP)                                                                             \
-    switch (bp.strip) {                                                                          \
-        case 8: hipLaunchKernelGGL((k_backproject<T, NP, 8>), PS_BPK_ARGS); break;               \
-        case 4: hipLaunchKernelGGL((k_backproject<T, NP, 4>), PS_BPK_ARGS); break;               \
-        default: hipLaunchKernelGGL((k_backproject<T, NP, 1>), PS_BPK_ARGS); break;              \
-    }
-    switch (g->bp_passes) {
-        case 1: PS_BPK_S(1) break;
-        case 2: PS_BPK_S(2) break;
-        case 3: PS_BPK_S(3) break;
-        case 4: PS_BPK_S(4) break;
-        default: PS_BPK_S(0) break;
-    }
-#undef PS_BPK_S
-#undef PS_BPK_ARGS
+template <typename T, int NP, int S>
+static ps_status launch_bp_list(const WorkList<BackItem<T>> &wl, int blocks, int waves, size_t lds,
+                                hipStream_t st) {
+    hipLaunchKernelGGL((k_backproject<T, NP, S>), dim3(blocks), dim3(kWave * waves), lds, st, wl);
     PS_LAUNCHED("k_backproject");
+    return PS_OK;
+}
 
-    UpdateT<T> ut{};
-    if (u) {
-        ut.x = static_cast<T *>(u->x);
-        ut.h = static_cast<const T *>(u->h);
-        ut.gs = static_cast<T *>(u->gs);
-        ut.vout = static_cast<T *>(u->vout);
-        ut.gamma = static_cast<T>(u->gamma);
-        ut.gamma_over_p = static_cast<T>(u->gamma_over_p);
-        ut.nsub = static_cast<T>(u->nsub);
-        ut.coin = u->coin;
-        ut.plain = u->plain;
+template <typename T, int NP>
+static ps_status launch_bp_strip(int strip, const WorkList<BackItem<T>> &wl, int blocks, int waves,
+                                 size_t lds, hipStream_t st) {
+    switch (strip) {
+        case 8: return launch_bp_list<T, NP, 8>(wl, blocks, waves, lds, st);
+        case 4: return launch_bp_list<T, NP, 4>(wl, blocks, waves, lds, st);
+        default: return launch_bp_list<T, NP, 1>(wl, blocks, waves, lds, st);
     }
-    const size_t n = static_cast<size_t>(d.nx) * d.ny * d.nz;
-    const unsigned blocks = static_cast<unsigned>(std::max<size_t>(1, std::min<size_t>((n + kBlock - 1) / kBlock, 8192)));
-    switch (mode) {
-#define PS_BP_CASE(M)                                                                           \
-    case M:                                                                                     \
-        hipLaunchKernelGGL((k_backproject_combine<T, M>), dim3(blocks), dim3(kBlock), 0, st, part, \
-                           bp.groups, n, out, ut);                                               \
-        break;
-        PS_BP_CASE(BP_OVERWRITE)
-        PS_BP_CASE(BP_ACCUMULATE)
-        PS_BP_CASE(BP_SVRG)
-        PS_BP_CASE(BP_SNAPSHOT)
-#undef PS_BP_CASE
-        default:
-            return fail(PS_EINVAL, "backprojector mode %d", mode);
+}
+
+template <typename T>
+static ps_status launch_bp_key(int np, int strip, const WorkList<BackItem<T>> &wl, int blocks,
+                               int waves, size_t lds, hipStream_t st) {
+    switch (np) {
+        case 1: return launch_bp_strip<T, 1>(strip, wl, blocks, waves, lds, st);
+        case 2: return launch_bp_strip<T, 2>(strip, wl, blocks, waves, lds, st);
+        case 3: return launch_bp_strip<T, 3>(strip, wl, blocks, waves, lds, st);
+        case 4: return launch_bp_strip<T, 4>(strip, wl, blocks, waves, lds, st);
+        default: return launch_bp_strip<T, 0>(strip, wl, blocks, waves, lds, st);
     }
-    PS_LAUNCHED("k_backproject_combine");
+}
+
+static int strip_key(int strip) { return strip == 8 || strip == 4 ? strip : 1; }
+static int np_key(int passes) { return passes >= 1 && passes <= 4 ? passes : 0; }
+
+// All calls of one dtype: scatter launches grouped by (passes, strip, waves), then the combines.
+template <typename T>
+static ps_status backproject_many_t(const BackCall *calls, int n, hipStream_t st) {
+    std::vector<BackItem<T>> items;
+    std::vector<BackPlan> plans;
+    std::vector<int> call_of;
+    for (int c = 0; c < n; ++c) {
+        const BackCall &bc = calls[c];
+        const ps_geometry *g = bc.g;
+        const auto &d = g->desc;
+        if (bc.mode < BP_OVERWRITE || bc.mode > BP_SNAPSHOT)
+            return fail(PS_EINVAL, "backprojector mode %d", bc.mode);
+        const BackPlan bp = back_plan(g, bc.subset);
+        const size_t need = back_workspace(g, bc.subset);
+        if (!bc.ws || bc.ws_bytes < need)
+            return fail(PS_EINVAL, "backprojector workspace: %zu bytes given, %zu needed", bc.ws_bytes, need);
+        const AngleTab<T> tab = angle_tab<T>(g);
+        BackItem<T> it{};
+        it.y = static_cast<const T *>(bc.y);
+        it.part = static_cast<T *>(bc.ws);
+        it.order = bc.subset < 0 ? tab.ord_full : tab.ord_sub + g->sub_off[bc.subset];
+        it.tab = tab;
+        it.subset = bc.subset;
+        it.nsub = d.n_subsets;
+        it.na = subset_count(g, bc.subset);
+        it.nx = d.nx;
+        it.ny = d.ny;
+        it.nz = d.nz;
+        it.nbins = d.n_bins;
+        it.strip = bp.strip;
+        it.stride = bp.stride;
+        it.s_row = bp.s_row;
+        it.s_col = bp.s_col;
+        it.groups = bp.groups;
+        it.passes = g->bp_passes;
+        it.nrow = bc.subset < 0 ? g->nrow_full : g->nrow_sub[bc.subset];
+        items.push_back(it);
+        plans.push_back(bp);
+        call_of.push_back(c);
+    }
+    // scatter: one list per kernel instance (passes, strip) and block size, kMaxItems at a time
+    std::vector<bool> done(items.size(), false);
+    for (size_t i0 = 0; i0 < items.size(); ++i0) {
+        if (done[i0]) continue;
+        const int np = np_key(items[i0].passes), sk = strip_key(items[i0].strip);
+        const int waves = plans[i0].waves;
+        ListBuilder<BackItem<T>> lb;
+        size_t lds = 0;
+        for (size_t i = i0; i < items.size(); ++i) {
+            if (done[i] || np_key(items[i].passes) != np || strip_key(items[i].strip) != sk ||
+                plans[i].waves != waves)
+                continue;
+            done[i] = true;
+            const long blocks = static_cast<long>(plans[i].s_row + plans[i].s_col) * plans[i].groups * items[i].nz;
+            if (blocks > (1L << 30)) return fail(PS_EUNSUPPORTED, "backprojector grid too large");
+            lb.add(items[i], static_cast<int>(blocks));
+            lds = std::max(lds, plans[i].lds_bytes);
+            if (lb.full()) {
+                PS_TRY(launch_bp_key<T>(np, sk, lb.wl, lb.blocks, waves, lds, st));
+                lb.clear();
+                lds = 0;
+            }
+        }
+        if (!lb.empty()) PS_TRY(launch_bp_key<T>(np, sk, lb.wl, lb.blocks, waves, lds, st));
+    }
+    // combine + epilogue
+    ListBuilder<CombineItem<T>> lb;
+    for (size_t i = 0; i < items.size(); ++i) {
+        const BackCall &bc = calls[call_of[i]];
+        CombineItem<T> ci{};
+        ci.part = items[i].part;
+        ci.out = static_cast<T *>(bc.out);
+        const UpdateArgs &u = bc.upd;
+        ci.upd.x = static_cast<T *>(u.x);
+        ci.upd.h = static_cast<const T *>(u.h);
+        ci.upd.gs = static_cast<T *>(u.gs);
+        ci.upd.vout = static_cast<T *>(u.vout);
+        ci.upd.gamma = static_cast<T>(u.gamma);
+        ci.upd.gamma_over_p = static_cast<T>(u.gamma_over_p);
+        ci.upd.nsub = static_cast<T>(u.nsub);
+        ci.upd.coin = u.coin;
+        ci.upd.plain = u.plain;
+        ci.n = static_cast<size_t>(items[i].nx) * items[i].ny * items[i].nz;
+        ci.groups = items[i].groups;
+        ci.mode = bc.mode;
+        ci.blocks = static_cast<int>(std::max<size_t>(1, std::min<size_t>((ci.n + kBlock - 1) / kBlock, 8192)));
+        lb.add(ci, ci.blocks);
+        if (lb.full()) {
+            hipLaunchKernelGGL((k_backproject_combine<T>), dim3(lb.blocks), dim3(kBlock), 0, st, lb.wl);
+            PS_LAUNCHED("k_backproject_combine");
+            lb.clear();
+        }
+    }
+    if (!lb.empty()) {
+        hipLaunchKernelGGL((k_backproject_combine<T>), dim3(lb.blocks), dim3(kBlock), 0, st, lb.wl);
+        PS_LAUNCHED("k_backproject_combine");
+    }
+    return PS_OK;
+}
+
+ps_status launch_backproject_many(const BackCall *calls, int n, hipStream_t st) {
+    std::vector<BackCall> f32, f64;
+    for (int c = 0; c < n; ++c) (calls[c].g->desc.dtype == PS_F64 ? f64 : f32).push_back(calls[c]);
+    if (!f32.empty()) PS_TRY(backproject_many_t<float>(f32.data(), static_cast<int>(f32.size()), st));
+    if (!f64.empty()) PS_TRY(backproject_many_t<double>(f64.data(), static_cast<int>(f64.size()), st));
     return PS_OK;
 }
 
 ps_status launch_backproject(const ps_geometry *g, int subset, const void *y, void *out, int mode,
                              const UpdateArgs *upd, void *ws, size_t ws_bytes, hipStream_t st) {
-    if (g->desc.dtype == PS_F64)
-        return backproject_t<double>(g, subset, static_cast<const double *>(y),
-                                     static_cast<double *>(out), mode, upd, ws, ws_bytes, st);
-    return backproject_t<float>(g, subset, static_cast<const float *>(y), static_cast<float *>(out),
-                                mode, upd, ws, ws_bytes, st);
+    BackCall c{};
+    c.g = g;
+    c.subset = subset;
+    c.y = y;
+    c.out = out;
+    c.mode = mode;
+    if (upd) c.upd = *upd;
+    c.ws = ws;
+    c.ws_bytes = ws_bytes;
+    return launch_backproject_many(&c, 1, st);
 }
 
 }  // namespace ps

@@ -42,18 +42,57 @@ constexpr int fgp_rw() { return std::is_same<T, double>::value ? 4 : 8; }
 static int fgp_rows(size_t elem) { return kFgpWaves * (elem == sizeof(double) ? 4 : 8); }
 static int fgp_max_iters(size_t elem) { return elem == sizeof(double) ? 4 : kFgpMaxIters; }
 
+// Whole-wave lane shifts through DPP (no LDS traffic): lane i receives lane i - 1 (shr) or
+// lane i + 1 (shl); the lane with no source receives 0.
+__device__ inline float lane_from_left(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, false));
+}
+__device__ inline float lane_from_right(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, false));
+}
+__device__ inline double lane_from_left(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(__double2loint(v)), 0x138, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(__double2hiint(v)), 0x138, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ inline double lane_from_right(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(__double2loint(v)), 0x130, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(__double2hiint(v)), 0x130, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// One launch of one FGP solve: `iters` inner iterations on every tile of every slice.
+template <typename T>
+struct FgpItem {
+    const T *v, *p_in, *r_in;
+    T *p_out, *r_out;
+    size_t ncomp;   // elements between the two dual components ([2][nz][ny][nx])
+    int nx, ny, iters, halo, tiles_x, tiles_y, nonneg;
+    T tau, step;
+    FgpCoef<T> cf;
+    FgpFinal<T> fin;
+};
+
 template <typename T, int RW>
-__global__ __launch_bounds__(kBlock) void k_fgp2d(
-    const T *__restrict__ v, const T *__restrict__ p_in, const T *__restrict__ r_in,
-    T *__restrict__ p_out, T *__restrict__ r_out, int nx, int ny, int iters, int halo,
-    FgpCoef<T> cf, T tau, T step, int nonneg, FgpFinal<T> fin) {
+__global__ __launch_bounds__(kBlock) void k_fgp2d(WorkList<FgpItem<T>> wl) {
     constexpr int EY = kFgpWaves * RW;
     __shared__ T xch[2][kFgpWaves][kFgpEX];   // last-row values (down) and first-row values (up)
+    int local;
+    const FgpItem<T> &it = wl.item[work_item(wl, local)];
+    const int nx = it.nx, ny = it.ny, halo = it.halo, iters = it.iters, nonneg = it.nonneg;
+    const T tau = it.tau, step = it.step;
+    const FgpFinal<T> &fin = it.fin;
+    const int tx = local % it.tiles_x, ty = (local / it.tiles_x) % it.tiles_y;
+    const int zsl = local / (it.tiles_x * it.tiles_y);   // slice (2D TV acts on each slice)
     const size_t n = static_cast<size_t>(nx) * ny;
+    const size_t zoff = static_cast<size_t>(zsl) * n;
+    const T *__restrict__ v = it.v + zoff;
+    const T *__restrict__ p_in = it.p_in + zoff;
+    const T *__restrict__ r_in = it.r_in + zoff;
     const int TX = kFgpEX - 2 * halo, TY = EY - 2 * halo;
     const int lane = threadIdx.x % kFgpEX, wave = threadIdx.x / kFgpEX;
-    const int i0 = blockIdx.y * TY - halo + wave * RW;   // image row of this wave's row 0
-    const int gj = blockIdx.x * TX - halo + lane;
+    const int i0 = ty * TY - halo + wave * RW;   // image row of this wave's row 0
+    const int gj = tx * TX - halo + lane;
     const bool col_in = gj >= 0 && gj < nx;
     const bool has_left = gj > 0 && lane > 0, has_right = gj < nx - 1 && lane < kFgpEX - 1;
 
@@ -67,15 +106,15 @@ __global__ __launch_bounds__(kBlock) void k_fgp2d(
             const size_t q = static_cast<size_t>(gi) * nx + gj;
             vv[r] = v[q];
             px[r] = p_in[q];
-            py[r] = p_in[q + n];
+            py[r] = p_in[q + it.ncomp];
             rx[r] = r_in[q];
-            ry[r] = r_in[q + n];
+            ry[r] = r_in[q + it.ncomp];
         } else {
             vv[r] = px[r] = py[r] = rx[r] = ry[r] = T(0);
         }
     }
 
-    for (int it = 0; it < iters; ++it) {
+    for (int t = 0; t < iters; ++t) {
         // z = P_C(v - tau D^T r): needs r^x of the left neighbour and r^y of the row above
         xch[0][wave][lane] = ry[RW - 1];
         __syncthreads();
@@ -83,7 +122,7 @@ __global__ __launch_bounds__(kBlock) void k_fgp2d(
 #pragma unroll
         for (int r = 0; r < RW; ++r) {
             const int gi = i0 + r;
-            const T rxl = __shfl_up(rx[r], 1);
+            const T rxl = lane_from_left(rx[r]);
             const T rx_here = (gj < nx - 1) ? rx[r] : T(0);
             const T rx_left = has_left ? rxl : T(0);
             const T ry_here = (gi < ny - 1) ? ry[r] : T(0);
@@ -96,11 +135,11 @@ __global__ __launch_bounds__(kBlock) void k_fgp2d(
         xch[1][wave][lane] = zz[0];
         __syncthreads();
         const T z_below = wave < kFgpWaves - 1 ? xch[1][wave + 1][lane] : T(0);
-        const T c = cf.c[it];
+        const T c = it.cf.c[t];
 #pragma unroll
         for (int r = 0; r < RW; ++r) {
             const int gi = i0 + r;
-            const T zr = __shfl_down(zz[r], 1);
+            const T zr = lane_from_right(zz[r]);
             const T zb = r < RW - 1 ? zz[r + 1] : z_below;
             const T dzx = has_right ? zr - zz[r] : T(0);
             const T dzy = (gi < ny - 1) ? zb - zz[r] : T(0);
@@ -128,16 +167,19 @@ __global__ __launch_bounds__(kBlock) void k_fgp2d(
 
     // write back the interior
     const bool col_int = lane >= halo && lane < halo + TX;
+    const size_t nc = it.ncomp;
     if (fin.mode == 0) {
+        T *__restrict__ p_out = it.p_out + zoff;
+        T *__restrict__ r_out = it.r_out + zoff;
 #pragma unroll
         for (int r = 0; r < RW; ++r) {
             const int ey = wave * RW + r;
             if (!in[r] || !col_int || ey < halo || ey >= halo + TY) continue;
             const size_t q = static_cast<size_t>(i0 + r) * nx + gj;
             p_out[q] = px[r];
-            p_out[q + n] = py[r];
+            p_out[q + nc] = py[r];
             r_out[q] = rx[r];
-            r_out[q + n] = ry[r];
+            r_out[q + nc] = ry[r];
         }
         return;
     }
@@ -149,7 +191,7 @@ __global__ __launch_bounds__(kBlock) void k_fgp2d(
 #pragma unroll
     for (int r = 0; r < RW; ++r) {
         const int gi = i0 + r, ey = wave * RW + r;
-        const T pxl = __shfl_up(px[r], 1);
+        const T pxl = lane_from_left(px[r]);
         if (!in[r] || !col_int || ey < halo || ey >= halo + TY) continue;
         const T ph = (gj < nx - 1) ? px[r] : T(0);
         const T pl = (gj > 0) ? pxl : T(0);
@@ -157,7 +199,7 @@ __global__ __launch_bounds__(kBlock) void k_fgp2d(
         const T qu = (gi > 0) ? (r > 0 ? py[r - 1] : py_above) : T(0);
         T zv = vv[r] - tau * ((pl - ph) + (qu - qh));
         if (nonneg && zv < T(0)) zv = T(0);
-        const size_t q = static_cast<size_t>(gi) * nx + gj;
+        const size_t q = zoff + static_cast<size_t>(gi) * nx + gj;
         if (fin.mode == 1) {
             fin.z[q] = zv;
         } else {
@@ -165,7 +207,7 @@ __global__ __launch_bounds__(kBlock) void k_fgp2d(
             if (fin.mode == 2) fin.h[q] = fin.hscale * (zv - vv[r]);
         }
         fin.dual_out[q] = px[r];
-        fin.dual_out[q + n] = py[r];
+        fin.dual_out[q + nc] = py[r];
     }
 }
 
@@ -293,43 +335,155 @@ size_t fgp_workspace(const ps_geometry *g) {
     return align_up(dn * g->elem) * 4 + align_up(n * g->elem) * 2;
 }
 
+// Inner iterations per 2D launch.  A launch recomputes a halo of T + 1 pixels around every tile,
+// so fewer iterations per launch waste less arithmetic but pay the per-launch cost (loading and
+// storing the tile state, about 4 us) more often; on this chip 8 per launch is faster at every
+// size measured (512^2: 7 launches of 15.5 us against 13 of 9.9 us at 4 per launch).  The choice
+// does not change results.
+static int fgp_iters_per_launch(const ps_geometry *g) { return fgp_max_iters(g->elem); }
+
+// A 2D FGP solve as its sequence of launches, plus the copies around them.
 template <typename T>
-static ps_status fgp_t(const ps_geometry *g, const T *v, T *dual, double tau_d, int K, int nonneg,
-                       const FgpOut &o, void *ws, size_t ws_bytes, hipStream_t st) {
+struct FgpProgram {
+    std::vector<FgpItem<T>> launches;
+    const T *pre_copy_src = nullptr;  // z aliases v: v is copied first
+    T *pre_copy_dst = nullptr;
+    T *pre_fill = nullptr;            // cold start: zero dual
+    size_t n = 0, dn = 0;
+    T *post_copy_dst = nullptr;       // final dual written to a work buffer, copied back
+    const T *post_copy_src = nullptr;
+};
+
+template <typename T>
+static ps_status fgp2d_program(const FgpCall &c, FgpProgram<T> &prog) {
+    const ps_geometry *g = c.g;
+    const auto &d = g->desc;
+    const size_t n = static_cast<size_t>(d.nx) * d.ny * d.nz;
+    const size_t dn = 2 * n;
+    const int K = c.n_inner;
+    prog.n = n;
+    prog.dn = dn;
+    FgpFinal<T> fin{};
+    fin.mode = c.out.proxskip == 0 ? 1 : (c.out.proxskip == 1 ? 2 : 3);
+    fin.z = static_cast<T *>(c.out.z);
+    fin.x = static_cast<T *>(c.out.x);
+    fin.h = static_cast<T *>(c.out.h);
+    fin.hscale = static_cast<T>(c.out.hscale);
+    unsigned char *w = static_cast<unsigned char *>(c.ws);
+    const size_t sd = align_up(dn * g->elem);
+    T *buf[4] = {reinterpret_cast<T *>(w), reinterpret_cast<T *>(w + sd),
+                 reinterpret_cast<T *>(w + 2 * sd), reinterpret_cast<T *>(w + 3 * sd)};
+    T *vcopy = reinterpret_cast<T *>(w + 4 * sd);
+    const T *v = static_cast<const T *>(c.v);
+    T *dual = static_cast<T *>(c.dual);
+
+    // z may alias v: the halo reads of v must not see finished pixels of another workgroup
+    const T *vin = v;
+    if (fin.mode == 1 && static_cast<const void *>(fin.z) == static_cast<const void *>(v)) {
+        prog.pre_copy_src = v;
+        prog.pre_copy_dst = vcopy;
+        vin = vcopy;
+    }
+    // cold start: zero dual in the workspace, final dual discarded
+    const T *dual_in = dual;
+    if (!dual) {
+        prog.pre_fill = buf[3];
+        dual_in = buf[3];
+    }
+    const T tauT = static_cast<T>(c.tau);
+    const T stepT = static_cast<T>(1.0 / (8.0 * c.tau));
+    const int tmax = fgp_iters_per_launch(g), EY = fgp_rows(g->elem);
+    const int launches = std::max(1, (K + tmax - 1) / tmax);
+    const std::vector<double> cn = momentum(K + 1);
+    int done = 0;
+    const T *in_p = dual_in, *in_r = dual_in;  // r_1 = p_0
+    for (int L = 0; L < launches; ++L) {
+        const int iters = std::min(tmax, K - done);
+        const int halo = iters + 1;
+        const int TX = kFgpEX - 2 * halo, TY = EY - 2 * halo;
+        FgpItem<T> it{};
+        it.v = vin;
+        it.p_in = in_p;
+        it.r_in = in_r;
+        it.ncomp = n;
+        it.nx = d.nx;
+        it.ny = d.ny;
+        it.iters = iters;
+        it.halo = halo;
+        it.tiles_x = (d.nx + TX - 1) / TX;
+        it.tiles_y = (d.ny + TY - 1) / TY;
+        it.nonneg = c.nonneg;
+        it.tau = tauT;
+        it.step = stepT;
+        for (int t = 0; t < iters; ++t) it.cf.c[t] = static_cast<T>(cn[done + t + 2]);
+        it.fin = fin;
+        const bool last = (L == launches - 1);
+        T *out_p = buf[2 * (L % 2)], *out_r = buf[2 * (L % 2) + 1];
+        it.p_out = out_p;
+        it.r_out = out_r;
+        if (last) {
+            // the final dual must not land in a buffer this launch still reads as halo
+            if (!dual) {
+                it.fin.dual_out = out_p;  // cold start: dual discarded
+            } else if (L == 0) {
+                it.fin.dual_out = out_p;  // single launch reading the caller's dual: copy after
+                prog.post_copy_dst = dual;
+                prog.post_copy_src = out_p;
+            } else {
+                it.fin.dual_out = dual;
+            }
+        } else {
+            it.fin.mode = 0;
+        }
+        prog.launches.push_back(it);
+        in_p = out_p;
+        in_r = out_r;
+        done += iters;
+    }
+    return PS_OK;
+}
+
+template <typename T>
+static ps_status launch_fgp2d_list(const WorkList<FgpItem<T>> &wl, int blocks, hipStream_t st) {
+    hipLaunchKernelGGL((k_fgp2d<T, fgp_rw<T>()>), dim3(blocks), dim3(kBlock), 0, st, wl);
+    PS_LAUNCHED("k_fgp2d");
+    return PS_OK;
+}
+
+// 3D (coupled slices) and tau = 0 solves run on their own.
+template <typename T>
+static ps_status fgp_single_t(const FgpCall &c, hipStream_t st) {
+    const ps_geometry *g = c.g;
     const auto &d = g->desc;
     const size_t n = static_cast<size_t>(d.nx) * d.ny * d.nz;
     const int dims = g->tv_dims;
     const size_t dn = static_cast<size_t>(dims) * n;
+    const int K = c.n_inner;
     FgpFinal<T> fin{};
-    fin.mode = o.proxskip == 0 ? 1 : (o.proxskip == 1 ? 2 : 3);
-    fin.z = static_cast<T *>(o.z);
-    fin.x = static_cast<T *>(o.x);
-    fin.h = static_cast<T *>(o.h);
-    fin.hscale = static_cast<T>(o.hscale);
-
-    if (tau_d == 0.0) {
-        hipLaunchKernelGGL((k_prox_identity<T>), dim3(grid_for(n)), dim3(kBlock), 0, st, v, n, nonneg, fin);
+    fin.mode = c.out.proxskip == 0 ? 1 : (c.out.proxskip == 1 ? 2 : 3);
+    fin.z = static_cast<T *>(c.out.z);
+    fin.x = static_cast<T *>(c.out.x);
+    fin.h = static_cast<T *>(c.out.h);
+    fin.hscale = static_cast<T>(c.out.hscale);
+    const T *v = static_cast<const T *>(c.v);
+    T *dual = static_cast<T *>(c.dual);
+    if (c.tau == 0.0) {
+        hipLaunchKernelGGL((k_prox_identity<T>), dim3(grid_for(n)), dim3(kBlock), 0, st, v, n, c.nonneg, fin);
         PS_LAUNCHED("k_prox_identity");
         return PS_OK;
     }
-    const size_t need = fgp_workspace(g);
-    if (!ws || ws_bytes < need)
-        return fail(PS_EINVAL, "TV prox workspace: %zu bytes given, %zu needed", ws_bytes, need);
-    unsigned char *w = static_cast<unsigned char *>(ws);
+    unsigned char *w = static_cast<unsigned char *>(c.ws);
     const size_t sd = align_up(dn * g->elem), sn = align_up(n * g->elem);
     T *buf[4] = {reinterpret_cast<T *>(w), reinterpret_cast<T *>(w + sd),
                  reinterpret_cast<T *>(w + 2 * sd), reinterpret_cast<T *>(w + 3 * sd)};
     T *vcopy = reinterpret_cast<T *>(w + 4 * sd);
     T *zscratch = reinterpret_cast<T *>(w + 4 * sd + sn);
-
-    // z may alias v: the halo reads of v must not see finished pixels of another workgroup
     const T *vin = v;
     if (fin.mode == 1 && static_cast<const void *>(fin.z) == static_cast<const void *>(v)) {
         hipLaunchKernelGGL((k_copy<T>), dim3(grid_for(n)), dim3(kBlock), 0, st, vcopy, v, n);
         PS_LAUNCHED("k_copy");
         vin = vcopy;
     }
-    // cold start: zero dual in the workspace, final dual discarded
     const T *dual_in = dual;
     if (!dual) {
         hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(dn)), dim3(kBlock), 0, st, buf[3], dn, T(0));
@@ -337,54 +491,9 @@ static ps_status fgp_t(const ps_geometry *g, const T *v, T *dual, double tau_d, 
         dual_in = buf[3];
     }
     const std::vector<double> cs = momentum(std::max(K, 1));
-    const T tauT = static_cast<T>(tau_d);
-    const T stepT = static_cast<T>(1.0 / (4.0 * dims * tau_d));
-
-    if (dims == 2) {
-        const int tmax = fgp_max_iters(g->elem), EY = fgp_rows(g->elem);
-        const int launches = std::max(1, (K + tmax - 1) / tmax);
-        const std::vector<double> cn = momentum(K + 1);
-        int done = 0;
-        const T *in_p = dual_in, *in_r = dual_in;  // r_1 = p_0
-        for (int L = 0; L < launches; ++L) {
-            const int iters = std::min(tmax, K - done);
-            const int halo = iters + 1;
-            const int TX = kFgpEX - 2 * halo, TY = EY - 2 * halo;
-            const dim3 grid((d.nx + TX - 1) / TX, (d.ny + TY - 1) / TY);
-            FgpCoef<T> cf{};
-            for (int t = 0; t < iters; ++t) cf.c[t] = static_cast<T>(cn[done + t + 2]);
-            const bool last = (L == launches - 1);
-            FgpFinal<T> f = fin;
-            T *out_p = buf[2 * (L % 2)], *out_r = buf[2 * (L % 2) + 1];
-            bool copy_back = false;
-            if (last) {
-                // the final dual must not land in a buffer this launch still reads as halo
-                if (!dual) {
-                    f.dual_out = out_p;  // cold start: dual discarded
-                } else if (L == 0) {
-                    f.dual_out = out_p;  // single launch reading the caller's dual: copy after
-                    copy_back = true;
-                } else {
-                    f.dual_out = dual;
-                }
-            } else {
-                f.mode = 0;
-            }
-            hipLaunchKernelGGL((k_fgp2d<T, fgp_rw<T>()>), grid, dim3(kBlock), 0, st, vin, in_p, in_r,
-                               out_p, out_r, d.nx, d.ny, iters, halo, cf, tauT, stepT, nonneg, f);
-            PS_LAUNCHED("k_fgp2d");
-            if (copy_back) {
-                hipLaunchKernelGGL((k_copy<T>), dim3(grid_for(dn)), dim3(kBlock), 0, st, dual, out_p, dn);
-                PS_LAUNCHED("k_copy");
-            }
-            in_p = out_p;
-            in_r = out_r;
-            done += iters;
-        }
-        return PS_OK;
-    }
-
-    // 3D: rotate three dual buffers p_{k-2}, p_{k-1}, p_k; buf[3] may hold the zero cold start.
+    const T tauT = static_cast<T>(c.tau);
+    const T stepT = static_cast<T>(1.0 / (4.0 * dims * c.tau));
+    // rotate three dual buffers p_{k-2}, p_{k-1}, p_k; buf[3] may hold the zero cold start
     const unsigned gr = grid_for(n);
     FgpFinal<T> mid{};
     mid.mode = 0;
@@ -392,14 +501,14 @@ static ps_status fgp_t(const ps_geometry *g, const T *v, T *dual, double tau_d, 
     T *rot[3] = {buf[0], buf[1], buf[2]};
     int next = 0;
     for (int k = 1; k <= K; ++k) {
-        const T c = static_cast<T>(cs[k]);
-        hipLaunchKernelGGL((k_fgp3d_primal<T>), dim3(gr), dim3(kBlock), 0, st, vin, pa, pb, c, d.nx,
-                           d.ny, d.nz, tauT, nonneg, zscratch, mid);
+        const T cc = static_cast<T>(cs[k]);
+        hipLaunchKernelGGL((k_fgp3d_primal<T>), dim3(gr), dim3(kBlock), 0, st, vin, pa, pb, cc, d.nx,
+                           d.ny, d.nz, tauT, c.nonneg, zscratch, mid);
         PS_LAUNCHED("k_fgp3d_primal");
         T *pn = rot[next];
         if (pn == pa || pn == pb) pn = rot[(next + 1) % 3];
         if (pn == pa || pn == pb) pn = rot[(next + 2) % 3];
-        hipLaunchKernelGGL((k_fgp3d_dual<T>), dim3(gr), dim3(kBlock), 0, st, zscratch, pa, pb, c,
+        hipLaunchKernelGGL((k_fgp3d_dual<T>), dim3(gr), dim3(kBlock), 0, st, zscratch, pa, pb, cc,
                            d.nx, d.ny, d.nz, stepT, pn);
         PS_LAUNCHED("k_fgp3d_dual");
         pb = pa;
@@ -410,7 +519,7 @@ static ps_status fgp_t(const ps_geometry *g, const T *v, T *dual, double tau_d, 
     FgpFinal<T> f = fin;
     f.dual_out = nullptr;
     hipLaunchKernelGGL((k_fgp3d_primal<T>), dim3(gr), dim3(kBlock), 0, st, vin, pa, pa, T(0), d.nx,
-                       d.ny, d.nz, tauT, nonneg, zscratch, f);
+                       d.ny, d.nz, tauT, c.nonneg, zscratch, f);
     PS_LAUNCHED("k_fgp3d_primal(final)");
     if (dual && K > 0) {
         hipLaunchKernelGGL((k_copy<T>), dim3(grid_for(dn)), dim3(kBlock), 0, st, dual, pa, dn);
@@ -419,13 +528,70 @@ static ps_status fgp_t(const ps_geometry *g, const T *v, T *dual, double tau_d, 
     return PS_OK;
 }
 
+// All calls of one dtype.  2D solves advance together: launch round r holds the r-th launch of
+// every solve that has one.
+template <typename T>
+static ps_status fgp_many_t(const FgpCall *calls, int n, hipStream_t st) {
+    std::vector<FgpProgram<T>> progs;
+    for (int i = 0; i < n; ++i) {
+        const FgpCall &c = calls[i];
+        const size_t need = fgp_workspace(c.g);
+        if (c.tau != 0.0 && (!c.ws || c.ws_bytes < need))
+            return fail(PS_EINVAL, "TV prox workspace: %zu bytes given, %zu needed", c.ws_bytes, need);
+        if (c.g->tv_dims != 2 || c.tau == 0.0) {
+            PS_TRY(fgp_single_t<T>(c, st));
+            continue;
+        }
+        progs.emplace_back();
+        PS_TRY(fgp2d_program<T>(c, progs.back()));
+    }
+    size_t rounds = 0;
+    for (const auto &p : progs) {
+        rounds = std::max(rounds, p.launches.size());
+        if (p.pre_copy_dst) {
+            hipLaunchKernelGGL((k_copy<T>), dim3(grid_for(p.n)), dim3(kBlock), 0, st, p.pre_copy_dst, p.pre_copy_src, p.n);
+            PS_LAUNCHED("k_copy");
+        }
+        if (p.pre_fill) {
+            hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(p.dn)), dim3(kBlock), 0, st, p.pre_fill, p.dn, T(0));
+            PS_LAUNCHED("k_fill");
+        }
+    }
+    for (size_t r = 0; r < rounds; ++r) {
+        ListBuilder<FgpItem<T>> lb;
+        for (const auto &p : progs) {
+            if (r >= p.launches.size()) continue;
+            const FgpItem<T> &it = p.launches[r];
+            const long blocks = static_cast<long>(it.tiles_x) * it.tiles_y * (it.ncomp / (static_cast<size_t>(it.nx) * it.ny));
+            lb.add(it, static_cast<int>(blocks));
+            if (lb.full()) {
+                PS_TRY(launch_fgp2d_list<T>(lb.wl, lb.blocks, st));
+                lb.clear();
+            }
+        }
+        if (!lb.empty()) PS_TRY(launch_fgp2d_list<T>(lb.wl, lb.blocks, st));
+    }
+    for (const auto &p : progs) {
+        if (p.post_copy_dst) {
+            hipLaunchKernelGGL((k_copy<T>), dim3(grid_for(p.dn)), dim3(kBlock), 0, st, p.post_copy_dst, p.post_copy_src, p.dn);
+            PS_LAUNCHED("k_copy");
+        }
+    }
+    return PS_OK;
+}
+
+ps_status launch_fgp_many(const FgpCall *calls, int n, hipStream_t st) {
+    std::vector<FgpCall> f32, f64;
+    for (int c = 0; c < n; ++c) (calls[c].g->desc.dtype == PS_F64 ? f64 : f32).push_back(calls[c]);
+    if (!f32.empty()) PS_TRY(fgp_many_t<float>(f32.data(), static_cast<int>(f32.size()), st));
+    if (!f64.empty()) PS_TRY(fgp_many_t<double>(f64.data(), static_cast<int>(f64.size()), st));
+    return PS_OK;
+}
+
 ps_status launch_fgp(const ps_geometry *g, const void *v, void *dual, double tau, int n_inner,
                      int nonneg, const FgpOut &out, void *ws, size_t ws_bytes, hipStream_t st) {
-    if (g->desc.dtype == PS_F64)
-        return fgp_t<double>(g, static_cast<const double *>(v), static_cast<double *>(dual), tau,
-                             n_inner, nonneg, out, ws, ws_bytes, st);
-    return fgp_t<float>(g, static_cast<const float *>(v), static_cast<float *>(dual), tau, n_inner,
-                        nonneg, out, ws, ws_bytes, st);
+    const FgpCall c{g, v, dual, tau, n_inner, nonneg, out, ws, ws_bytes};
+    return launch_fgp_many(&c, 1, st);
 }
 
 }  // namespace ps

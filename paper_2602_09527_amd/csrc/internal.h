@@ -128,11 +128,69 @@ AngleTab<T> angle_tab(const ps_geometry *g) {
 }
 
 // ---------------------------------------------------------------------------------------------
+// Work lists.  A batched launch processes up to kMaxItems independent items (one problem's
+// operator application each: its own geometry, buffers and launch plan) over a 1D grid; item i
+// owns workgroups [first[i], first[i+1]).  An item computes exactly what it computes alone, so
+// results do not depend on what else shares the launch.  The list travels in the kernel
+// arguments (no device-side descriptor memory).
+// ---------------------------------------------------------------------------------------------
+constexpr int kMaxItems = 16;
+
+template <typename Item>
+struct WorkList {
+    int count;
+    int first[kMaxItems + 1];
+    Item item[kMaxItems];
+};
+
+// Index of the item that owns this workgroup, and the workgroup's index within that item.
+template <typename Item>
+__device__ inline int work_item(const WorkList<Item> &wl, int &local) {
+    const int b = static_cast<int>(blockIdx.x);
+    int i = 0;
+#pragma unroll
+    for (int q = 1; q < kMaxItems; ++q)
+        if (q < wl.count && b >= wl.first[q]) i = q;
+    local = b - wl.first[i];
+    return i;
+}
+
+// Host side: append items, launching a kernel whenever the list is full.
+template <typename Item>
+struct ListBuilder {
+    WorkList<Item> wl{};
+    int blocks = 0;
+    void clear() {
+        wl.count = 0;
+        blocks = 0;
+        wl.first[0] = 0;
+    }
+    ListBuilder() { clear(); }
+    bool full() const { return wl.count == kMaxItems; }
+    bool empty() const { return wl.count == 0; }
+    void add(const Item &it, int nblocks) {
+        wl.item[wl.count] = it;
+        wl.first[wl.count] = blocks;
+        blocks += nblocks;
+        ++wl.count;
+        wl.first[wl.count] = blocks;
+    }
+};
+
+// ---------------------------------------------------------------------------------------------
 // Projector (project.hip).
 // ---------------------------------------------------------------------------------------------
 ProjPlan proj_plan(const ps_geometry *g, int na);
 size_t proj_workspace(const ps_geometry *g, int na);
 // y = A_sub (x - xs) [ - b_sub ]: xs and b may be null.  y is [nz][na][B].
+struct ProjCall {
+    const ps_geometry *g;
+    int subset;
+    const void *x, *xs, *b;
+    void *y, *ws;
+    size_t ws_bytes;
+};
+ps_status launch_project_many(const ProjCall *calls, int n, hipStream_t st);
 ps_status launch_project(const ps_geometry *g, int subset, const void *x, const void *xs,
                          const void *b, void *y, void *ws, size_t ws_bytes, hipStream_t st);
 
@@ -158,6 +216,17 @@ struct UpdateArgs {
 };
 BackPlan back_plan(const ps_geometry *g, int subset);
 size_t back_workspace(const ps_geometry *g, int subset);
+struct BackCall {
+    const ps_geometry *g;
+    int subset;
+    const void *y;
+    void *out;
+    int mode;
+    UpdateArgs upd;
+    void *ws;
+    size_t ws_bytes;
+};
+ps_status launch_backproject_many(const BackCall *calls, int n, hipStream_t st);
 ps_status launch_backproject(const ps_geometry *g, int subset, const void *y, void *out, int mode,
                              const UpdateArgs *upd, void *ws, size_t ws_bytes, hipStream_t st);
 
@@ -172,6 +241,17 @@ struct FgpOut {
     double hscale;  // p / gamma
     int proxskip;   // 0: z, 1: proxskip update (h written), 2: plain (x = z, h untouched)
 };
+struct FgpCall {
+    const ps_geometry *g;
+    const void *v;
+    void *dual;
+    double tau;
+    int n_inner, nonneg;
+    FgpOut out;
+    void *ws;
+    size_t ws_bytes;
+};
+ps_status launch_fgp_many(const FgpCall *calls, int n, hipStream_t st);
 ps_status launch_fgp(const ps_geometry *g, const void *v, void *dual, double tau, int n_inner,
                      int nonneg, const FgpOut &out, void *ws, size_t ws_bytes, hipStream_t st);
 

@@ -13,6 +13,7 @@
 // not depend on timing).  A per-workgroup completion counter with a device-scope fence would
 // save that launch, but on this chip such a fence writes back the XCD's L2 and costs more.
 #include <algorithm>
+#include <vector>
 
 #include "internal.h"
 
@@ -66,16 +67,35 @@ __device__ inline Vec4<T> load4(const T *p) {
     }
 }
 
+// One projector application: y = inv * A_sub (x - xs) [- b_sub], or partial sums when split.
+template <typename T>
+struct ProjItem {
+    const T *x, *xs, *b;
+    T *out, *part;
+    AngleTab<T> tab;
+    int subset, nsub, na, nx, ny, nz, nbins, n_angles;
+    int split, strip, stride, vec;
+};
+
 template <typename T, int RPT>
-__global__ __launch_bounds__(kBlock) void k_project(
-    const T *__restrict__ x, const T *__restrict__ xs, AngleTab<T> tab, int subset, int nsub,
-    int na, int nx, int ny, int nbins, int split, int strip, int stride, int vec,
-    T *__restrict__ out, const T *__restrict__ b, int n_angles, T *__restrict__ part) {
+__global__ __launch_bounds__(kBlock) void k_project(WorkList<ProjItem<T>> wl) {
     extern __shared__ unsigned char smem_raw[];
     T *lds = reinterpret_cast<T *>(smem_raw);
     constexpr bool kFixed = std::is_same<T, float>::value;
 
-    const int s = blockIdx.x, l = blockIdx.y, z = blockIdx.z;
+    int local;
+    const ProjItem<T> &it = wl.item[work_item(wl, local)];
+    const T *__restrict__ x = it.x;
+    const T *__restrict__ xs = it.xs;
+    const T *__restrict__ b = it.b;
+    T *__restrict__ out = it.out;
+    T *__restrict__ part = it.part;
+    const AngleTab<T> &tab = it.tab;
+    const int subset = it.subset, nsub = it.nsub, na = it.na, nx = it.nx, ny = it.ny;
+    const int nbins = it.nbins, n_angles = it.n_angles, split = it.split, strip = it.strip;
+    const int stride = it.stride, vec = it.vec;
+    // workgroup -> (split s, angle l, slice z), s fastest
+    const int s = local % split, l = (local / split) % na, z = local / (split * na);
     const int k = subset < 0 ? l : subset + l * nsub;
     const bool row = tab.row[k] != 0;
     const int nsteps = row ? ny : nx;
@@ -240,7 +260,7 @@ __global__ __launch_bounds__(kBlock) void k_project(
         __syncthreads();
     }
 
-    const int nz_ = gridDim.z;
+    const int nz_ = it.nz;
     const T dscale = kFixed ? T(0x1p-32f) : T(1);
     const T inv = tab.inv[k];
 #pragma unroll
@@ -260,17 +280,28 @@ __global__ __launch_bounds__(kBlock) void k_project(
 
 // y = inv_k * sum_s partial[s] (- b): fixed summation order, loads issued eight at a time.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_project_reduce(
-    const T *__restrict__ part, AngleTab<T> tab, int subset, int nsub, int na, int nz, int nbins,
-    int split, T *__restrict__ y, const T *__restrict__ b, int n_angles) {
-    const size_t total = static_cast<size_t>(nz) * na * nbins;
-    for (size_t e = blockIdx.x * static_cast<size_t>(kBlock) + threadIdx.x; e < total;
-         e += static_cast<size_t>(gridDim.x) * kBlock) {
+struct ReduceItem {
+    const T *part, *b, *inv;
+    T *y;
+    int subset, nsub, na, nz, nbins, split, n_angles, blocks;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_project_reduce(WorkList<ReduceItem<T>> wl) {
+    int local;
+    const ReduceItem<T> &it = wl.item[work_item(wl, local)];
+    const T *__restrict__ part = it.part;
+    const T *__restrict__ b = it.b;
+    T *__restrict__ y = it.y;
+    const int na = it.na, nbins = it.nbins, split = it.split;
+    const size_t total = static_cast<size_t>(it.nz) * na * nbins;
+    for (size_t e = local * static_cast<size_t>(kBlock) + threadIdx.x; e < total;
+         e += static_cast<size_t>(it.blocks) * kBlock) {
         const int u = static_cast<int>(e % nbins);
         const size_t zl = e / nbins;
         const int l = static_cast<int>(zl % na);
         const int z = static_cast<int>(zl / na);
-        const int k = subset < 0 ? l : subset + l * nsub;
+        const int k = it.subset < 0 ? l : it.subset + l * it.nsub;
         T acc = T(0);
         for (int s0 = 0; s0 < split; s0 += 8) {
             T v[8];
@@ -280,70 +311,145 @@ __global__ __launch_bounds__(kBlock) void k_project_reduce(
             for (int q = 0; q < 8; ++q)
                 if (s0 + q < split) acc += v[q];
         }
-        T val = acc * tab.inv[k];
-        if (b) val -= b[(static_cast<size_t>(z) * n_angles + k) * nbins + u];
+        T val = acc * it.inv[k];
+        if (b) val -= b[(static_cast<size_t>(z) * it.n_angles + k) * nbins + u];
         y[e] = val;
     }
 }
 
-template <typename T>
-static ps_status project_t(const ps_geometry *g, int subset, const T *x, const T *xs, const T *b,
-                           T *y, void *ws, size_t ws_bytes, hipStream_t st) {
-    const auto &d = g->desc;
-    const int na = subset_count(g, subset);
-    if (na <= 0) return PS_OK;
-    const ProjPlan p = proj_plan(g, na);
-    const AngleTab<T> tab = angle_tab<T>(g);
-    T *part = nullptr;
-    if (p.split > 1) {
-        const size_t need = proj_workspace(g, na);
-        if (!ws || ws_bytes < need)
-            return fail(PS_EINVAL, "projector workspace: %zu bytes given, %zu needed", ws_bytes, need);
-        part = static_cast<T *>(ws);
-    }
-    // 16-byte staging needs rows (and column strips) that start on 16-byte boundaries
-    const bool aligned = reinterpret_cast<uintptr_t>(x) % 16 == 0 &&
-                         (!xs || reinterpret_cast<uintptr_t>(xs) % 16 == 0);
-    const int vec = (d.nx % 4 == 0 && aligned && sizeof(T) == 4) ? 1 : 0;
-    const dim3 grid(p.split, na, d.nz);
-    switch (p.rpt) {
-#define PS_PROJ_CASE(R)                                                                         \
-    case R:                                                                                     \
-        hipLaunchKernelGGL((k_project<T, R>), grid, dim3(kBlock), p.lds_bytes, st, x, xs, tab,   \
-                           subset, d.n_subsets, na, d.nx, d.ny, d.n_bins, p.split, p.strip,      \
-                           p.stride, vec, y, b, d.n_angles, part);                               \
-        break;
-        PS_PROJ_CASE(1)
-        PS_PROJ_CASE(2)
-        PS_PROJ_CASE(3)
-        PS_PROJ_CASE(4)
-        PS_PROJ_CASE(5)
-        PS_PROJ_CASE(6)
-        PS_PROJ_CASE(7)
-        PS_PROJ_CASE(8)
-#undef PS_PROJ_CASE
-        default:
-            return fail(PS_EUNSUPPORTED, "rays per thread %d", p.rpt);
-    }
+template <typename T, int R>
+static ps_status launch_proj_list(const WorkList<ProjItem<T>> &wl, int blocks, size_t lds,
+                                  hipStream_t st) {
+    hipLaunchKernelGGL((k_project<T, R>), dim3(blocks), dim3(kBlock), lds, st, wl);
     PS_LAUNCHED("k_project");
-    if (p.split > 1) {
-        const size_t total = static_cast<size_t>(d.nz) * na * d.n_bins;
-        const unsigned blocks = static_cast<unsigned>(std::min<size_t>((total + kBlock - 1) / kBlock, 65535));
-        hipLaunchKernelGGL((k_project_reduce<T>), dim3(blocks), dim3(kBlock), 0, st, part, tab,
-                           subset, d.n_subsets, na, d.nz, d.n_bins, p.split, y, b, d.n_angles);
+    return PS_OK;
+}
+
+template <typename T>
+static ps_status launch_proj_rpt(int rpt, const WorkList<ProjItem<T>> &wl, int blocks, size_t lds,
+                                 hipStream_t st) {
+    switch (rpt) {
+        case 1: return launch_proj_list<T, 1>(wl, blocks, lds, st);
+        case 2: return launch_proj_list<T, 2>(wl, blocks, lds, st);
+        case 3: return launch_proj_list<T, 3>(wl, blocks, lds, st);
+        case 4: return launch_proj_list<T, 4>(wl, blocks, lds, st);
+        case 5: return launch_proj_list<T, 5>(wl, blocks, lds, st);
+        case 6: return launch_proj_list<T, 6>(wl, blocks, lds, st);
+        case 7: return launch_proj_list<T, 7>(wl, blocks, lds, st);
+        case 8: return launch_proj_list<T, 8>(wl, blocks, lds, st);
+        default: return fail(PS_EUNSUPPORTED, "rays per thread %d", rpt);
+    }
+}
+
+// All calls of one dtype: projector launches grouped by rays per thread, then the reductions.
+template <typename T>
+static ps_status project_many_t(const ProjCall *calls, int n, hipStream_t st) {
+    std::vector<ProjItem<T>> items;
+    std::vector<ProjPlan> plans;
+    items.reserve(n);
+    plans.reserve(n);
+    for (int c = 0; c < n; ++c) {
+        const ProjCall &pc = calls[c];
+        const ps_geometry *g = pc.g;
+        const auto &d = g->desc;
+        const int na = subset_count(g, pc.subset);
+        if (na <= 0) continue;
+        const ProjPlan p = proj_plan(g, na);
+        T *part = nullptr;
+        if (p.split > 1) {
+            const size_t need = proj_workspace(g, na);
+            if (!pc.ws || pc.ws_bytes < need)
+                return fail(PS_EINVAL, "projector workspace: %zu bytes given, %zu needed", pc.ws_bytes, need);
+            part = static_cast<T *>(pc.ws);
+        }
+        // 16-byte staging needs rows (and column strips) that start on 16-byte boundaries
+        const bool aligned = reinterpret_cast<uintptr_t>(pc.x) % 16 == 0 &&
+                             (!pc.xs || reinterpret_cast<uintptr_t>(pc.xs) % 16 == 0);
+        ProjItem<T> it{};
+        it.x = static_cast<const T *>(pc.x);
+        it.xs = static_cast<const T *>(pc.xs);
+        it.b = static_cast<const T *>(pc.b);
+        it.out = static_cast<T *>(pc.y);
+        it.part = part;
+        it.tab = angle_tab<T>(g);
+        it.subset = pc.subset;
+        it.nsub = d.n_subsets;
+        it.na = na;
+        it.nx = d.nx;
+        it.ny = d.ny;
+        it.nz = d.nz;
+        it.nbins = d.n_bins;
+        it.n_angles = d.n_angles;
+        it.split = p.split;
+        it.strip = p.strip;
+        it.stride = p.stride;
+        it.vec = (d.nx % 4 == 0 && aligned && sizeof(T) == 4) ? 1 : 0;
+        items.push_back(it);
+        plans.push_back(p);
+    }
+    // projector: one list per rays-per-thread value, flushed every kMaxItems items
+    for (int rpt = 1; rpt <= 8; ++rpt) {
+        ListBuilder<ProjItem<T>> lb;
+        size_t lds = 0;
+        for (size_t i = 0; i < items.size(); ++i) {
+            if (plans[i].rpt != rpt) continue;
+            const long blocks = static_cast<long>(plans[i].split) * items[i].na * items[i].nz;
+            if (blocks > (1L << 30)) return fail(PS_EUNSUPPORTED, "projector grid too large");
+            lb.add(items[i], static_cast<int>(blocks));
+            lds = std::max(lds, plans[i].lds_bytes);
+            if (lb.full()) {
+                PS_TRY(launch_proj_rpt<T>(rpt, lb.wl, lb.blocks, lds, st));
+                lb.clear();
+                lds = 0;
+            }
+        }
+        if (!lb.empty()) PS_TRY(launch_proj_rpt<T>(rpt, lb.wl, lb.blocks, lds, st));
+    }
+    // reductions of the split items
+    ListBuilder<ReduceItem<T>> lb;
+    for (size_t i = 0; i < items.size(); ++i) {
+        if (plans[i].split <= 1) continue;
+        const ProjItem<T> &pi = items[i];
+        ReduceItem<T> r{};
+        r.part = pi.part;
+        r.b = pi.b;
+        r.inv = pi.tab.inv;
+        r.y = pi.out;
+        r.subset = pi.subset;
+        r.nsub = pi.nsub;
+        r.na = pi.na;
+        r.nz = pi.nz;
+        r.nbins = pi.nbins;
+        r.split = pi.split;
+        r.n_angles = pi.n_angles;
+        const size_t total = static_cast<size_t>(pi.nz) * pi.na * pi.nbins;
+        r.blocks = static_cast<int>(std::min<size_t>((total + kBlock - 1) / kBlock, 65535));
+        lb.add(r, r.blocks);
+        if (lb.full()) {
+            hipLaunchKernelGGL((k_project_reduce<T>), dim3(lb.blocks), dim3(kBlock), 0, st, lb.wl);
+            PS_LAUNCHED("k_project_reduce");
+            lb.clear();
+        }
+    }
+    if (!lb.empty()) {
+        hipLaunchKernelGGL((k_project_reduce<T>), dim3(lb.blocks), dim3(kBlock), 0, st, lb.wl);
         PS_LAUNCHED("k_project_reduce");
     }
     return PS_OK;
 }
 
+ps_status launch_project_many(const ProjCall *calls, int n, hipStream_t st) {
+    std::vector<ProjCall> f32, f64;
+    for (int c = 0; c < n; ++c) (calls[c].g->desc.dtype == PS_F64 ? f64 : f32).push_back(calls[c]);
+    if (!f32.empty()) PS_TRY(project_many_t<float>(f32.data(), static_cast<int>(f32.size()), st));
+    if (!f64.empty()) PS_TRY(project_many_t<double>(f64.data(), static_cast<int>(f64.size()), st));
+    return PS_OK;
+}
+
 ps_status launch_project(const ps_geometry *g, int subset, const void *x, const void *xs,
                          const void *b, void *y, void *ws, size_t ws_bytes, hipStream_t st) {
-    if (g->desc.dtype == PS_F64)
-        return project_t<double>(g, subset, static_cast<const double *>(x),
-                                 static_cast<const double *>(xs), static_cast<const double *>(b),
-                                 static_cast<double *>(y), ws, ws_bytes, st);
-    return project_t<float>(g, subset, static_cast<const float *>(x), static_cast<const float *>(xs),
-                            static_cast<const float *>(b), static_cast<float *>(y), ws, ws_bytes, st);
+    const ProjCall c{g, subset, x, xs, b, y, ws, ws_bytes};
+    return launch_project_many(&c, 1, st);
 }
 
 }  // namespace ps

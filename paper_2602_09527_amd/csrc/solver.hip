@@ -23,13 +23,25 @@ constexpr int kNormBlocks = 1024;
 
 // Partial sums of ||x - xs||^2 and ||x||^2 (FP64) per block; optionally xs = x afterwards.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_snapshot(const T *__restrict__ x, T *__restrict__ xs,
-                                                     size_t n, int do_norm, int do_copy,
-                                                     double *__restrict__ part) {
+struct SnapItem {
+    const T *x;
+    T *xs;
+    double *part;
+    size_t n;
+    int do_norm, do_copy, blocks;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_snapshot(WorkList<SnapItem<T>> wl) {
     __shared__ double sd[kBlock], sx[kBlock];
+    int local;
+    const SnapItem<T> &it = wl.item[work_item(wl, local)];
+    const T *__restrict__ x = it.x;
+    T *__restrict__ xs = it.xs;
+    const int do_norm = it.do_norm, do_copy = it.do_copy;
     double dd = 0.0, xx = 0.0;
-    for (size_t e = blockIdx.x * static_cast<size_t>(kBlock) + threadIdx.x; e < n;
-         e += static_cast<size_t>(gridDim.x) * kBlock) {
+    for (size_t e = local * static_cast<size_t>(kBlock) + threadIdx.x; e < it.n;
+         e += static_cast<size_t>(it.blocks) * kBlock) {
         const T xv = x[e];
         if (do_norm) {
             const double dv = static_cast<double>(xv) - static_cast<double>(xs[e]);
@@ -50,19 +62,26 @@ __global__ __launch_bounds__(kBlock) void k_snapshot(const T *__restrict__ x, T 
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = sd[0];
-        part[2 * blockIdx.x + 1] = sx[0];
+        it.part[2 * local] = sd[0];
+        it.part[2 * local + 1] = sx[0];
     }
 }
 
-// out[0..1] = sums of the block partials, in a fixed order.
-__global__ __launch_bounds__(kBlock) void k_norm_final(const double *__restrict__ part, int nblk,
-                                                       double *__restrict__ out) {
+// out[0..1] = sums of the block partials, in a fixed order (one workgroup per item).
+struct NormItem {
+    const double *part;
+    double *out;
+    int nblk;
+};
+
+__global__ __launch_bounds__(kBlock) void k_norm_final(WorkList<NormItem> wl) {
     __shared__ double sd[kBlock], sx[kBlock];
+    int local;
+    const NormItem &it = wl.item[work_item(wl, local)];
     double dd = 0.0, xx = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += kBlock) {
-        dd += part[2 * b];
-        xx += part[2 * b + 1];
+    for (int b = threadIdx.x; b < it.nblk; b += kBlock) {
+        dd += it.part[2 * b];
+        xx += it.part[2 * b + 1];
     }
     sd[threadIdx.x] = dd;
     sx[threadIdx.x] = xx;
@@ -75,8 +94,8 @@ __global__ __launch_bounds__(kBlock) void k_norm_final(const double *__restrict_
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        out[0] = sd[0];
-        out[1] = sx[0];
+        it.out[0] = sd[0];
+        it.out[1] = sx[0];
     }
 }
 
@@ -147,111 +166,188 @@ struct ps_solver {
     double last_rel;
     bool converged, cancelled, nonfinite;
     hipStream_t stream;
-    std::vector<int32_t> sub;
+    std::vector<int32_t> sub;   // i_k and theta_k of the current epoch
     std::vector<uint8_t> coin;
     std::vector<double> stats_host;
+    // tolerance runs: the epoch-end norms travel to pinned host memory behind an event
+    bool pending;
+    hipEvent_t ev;
+    double *pinned;
 };
 
 namespace ps {
 
-template <typename T>
-static ps_status snapshot_norms(ps_solver *s, int do_norm, int do_copy, hipStream_t st) {
-    const auto &d = s->g->desc;
-    const size_t n = static_cast<size_t>(d.nx) * d.ny * d.nz;
-    const int nb = norm_blocks(n);
-    double *part = reinterpret_cast<double *>(s->ws + s->L.npart);
-    hipLaunchKernelGGL((k_snapshot<T>), dim3(nb), dim3(kBlock), 0, st, static_cast<const T *>(s->x),
-                       reinterpret_cast<T *>(s->ws + s->L.xs), n, do_norm, do_copy, part);
-    PS_LAUNCHED("k_snapshot");
-    if (do_norm) {
-        double *out = reinterpret_cast<double *>(s->ws + s->L.stats) + 2 * s->epochs_done;
-        hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(kBlock), 0, st, part, nb, out);
-        PS_LAUNCHED("k_norm_final");
-    }
-    return PS_OK;
-}
-
-template <typename T>
-static ps_status run_epoch(ps_solver *s, hipStream_t st) {
-    const ps_geometry *g = s->g;
-    const auto &d = g->desc;
-    const auto &P = s->prm;
-    const int N = d.n_subsets;
-    unsigned char *w = s->ws;
-    s->sub.resize(N);
-    s->coin.resize(N);
-    draw_sequences(P.seed, s->k, N, N, P.p, s->sub.data(), s->coin.data());
-
-    UpdateArgs up{};
-    up.x = s->x;
-    up.h = s->h;
-    up.gs = w + s->L.gs;
-    up.vout = w + s->L.v;
-    up.gamma = P.gamma;
-    up.gamma_over_p = P.gamma / P.p;
-    up.nsub = static_cast<double>(N);
-    up.plain = P.plain_prox_svrg;
-
-    FgpOut fo{};
-    fo.x = s->x;
-    fo.h = s->h;
-    fo.hscale = P.p / P.gamma;
-    fo.proxskip = P.plain_prox_svrg ? 2 : 1;
-    const double tau = P.plain_prox_svrg ? P.gamma * P.alpha : P.gamma * P.alpha / P.p;
-
-    PS_TRY(snapshot_norms<T>(s, 0, 1, st));  // xs = x
-    for (int t = 0; t < N; ++t) {
-        const int i = s->sub[t];
-        const bool prox = P.plain_prox_svrg || s->coin[t];
-        up.coin = s->coin[t];
-        if (t == 0) {
-            // r = A xs - b over all angles, then gs = A^T r fused with the step (G = gs)
-            PS_TRY(launch_project(g, -1, w + s->L.xs, nullptr, s->b, w + s->L.sino, w + s->L.pws,
-                                  s->L.pws_bytes, st));
-            PS_TRY(launch_backproject(g, -1, w + s->L.sino, nullptr, BP_SNAPSHOT, &up, w + s->L.bws,
-                                      s->L.bws_bytes, st));
-        } else {
-            PS_TRY(launch_project(g, i, s->x, w + s->L.xs, nullptr, w + s->L.sino, w + s->L.pws,
-                                  s->L.pws_bytes, st));
-            PS_TRY(launch_backproject(g, i, w + s->L.sino, nullptr, BP_SVRG, &up, w + s->L.bws,
-                                      s->L.bws_bytes, st));
-        }
-        if (prox) {
-            PS_TRY(launch_fgp(g, w + s->L.v, s->dual, tau, P.fgp_inner, P.nonneg, fo, w + s->L.fws,
-                              s->L.fws_bytes, st));
-            s->prox_calls++;
-        }
-    }
-    s->k += N;
-    PS_TRY(snapshot_norms<T>(s, 1, 0, st));  // ||x_e - x_{e-1}||, ||x_e||
-    s->epochs_done++;
-    return PS_OK;
+// Record an epoch's norms (dd = ||x_e - x_{e-1}||^2, xx = ||x_e||^2) on the host.
+static void take_norms(ps_solver *s, int e, double dd, double xx) {
+    if (!std::isfinite(dd) || !std::isfinite(xx)) s->nonfinite = true;
+    s->last_rel = xx > 0.0 ? std::sqrt(dd) / std::sqrt(xx) : (dd > 0.0 ? INFINITY : 0.0);
+    if (s->prm.tol_rel_change > 0.0 && s->last_rel < s->prm.tol_rel_change) s->converged = true;
+    if (s->stats_host.size() < 2 * static_cast<size_t>(e + 1)) s->stats_host.resize(2 * static_cast<size_t>(e + 1));
+    s->stats_host[2 * e] = dd;
+    s->stats_host[2 * e + 1] = xx;
+    s->epochs_read = std::max(s->epochs_read, e + 1);
 }
 
 // Read back the norms of the epochs queued since the last read; updates last_rel/converged.
 static ps_status read_stats(ps_solver *s) {
-    if (s->epochs_read >= s->epochs_done) return PS_OK;
+    if (s->pending) {
+        PS_HIP(hipEventSynchronize(s->ev));
+        take_norms(s, s->epochs_done - 1, s->pinned[0], s->pinned[1]);
+        s->pending = false;
+    }
+    if (s->epochs_read >= s->epochs_done) {
+        if (s->nonfinite) return fail(PS_ENONFINITE, "non-finite iterate at an epoch end");
+        return PS_OK;
+    }
     PS_HIP(hipStreamSynchronize(s->stream));
     const int e0 = s->epochs_read, cnt = s->epochs_done - e0;
-    s->stats_host.resize(2 * static_cast<size_t>(s->epochs_done));
-    PS_HIP(hipMemcpy(s->stats_host.data() + 2 * e0,
-                     reinterpret_cast<double *>(s->ws + s->L.stats) + 2 * e0,
+    std::vector<double> buf(2 * static_cast<size_t>(cnt));
+    PS_HIP(hipMemcpy(buf.data(), reinterpret_cast<double *>(s->ws + s->L.stats) + 2 * e0,
                      sizeof(double) * 2 * cnt, hipMemcpyDeviceToHost));
-    for (int e = e0; e < s->epochs_done; ++e) {
-        const double dd = s->stats_host[2 * e], xx = s->stats_host[2 * e + 1];
-        if (!std::isfinite(dd) || !std::isfinite(xx)) s->nonfinite = true;
-        s->last_rel = xx > 0.0 ? std::sqrt(dd) / std::sqrt(xx) : (dd > 0.0 ? INFINITY : 0.0);
-        if (s->prm.tol_rel_change > 0.0 && s->last_rel < s->prm.tol_rel_change) {
-            s->converged = true;
-        }
-    }
-    s->epochs_read = s->epochs_done;
+    for (int e = 0; e < cnt; ++e) take_norms(s, e0 + e, buf[2 * e], buf[2 * e + 1]);
     if (s->nonfinite) return fail(PS_ENONFINITE, "non-finite iterate at an epoch end");
     return PS_OK;
 }
 
 static bool active(const ps_solver *s) {
     return !s->cancelled && !s->converged && !s->nonfinite && s->epochs_done < s->prm.n_epochs;
+}
+
+template <typename T>
+static ps_status launch_snapshots(const std::vector<SnapItem<T>> &items, hipStream_t st) {
+    ListBuilder<SnapItem<T>> lb;
+    for (const auto &it : items) {
+        lb.add(it, it.blocks);
+        if (lb.full()) {
+            hipLaunchKernelGGL((k_snapshot<T>), dim3(lb.blocks), dim3(kBlock), 0, st, lb.wl);
+            PS_LAUNCHED("k_snapshot");
+            lb.clear();
+        }
+    }
+    if (!lb.empty()) {
+        hipLaunchKernelGGL((k_snapshot<T>), dim3(lb.blocks), dim3(kBlock), 0, st, lb.wl);
+        PS_LAUNCHED("k_snapshot");
+    }
+    return PS_OK;
+}
+
+// xs = x (do_norm = 0) or the epoch-end norms (do_norm = 1) of every handle in `hs`.
+static ps_status snapshot_many(const std::vector<ps_solver *> &hs, int do_norm, hipStream_t st) {
+    std::vector<SnapItem<float>> f32;
+    std::vector<SnapItem<double>> f64;
+    ListBuilder<NormItem> nb;
+    std::vector<WorkList<NormItem>> norm_lists;
+    std::vector<int> norm_blocks_of;
+    for (ps_solver *s : hs) {
+        const auto &d = s->g->desc;
+        const size_t n = static_cast<size_t>(d.nx) * d.ny * d.nz;
+        const int nbk = norm_blocks(n);
+        double *part = reinterpret_cast<double *>(s->ws + s->L.npart);
+        if (d.dtype == PS_F64) {
+            f64.push_back(SnapItem<double>{static_cast<const double *>(s->x),
+                                           reinterpret_cast<double *>(s->ws + s->L.xs), part, n,
+                                           do_norm, 1 - do_norm, nbk});
+        } else {
+            f32.push_back(SnapItem<float>{static_cast<const float *>(s->x),
+                                          reinterpret_cast<float *>(s->ws + s->L.xs), part, n,
+                                          do_norm, 1 - do_norm, nbk});
+        }
+    }
+    if (!f32.empty()) PS_TRY(launch_snapshots<float>(f32, st));
+    if (!f64.empty()) PS_TRY(launch_snapshots<double>(f64, st));
+    if (!do_norm) return PS_OK;
+    for (ps_solver *s : hs) {
+        const auto &d = s->g->desc;
+        const size_t n = static_cast<size_t>(d.nx) * d.ny * d.nz;
+        NormItem ni{reinterpret_cast<const double *>(s->ws + s->L.npart),
+                    reinterpret_cast<double *>(s->ws + s->L.stats) + 2 * s->epochs_done, norm_blocks(n)};
+        nb.add(ni, 1);
+        if (nb.full()) {
+            hipLaunchKernelGGL(k_norm_final, dim3(nb.blocks), dim3(kBlock), 0, st, nb.wl);
+            PS_LAUNCHED("k_norm_final");
+            nb.clear();
+        }
+    }
+    if (!nb.empty()) {
+        hipLaunchKernelGGL(k_norm_final, dim3(nb.blocks), dim3(kBlock), 0, st, nb.wl);
+        PS_LAUNCHED("k_norm_final");
+    }
+    return PS_OK;
+}
+
+// One iteration of every handle in `hs`, each stage one batched launch (per kernel variant):
+//   snapshot copies (handles at an epoch start) -> projections -> backprojections with the
+//   fused SVRG/ProxSkip step -> FGP prox (handles whose coin is heads) -> epoch-end norms.
+// Every handle computes exactly what it computes alone.
+static ps_status run_step(const std::vector<ps_solver *> &hs, hipStream_t st) {
+    std::vector<ps_solver *> starting, ending;
+    std::vector<ProjCall> pc;
+    std::vector<BackCall> bc;
+    std::vector<FgpCall> fc;
+    pc.reserve(hs.size());
+    bc.reserve(hs.size());
+    for (ps_solver *s : hs) {
+        const ps_geometry *g = s->g;
+        const auto &P = s->prm;
+        const int N = g->desc.n_subsets;
+        const int t = static_cast<int>(s->k % N);
+        unsigned char *w = s->ws;
+        if (t == 0) {
+            s->sub.resize(N);
+            s->coin.resize(N);
+            draw_sequences(P.seed, s->k, N, N, P.p, s->sub.data(), s->coin.data());
+            starting.push_back(s);
+        }
+        const int i = s->sub[t];
+        const bool prox = P.plain_prox_svrg || s->coin[t];
+        UpdateArgs up{};
+        up.x = s->x;
+        up.h = s->h;
+        up.gs = w + s->L.gs;
+        up.vout = w + s->L.v;
+        up.gamma = P.gamma;
+        up.gamma_over_p = P.gamma / P.p;
+        up.nsub = static_cast<double>(N);
+        up.plain = P.plain_prox_svrg;
+        up.coin = s->coin[t];
+        if (t == 0) {
+            // r = A xs - b over all angles, then gs = A^T r fused with the step (G = gs)
+            pc.push_back(ProjCall{g, -1, w + s->L.xs, nullptr, s->b, w + s->L.sino, w + s->L.pws, s->L.pws_bytes});
+            bc.push_back(BackCall{g, -1, w + s->L.sino, nullptr, BP_SNAPSHOT, up, w + s->L.bws, s->L.bws_bytes});
+        } else {
+            pc.push_back(ProjCall{g, i, s->x, w + s->L.xs, nullptr, w + s->L.sino, w + s->L.pws, s->L.pws_bytes});
+            bc.push_back(BackCall{g, i, w + s->L.sino, nullptr, BP_SVRG, up, w + s->L.bws, s->L.bws_bytes});
+        }
+        if (prox) {
+            FgpOut fo{};
+            fo.x = s->x;
+            fo.h = s->h;
+            fo.hscale = P.p / P.gamma;
+            fo.proxskip = P.plain_prox_svrg ? 2 : 1;
+            const double tau = P.plain_prox_svrg ? P.gamma * P.alpha : P.gamma * P.alpha / P.p;
+            fc.push_back(FgpCall{g, w + s->L.v, s->dual, tau, P.fgp_inner, P.nonneg, fo, w + s->L.fws, s->L.fws_bytes});
+            s->prox_calls++;
+        }
+        s->k++;
+        if (s->k % N == 0) ending.push_back(s);
+    }
+    if (!starting.empty()) PS_TRY(snapshot_many(starting, 0, st));   // xs = x
+    PS_TRY(launch_project_many(pc.data(), static_cast<int>(pc.size()), st));
+    PS_TRY(launch_backproject_many(bc.data(), static_cast<int>(bc.size()), st));
+    if (!fc.empty()) PS_TRY(launch_fgp_many(fc.data(), static_cast<int>(fc.size()), st));
+    if (!ending.empty()) {
+        PS_TRY(snapshot_many(ending, 1, st));  // ||x_e - x_{e-1}||, ||x_e||
+        for (ps_solver *s : ending) {
+            if (s->prm.tol_rel_change > 0.0) {
+                const double *src = reinterpret_cast<const double *>(s->ws + s->L.stats) + 2 * s->epochs_done;
+                PS_HIP(hipMemcpyAsync(s->pinned, src, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+                PS_HIP(hipEventRecord(s->ev, st));
+                s->pending = true;
+            }
+            s->epochs_done++;
+        }
+    }
+    return PS_OK;
 }
 
 }  // namespace ps
@@ -293,6 +389,18 @@ extern "C" ps_status solver_init(const ps_geometry *g, const void *b, void *x, v
     s->last_rel = 0.0;
     s->converged = s->cancelled = s->nonfinite = false;
     s->stream = nullptr;
+    s->pending = false;
+    s->ev = nullptr;
+    s->pinned = nullptr;
+    if (prm->tol_rel_change > 0.0) {
+        // pinned host memory (no device allocation) for the per-epoch tolerance checks
+        if (hipHostMalloc(reinterpret_cast<void **>(&s->pinned), 2 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+            hipEventCreateWithFlags(&s->ev, hipEventDisableTiming) != hipSuccess) {
+            if (s->pinned) (void)hipHostFree(s->pinned);
+            delete s;
+            return fail(PS_EHIP, "could not create the tolerance-check event or host buffer");
+        }
+    }
     *out = s;
     return PS_OK;
 }
@@ -306,28 +414,54 @@ extern "C" ps_status solver_epochs(ps_solver *const *handles, int32_t n_handles,
     for (int i = 0; i < n_handles; ++i) {
         if (!handles[i]) return fail(PS_EINVAL, "handle %d is null", i);
         if (handles[i]->cancelled) return fail(PS_ECANCELLED, "handle %d was cancelled", i);
+        for (int j = 0; j < i; ++j)
+            if (handles[j] == handles[i]) return fail(PS_EINVAL, "handle %d appears twice", i);
     }
-    for (int e = 0; e < n_epochs; ++e) {
-        bool any = false;
+    std::vector<int> target(n_handles);
+    for (int i = 0; i < n_handles; ++i) {
+        ps_solver *s = handles[i];
+        // a tolerance check left over from an earlier call is settled first
+        if (s->pending) {
+            PS_HIP(hipEventSynchronize(s->ev));
+            take_norms(s, s->epochs_done - 1, s->pinned[0], s->pinned[1]);
+            s->pending = false;
+        }
+        s->stream = st;
+        target[i] = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(s->epochs_done) + n_epochs,
+                                                       s->prm.n_epochs));
+    }
+    // Lockstep: every ready handle advances one iteration per step.  A handle with a tolerance
+    // waits at its epoch end until its norms have reached the host; the others keep going.
+    std::vector<ps_solver *> ready;
+    bool nonfinite = false;
+    for (;;) {
+        ready.clear();
+        ps_solver *waiting = nullptr;
         for (int i = 0; i < n_handles; ++i) {
             ps_solver *s = handles[i];
-            if (!active(s)) continue;
-            s->stream = st;
-            any = true;
-            if (s->g->desc.dtype == PS_F64)
-                PS_TRY(run_epoch<double>(s, st));
-            else
-                PS_TRY(run_epoch<float>(s, st));
+            if (s->pending) {
+                const hipError_t q = hipEventQuery(s->ev);
+                if (q == hipSuccess) {
+                    take_norms(s, s->epochs_done - 1, s->pinned[0], s->pinned[1]);
+                    s->pending = false;
+                    if (s->nonfinite) nonfinite = true;
+                } else if (q != hipErrorNotReady) {
+                    return fail(PS_EHIP, "hipEventQuery failed: %s", hipGetErrorString(q));
+                } else {
+                    if (!waiting) waiting = s;
+                    continue;
+                }
+            }
+            if (active(s) && s->epochs_done < target[i]) ready.push_back(s);
         }
-        if (!any) break;
-        bool need_read = false;
-        for (int i = 0; i < n_handles; ++i)
-            if (handles[i]->prm.tol_rel_change > 0.0 && handles[i]->epochs_read < handles[i]->epochs_done)
-                need_read = true;
-        if (need_read) {
-            for (int i = 0; i < n_handles; ++i) PS_TRY(read_stats(handles[i]));
+        if (ready.empty()) {
+            if (!waiting) break;
+            PS_HIP(hipEventSynchronize(waiting->ev));
+            continue;
         }
+        PS_TRY(run_step(ready, st));
     }
+    if (nonfinite) return fail(PS_ENONFINITE, "non-finite iterate at an epoch end");
     return PS_OK;
 }
 
@@ -351,7 +485,15 @@ extern "C" ps_status solver_cancel(ps_solver *s) {
     return PS_OK;
 }
 
-extern "C" void solver_free(ps_solver *s) { delete s; }
+extern "C" void solver_free(ps_solver *s) {
+    if (!s) return;
+    if (s->ev) {
+        (void)hipEventSynchronize(s->ev);
+        (void)hipEventDestroy(s->ev);
+    }
+    if (s->pinned) (void)hipHostFree(s->pinned);
+    delete s;
+}
 
 extern "C" ps_status proxskip_svrg_run(const ps_geometry *g, const void *b, void *x, void *h,
                                        void *dual, const ps_solver_params *prm,
