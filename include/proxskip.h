@@ -184,6 +184,16 @@ PS_API ps_status solver_init(const ps_geometry *geom, const void *b, void *x, vo
                       ps_solver **out);
 PS_API ps_status solver_epochs(ps_solver *const *handles, int32_t n_handles, int32_t n_epochs,
                         void *stream);
+/* solver_steps: the same lockstep, bounded by steps instead of epochs: every handle that can
+ * still advance (epoch budget not spent, tolerance not met, not cancelled) does at most n_steps
+ * iterations, crossing epoch ends as it goes.  A serving loop calls it in rounds and admits new
+ * handles between rounds.  Returns with every tolerance check settled. */
+PS_API ps_status solver_steps(ps_solver *const *handles, int32_t n_handles, int32_t n_steps,
+                       void *stream);
+/* 1 when the handle will not advance any further (converged, budget spent, cancelled or
+ * non-finite) and nothing of it is pending on the host side, 0 otherwise, -1 for NULL.  Does not
+ * synchronise. */
+PS_API int32_t solver_done(const ps_solver *handle);
 PS_API ps_status solver_query(ps_solver *handle, ps_solver_stats *stats_out);
 PS_API ps_status solver_cancel(ps_solver *handle);
 PS_API void solver_free(ps_solver *handle);

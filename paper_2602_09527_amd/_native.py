@@ -23,8 +23,8 @@ EXPORTS = (
     "project_workspace_bytes", "project_subset", "backproject_workspace_bytes",
     "backproject_subset", "tv_prox_workspace_bytes",
     "tv_prox_fgp", "proxskip_workspace_bytes", "proxskip_svrg_run", "solver_init",
-    "solver_epochs", "solver_query", "solver_cancel", "solver_free", "sample_sequences",
-    "last_error_message",
+    "solver_epochs", "solver_steps", "solver_done", "solver_query", "solver_cancel",
+    "solver_free", "sample_sequences", "last_error_message",
 )
 
 
@@ -90,6 +90,8 @@ def load():
                                    C.POINTER(SolverStats), vp, sz, vp]),
         "solver_init": (st, [vp, vp, vp, vp, vp, C.POINTER(SolverParams), vp, sz, C.POINTER(vp)]),
         "solver_epochs": (st, [C.POINTER(vp), i32, i32, vp]),
+        "solver_steps": (st, [C.POINTER(vp), i32, i32, vp]),
+        "solver_done": (i32, [vp]),
         "solver_query": (st, [vp, C.POINTER(SolverStats)]),
         "solver_cancel": (st, [vp]),
         "solver_free": (None, [vp]),

@@ -238,6 +238,10 @@ class Solver:
     def epochs(self, n: int, stream=None):
         run_epochs([self], n, stream)
 
+    def done(self) -> bool:
+        """True once the handle will not advance any further (no synchronisation)."""
+        return self.g.lib.solver_done(self.handle) == 1
+
     def query(self) -> dict:
         st = nat.SolverStats()
         nat.check(self.g.lib.solver_query(self.handle, C.byref(st)), "solver_query")
@@ -259,13 +263,24 @@ class Solver:
 
 
 def run_epochs(solvers, n_epochs: int, stream=None):
-    """Queue ``n_epochs`` more epochs of every solver, interleaved epoch by epoch."""
+    """Run ``n_epochs`` more epochs of every solver, batched in lockstep (one launch per stage
+    over all solvers); each solver's result is bit for bit its result alone."""
     if not solvers:
         return
     arr = (C.c_void_p * len(solvers))(*[s.handle for s in solvers])
     dev = solvers[0].g.device
     st = C.c_void_p(stream.cuda_stream) if stream is not None else _stream(dev)
     nat.check(solvers[0].g.lib.solver_epochs(arr, len(solvers), int(n_epochs), st), "solver_epochs")
+
+
+def run_steps(solvers, n_steps: int, stream=None):
+    """Advance every solver by up to ``n_steps`` iterations in lockstep (batched launches)."""
+    if not solvers:
+        return
+    arr = (C.c_void_p * len(solvers))(*[s.handle for s in solvers])
+    dev = solvers[0].g.device
+    st = C.c_void_p(stream.cuda_stream) if stream is not None else _stream(dev)
+    nat.check(solvers[0].g.lib.solver_steps(arr, len(solvers), int(n_steps), st), "solver_steps")
 
 
 def sample_sequences(seed: int, k0: int, count: int, n_subsets: int, p: float):

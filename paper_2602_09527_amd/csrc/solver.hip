@@ -11,6 +11,7 @@
 //               then FGP gives x = prox(v) and h = h + (p/gamma)(x - xh) = (p/gamma)(x - v).
 //   epoch end   ||x - xs||^2 and ||x||^2 (fixed-order two-level reduction in FP64).
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <new>
 #include <vector>
@@ -405,35 +406,16 @@ extern "C" ps_status solver_init(const ps_geometry *g, const void *b, void *x, v
     return PS_OK;
 }
 
-extern "C" ps_status solver_epochs(ps_solver *const *handles, int32_t n_handles, int32_t n_epochs,
-                                   void *stream) {
-    clear_error();
-    if (n_handles < 0 || n_epochs < 0 || (n_handles > 0 && !handles))
-        return fail(PS_EINVAL, "bad handle list or epoch count");
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    for (int i = 0; i < n_handles; ++i) {
-        if (!handles[i]) return fail(PS_EINVAL, "handle %d is null", i);
-        if (handles[i]->cancelled) return fail(PS_ECANCELLED, "handle %d was cancelled", i);
-        for (int j = 0; j < i; ++j)
-            if (handles[j] == handles[i]) return fail(PS_EINVAL, "handle %d appears twice", i);
-    }
-    std::vector<int> target(n_handles);
-    for (int i = 0; i < n_handles; ++i) {
-        ps_solver *s = handles[i];
-        // a tolerance check left over from an earlier call is settled first
-        if (s->pending) {
-            PS_HIP(hipEventSynchronize(s->ev));
-            take_norms(s, s->epochs_done - 1, s->pinned[0], s->pinned[1]);
-            s->pending = false;
-        }
-        s->stream = st;
-        target[i] = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(s->epochs_done) + n_epochs,
-                                                       s->prm.n_epochs));
-    }
-    // Lockstep: every ready handle advances one iteration per step.  A handle with a tolerance
-    // waits at its epoch end until its norms have reached the host; the others keep going.
+namespace ps {
+
+// Lockstep driver shared by solver_epochs and solver_steps.  Handle i runs until it has done
+// target[i] epochs (or met its tolerance or budget), for at most max_steps steps.  On return
+// no tolerance check is left pending.
+static ps_status lockstep(ps_solver *const *handles, int n_handles, const std::vector<int> &target,
+                          int64_t max_steps, hipStream_t st) {
     std::vector<ps_solver *> ready;
     bool nonfinite = false;
+    int64_t steps = 0;
     for (;;) {
         ready.clear();
         ps_solver *waiting = nullptr;
@@ -454,15 +436,68 @@ extern "C" ps_status solver_epochs(ps_solver *const *handles, int32_t n_handles,
             }
             if (active(s) && s->epochs_done < target[i]) ready.push_back(s);
         }
-        if (ready.empty()) {
+        if (ready.empty() || steps >= max_steps) {
             if (!waiting) break;
             PS_HIP(hipEventSynchronize(waiting->ev));
             continue;
         }
         PS_TRY(run_step(ready, st));
+        ++steps;
     }
     if (nonfinite) return fail(PS_ENONFINITE, "non-finite iterate at an epoch end");
     return PS_OK;
+}
+
+static ps_status begin_call(ps_solver *const *handles, int32_t n_handles, hipStream_t st) {
+    if (n_handles < 0 || (n_handles > 0 && !handles)) return fail(PS_EINVAL, "bad handle list");
+    for (int i = 0; i < n_handles; ++i) {
+        if (!handles[i]) return fail(PS_EINVAL, "handle %d is null", i);
+        if (handles[i]->cancelled) return fail(PS_ECANCELLED, "handle %d was cancelled", i);
+        for (int j = 0; j < i; ++j)
+            if (handles[j] == handles[i]) return fail(PS_EINVAL, "handle %d appears twice", i);
+    }
+    for (int i = 0; i < n_handles; ++i) {
+        ps_solver *s = handles[i];
+        // a tolerance check left over from an earlier call is settled first
+        if (s->pending) {
+            PS_HIP(hipEventSynchronize(s->ev));
+            take_norms(s, s->epochs_done - 1, s->pinned[0], s->pinned[1]);
+            s->pending = false;
+        }
+        s->stream = st;
+    }
+    return PS_OK;
+}
+
+}  // namespace ps
+
+extern "C" ps_status solver_epochs(ps_solver *const *handles, int32_t n_handles, int32_t n_epochs,
+                                   void *stream) {
+    clear_error();
+    if (n_epochs < 0) return fail(PS_EINVAL, "n_epochs must be >= 0");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    PS_TRY(begin_call(handles, n_handles, st));
+    std::vector<int> target(n_handles);
+    for (int i = 0; i < n_handles; ++i)
+        target[i] = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(handles[i]->epochs_done) + n_epochs,
+                                                       handles[i]->prm.n_epochs));
+    return lockstep(handles, n_handles, target, INT64_MAX, st);
+}
+
+extern "C" ps_status solver_steps(ps_solver *const *handles, int32_t n_handles, int32_t n_steps,
+                                  void *stream) {
+    clear_error();
+    if (n_steps < 0) return fail(PS_EINVAL, "n_steps must be >= 0");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    PS_TRY(begin_call(handles, n_handles, st));
+    std::vector<int> target(n_handles);
+    for (int i = 0; i < n_handles; ++i) target[i] = handles[i]->prm.n_epochs;
+    return lockstep(handles, n_handles, target, n_steps, st);
+}
+
+extern "C" int32_t solver_done(const ps_solver *s) {
+    if (!s) return -1;
+    return (!s->pending && !active(s)) ? 1 : 0;
 }
 
 extern "C" ps_status solver_query(ps_solver *s, ps_solver_stats *out) {

@@ -200,6 +200,14 @@ def analytic_sinogram_torch(ellipses: list[Ellipse], nx: int, ny: int, n_angles:
     return out
 
 
+def gaussian_noise_torch(sino, seed: int, level: float = 0.01):
+    """sino + N(0, (level * max|sino|)^2) from a seeded torch generator on sino's device."""
+    import torch
+    gen = torch.Generator(device=sino.device).manual_seed(int(seed))
+    sigma = level * float(sino.abs().max())
+    return sino + sigma * torch.randn(sino.shape, generator=gen, device=sino.device, dtype=sino.dtype)
+
+
 def poisson_log_noise_torch(sino, seed: int, photons: float = 1e4, max_attenuation: float = 2.0):
     """Transmission noise of add_poisson_log_noise, drawn with a seeded torch generator on the
     sinogram's device (in place on a float copy)."""
