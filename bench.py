@@ -7,11 +7,20 @@ the SVRG snapshot with its full projection/backprojection, 20 subset projection/
 pairs with the fused SVRG/ProxSkip update, and the FGP prox on the coin flips that hit).
 
 Prints one JSON line.  Besides the timed epochs it reports:
-  roofline      the dominant kernel's algorithmic rate against the chip's peak, its duration
-                measured here with HIP events on the launching stream;
-  cpu_baseline  the FP64 oracle timed on the host cores over a short sample of the same solve;
-  parity        the GPU iterate against the oracle's after that sample;
-  sweep         epochs/s and prox calls at p in {1, 0.1, 0.02} and non-skipped ProxSVRG.
+  roofline      the dominant kernel (the backprojector) on its all-angle launch: algorithmic lane
+                operations per second against the VALU issue peak, the duration measured here
+                with HIP events on the launching stream, and the HBM bytes per launch from the
+                committed rocprofv3 counter summary (null once the kernel source has changed);
+  kernels       each operator's rate in samples/s, lane operations/s and algorithmic GB/s;
+  sweep         epochs/s and prox calls at p in {1, 0.1, 0.02} and non-skipped ProxSVRG;
+  batch         64 independent 128^2 solves batched in lockstep against one after another;
+  serving       a Poisson trace of mixed-size requests with continuous batching against one
+                request at a time (p50/p99 latency, throughput);
+  cpu_baseline  the FP64 oracle timed on the host cores over a bounded sample of the same solve;
+  parity        the GPU iterate against the oracle's after that sample.
+
+--volume times the 256 x 1024^2 volume instead; --calibrate-copy runs only a plain device copy
+of known size (for scaling the HBM byte counters).
 """
 from __future__ import annotations
 
@@ -26,7 +35,32 @@ sys.path.insert(0, ROOT)
 
 METRIC = "epochs/s to 1e-4 rel-err vs oracle; projector HBM GB/s; p50/p99 recon latency"
 HBM_PEAK_GBS = 8000.0
-FP32_VECTOR_PEAK_TFLOPS = 157.3
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 lane operations per second
+# (one non-packed FP32 or integer operation per lane per cycle; packed FP32 is not used).
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# algorithmic lane operations per interpolation sample (one ray crossing one row or column):
+#   projector:     position step, floor, weight, v1 - v0, fused multiply-add, accumulate  = 6
+#   backprojector: position step, floor, weight, w y, y - w y, two accumulations        = 7
+OPS_PROJECT = 6
+OPS_BACKPROJECT = 7
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_backproject_2d-512-a720_traffic.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2602_09527_amd", "csrc", "backproject.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the backprojector (all angles) from the committed rocprofv3 counter
+    summary, or None once the kernel source differs from the one the counters were taken on."""
+    import hashlib
+    try:
+        line = next(l for l in open(TRAFFIC_FILE) if l.startswith("traffic:"))
+    except (OSError, StopIteration):
+        return None
+    kv = dict(tok.split("=", 1) for tok in line.split()[1:])
+    with open(KERNEL_SOURCE, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != kv.get("source_sha256"):
+            return None
+    return (float(kv["fetch_kib"]) * float(kv["fetch_factor"]) +
+            float(kv["write_kib"]) * float(kv["write_factor"])) * 1024.0
 
 
 def log(*a):
@@ -41,7 +75,13 @@ def parse():
     ap.add_argument("--p", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
-    ap.add_argument("--cpu-epochs", type=int, default=3)
+    ap.add_argument("--cpu-epochs", type=int, default=12,
+                    help="epochs of the oracle sample (about 10 s on 16 host threads)")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=60)
+    ap.add_argument("--serve-cap", type=int, default=30, help="epoch cap per served request")
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrivals per second")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (for HBM counter scaling)")
     ap.add_argument("--volume", action="store_true",
@@ -126,6 +166,71 @@ def bench_volume(args):
         },
     }
     print(json.dumps(out), flush=True)
+
+
+def bench_batch(dev, log_fn, n_slices=64, epochs=10):
+    """Epochs per second of 64 independent 128^2 solves batched in lockstep, against the same
+    solves run one after another."""
+    import torch
+    from paper_2602_09527_amd import api, synth, workloads
+    w = workloads.SMALL_2D
+    g = api.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=w.n_subsets, device=dev)
+    L = stored_L(w) or api.lipschitz(g, 50)
+    bs = []
+    for j in range(n_slices):
+        prob = synth.make_problem(w.nx, w.ny, w.n_angles, w.n_bins, seed=w.seed + 10 * j,
+                                  noise=w.noise, with_phantom=False)
+        bs.append(torch.from_numpy(prob.b).to(device=dev, dtype=torch.float32))
+
+    def solvers():
+        return [api.Solver(g, b, api.SolverParams(gamma=1.0 / L, p=w.p, alpha=w.alpha,
+                                                  fgp_inner=w.fgp_inner, n_epochs=epochs + 1,
+                                                  nonneg=w.nonneg, seed=w.seed + 2 + 10 * j))
+                for j, b in enumerate(bs)]
+    sv = solvers()
+    api.run_epochs(sv, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    api.run_epochs(sv, epochs)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    sq = solvers()
+    for s in sq:
+        s.epochs(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in sq:
+        s.epochs(epochs)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    same = all(torch.equal(a.x, b.x) for a, b in zip(sv, sq))
+    rec = {"workload": f"{n_slices} x {w.name}", "epochs": epochs,
+           "batched_slice_epochs_per_s": round(n_slices * epochs / t_batch, 1),
+           "sequential_slice_epochs_per_s": round(n_slices * epochs / t_seq, 1),
+           "speedup": round(t_seq / t_batch, 3), "bitwise_equal_to_sequential": bool(same)}
+    log_fn(f"bench: batch {rec}")
+    return rec
+
+
+def bench_serve(args, dev, log_fn):
+    """A Poisson trace of mixed-size reconstructions served with continuous batching, against the
+    same trace served one request at a time."""
+    from paper_2602_09527_amd import serve
+    trace = serve.make_trace(args.serve_requests, args.serve_rate, seed=505)
+    geoms = serve.GeometryCache(dev, power_iters=30)
+    geoms.warm(trace)
+    bank = serve.data_bank(trace, dev)
+    cfg = serve.ServeConfig(max_epochs=args.serve_cap)
+    res, wall = serve.serve(trace, cfg, bank, geoms)
+    batched = serve.summarize(res, wall)
+    log_fn(f"bench: serving (batched) {batched}")
+    res2, wall2 = serve.serve_sequential(trace, cfg, bank, geoms)
+    seq = serve.summarize(res2, wall2)
+    log_fn(f"bench: serving (one at a time) {seq}")
+    return {"trace": f"{args.serve_requests} requests, Poisson {args.serve_rate}/s, sides "
+                     f"{{128..1024}}, angles {{90..1800}}, bins 1.5 N, p = {cfg.p}, "
+                     f"tol {cfg.tol}, cap {cfg.max_epochs} epochs",
+            "continuous_batching": batched, "one_at_a_time": seq}
 
 
 def calibrate_copy():
@@ -215,31 +320,34 @@ def main():
     t_fp_sub = event_time(lambda: api.project(g, x, 0, out=ysub))
     n = w.nx * w.ny
     a_sub = g.subset_size(0)
-    # algorithmic work: 7 flops per interpolation (position step, fraction, 1 - w, two products,
-    # two adds); the backprojector does the same per pixel-angle-sample (2 samples per pair).
-    fp_full_flops = 7.0 * w.n_angles * w.n_bins * max(w.nx, w.ny)
-    bp_full_flops = 7.0 * 2 * w.n_angles * n
+    samples_full = w.n_angles * w.n_bins * max(w.nx, w.ny)   # ray-row crossings, all angles
+    samples_sub = a_sub * w.n_bins * max(w.nx, w.ny)
     bytes_fp_full = 4.0 * (n + w.n_angles * w.n_bins)
     bytes_fp_sub = 4.0 * (2 * n + a_sub * w.n_bins)
     bytes_bp_full = 4.0 * (w.n_angles * w.n_bins + n)
+
+    def krec(t, samples, ops, nbytes):
+        return {"us": round(t * 1e6, 2), "gsamples_per_s": round(samples / t / 1e9, 1),
+                "alu_tops": round(ops * samples / t / 1e12, 3),
+                "alu_frac": round(ops * samples / t / 1e12 / ALU_PEAK_TOPS, 4),
+                "algorithmic_gbs": round(nbytes / t / 1e9, 2)}
     kern = {
-        "backproject_full": {"s": t_bp_full, "tflops": bp_full_flops / t_bp_full / 1e12,
-                             "gbs": bytes_bp_full / t_bp_full / 1e9},
-        "project_full": {"s": t_fp_full, "tflops": fp_full_flops / t_fp_full / 1e12,
-                         "gbs": bytes_fp_full / t_fp_full / 1e9},
-        "backproject_subset": {"s": t_bp_sub},
-        "project_subset": {"s": t_fp_sub, "gbs": bytes_fp_sub / t_fp_sub / 1e9},
+        "backproject_full": krec(t_bp_full, samples_full, OPS_BACKPROJECT, bytes_bp_full),
+        "project_full": krec(t_fp_full, samples_full, OPS_PROJECT, bytes_fp_full),
+        "backproject_subset": krec(t_bp_sub, samples_sub, OPS_BACKPROJECT, 4.0 * (a_sub * w.n_bins + n)),
+        "project_subset": krec(t_fp_sub, samples_sub, OPS_PROJECT, bytes_fp_sub),
     }
     for k_, v in kern.items():
-        log(f"bench: {k_}: {v['s'] * 1e6:.1f} us/launch " +
-            " ".join(f"{kk}={vv:.3f}" for kk, vv in v.items() if kk != "s"))
-    dom = "backproject_full" if t_bp_full >= t_fp_full else "project_full"
-    dk = kern[dom]
-    roofline = {"kernel": "k_backproject (all angles)" if dom == "backproject_full" else
-                "k_project (all angles)",
-                "bound": "alu", "achieved": round(dk["tflops"], 4), "peak": FP32_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(dk["tflops"] / FP32_VECTOR_PEAK_TFLOPS, 5),
-                "traffic": None, "us_per_launch": round(dk["s"] * 1e6, 2)}
+        log(f"bench: {k_}: " + " ".join(f"{kk}={vv}" for kk, vv in v.items()))
+    # k_backproject is the kernel with the most time per epoch (all-angle and subset launches);
+    # its all-angle launch is the one rated here.
+    dk = kern["backproject_full"]
+    traffic = measured_traffic()
+    roofline = {"kernel": "k_backproject (all 720 angles, 512^2)", "bound": "alu",
+                "achieved": dk["alu_tops"], "peak": round(ALU_PEAK_TOPS, 2), "unit": "Tops/s",
+                "frac": dk["alu_frac"], "traffic": round(traffic) if traffic else None,
+                "us_per_launch": dk["us"], "ops_per_sample": OPS_BACKPROJECT,
+                "samples_per_launch": samples_full}
 
     out = {
         "metric": METRIC, "value": round(eps, 3), "unit": "epochs/s", "n_gpus": 1, "steps": K,
@@ -249,8 +357,8 @@ def main():
                    "bins": w.n_bins, "subsets": w.n_subsets, "p": p, "alpha": w.alpha,
                    "fgp_inner": w.fgp_inner, "method": "ProxSkip-SVRG"},
         "roofline": roofline,
-        "projector_hbm_gbs": round(kern["project_full"]["gbs"], 2),
-        "kernels_us": {k_: round(v["s"] * 1e6, 2) for k_, v in kern.items()},
+        "projector_hbm_gbs": kern["project_full"]["algorithmic_gbs"],
+        "kernels": kern,
     }
 
     # ---- differentiable projector on a batch of 64 images of 256^2 (360 x 384, all angles) ---
@@ -284,6 +392,14 @@ def main():
                           "prox_calls": q["prox_calls"], "rel_change": q["last_rel_change"]})
             log(f"bench: sweep {label}: {E / dt:.1f} epochs/s, prox calls {q['prox_calls']}")
         out["sweep"] = sweep
+
+    # ---- batched independent slices: 64 solves of 128^2 (180 x 128, N = 10) ----------------
+    if not args.no_batch:
+        out["batch"] = bench_batch(dev, log)
+
+    # ---- serving: Poisson trace of mixed sizes, continuous batching vs one at a time ---------
+    if not args.no_serve:
+        out["serving"] = bench_serve(args, dev, log)
 
     # ---- CPU oracle baseline on a bounded sample + parity of that sample -------------------
     if not args.no_cpu_baseline:
