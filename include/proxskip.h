@@ -87,6 +87,37 @@ PS_API ps_status geometry_upload(ps_geometry *geom, void *dev_buf, size_t bytes,
 /* a_i, the number of angles in subset i; subset = -1 => A.  Returns -1 for a bad subset. */
 PS_API int32_t subset_size(const ps_geometry *geom, int32_t subset);
 
+/* Launch plan of a geometry: tile shapes and work splits of the kernels.  A field of 0 means
+ * "chosen by the library from the shape".  A plan changes how work is divided, never what is
+ * computed: results differ only by the order of floating-point sums (a different ray split or
+ * angle grouping), within the documented tolerances.  Workspace sizes depend on the plan: set it
+ * (or autotune) before sizing workspaces and creating solver handles.
+ *   proj_split_*   workgroups along each ray (projector; partial sums added by a second pass)
+ *   bp_groups_*    angle groups of the backprojector (each writes its own partial image)
+ *   bp_strip_*     image rows (or columns) per backprojector workgroup: 8, 4, 2 or 1
+ *   fgp_iters      inner iterations per 2D FGP launch (temporal blocking): 1..8 (1..4 FP64)
+ * "_full" applies to all-angle calls (subset = -1), "_subset" to single subsets. */
+typedef struct {
+    int32_t proj_split_full, proj_split_subset;
+    int32_t bp_groups_full, bp_groups_subset;
+    int32_t bp_strip_full, bp_strip_subset;
+    int32_t fgp_iters;
+} ps_plan;
+
+/* The plan in effect (automatic choices filled in) / replace the overrides.  set: fields out of
+ * range => PS_EINVAL and nothing changes. */
+PS_API ps_status geometry_get_plan(const ps_geometry *geom, ps_plan *out);
+PS_API ps_status geometry_set_plan(ps_geometry *geom, const ps_plan *plan);
+
+/* Autotuner: time candidate plans of the projector, backprojector and 2D FGP on this geometry
+ * (HIP events on `stream`, `reps` timed launches each after one warm-up launch, synthetic
+ * inputs), keep the fastest of each, store them as the geometry's plan and return it in `out`.
+ * Synchronises `stream`.  workspace: device scratch of geometry_autotune_workspace_bytes bytes.
+ * The geometry must be uploaded.  Errors: PS_EINVAL, PS_EHIP. */
+PS_API size_t geometry_autotune_workspace_bytes(const ps_geometry *geom);
+PS_API ps_status geometry_autotune(ps_geometry *geom, void *workspace, size_t ws_bytes,
+                            int32_t reps, void *stream, ps_plan *out);
+
 /* Forward projection y = A_i x (Sec. 1.2: the subset operator A_i), ray-driven Joseph
  * interpolation.  subset = -1 projects all A angles (y = [nz][A][B]).
  * x: device [nz][ny][nx]; y: device [nz][a_i][B], overwritten.
@@ -190,6 +221,15 @@ PS_API ps_status solver_epochs(ps_solver *const *handles, int32_t n_handles, int
  * handles between rounds.  Returns with every tolerance check settled. */
 PS_API ps_status solver_steps(ps_solver *const *handles, int32_t n_handles, int32_t n_steps,
                        void *stream);
+/* solver_epochs_graph: the same epochs as solver_epochs, issued as HIP graphs.  Each round (one
+ * epoch of every handle that still runs; handles with fewer subsets wait for the round's end) is
+ * captured on a library-owned stream, instantiated -- or, when an earlier round had the same
+ * launch topology (handles, subset counts, coin pattern), that executable graph is updated with
+ * the new kernel arguments -- and launched on `stream`.  The graphs are cached in handles[0]
+ * (at most 64, released by solver_free).  Every handle must be at an epoch start (k a multiple
+ * of N), else PS_EINVAL.  Results are bit for bit those of solver_epochs. */
+PS_API ps_status solver_epochs_graph(ps_solver *const *handles, int32_t n_handles, int32_t n_epochs,
+                              void *stream);
 /* 1 when the handle will not advance any further (converged, budget spent, cancelled or
  * non-finite) and nothing of it is pending on the host side, 0 otherwise, -1 for NULL.  Does not
  * synchronise. */

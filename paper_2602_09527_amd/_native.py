@@ -20,10 +20,13 @@ PS_F32, PS_F64 = 0, 1
 # Every symbol include/proxskip.h declares.
 EXPORTS = (
     "make_geometry", "free_geometry", "geometry_device_bytes", "geometry_upload", "subset_size",
+    "geometry_get_plan", "geometry_set_plan", "geometry_autotune_workspace_bytes",
+    "geometry_autotune",
     "project_workspace_bytes", "project_subset", "backproject_workspace_bytes",
     "backproject_subset", "tv_prox_workspace_bytes",
     "tv_prox_fgp", "proxskip_workspace_bytes", "proxskip_svrg_run", "solver_init",
-    "solver_epochs", "solver_steps", "solver_done", "solver_query", "solver_cancel",
+    "solver_epochs", "solver_epochs_graph", "solver_steps", "solver_done", "solver_query",
+    "solver_cancel",
     "solver_free", "sample_sequences", "last_error_message",
 )
 
@@ -35,6 +38,13 @@ class GeometryDesc(C.Structure):
         ("n_bins", C.c_int32), ("bin_width", C.c_double), ("det_offset", C.c_double),
         ("n_subsets", C.c_int32), ("dtype", C.c_int),
     ]
+
+
+class Plan(C.Structure):
+    _fields_ = [("proj_split_full", C.c_int32), ("proj_split_subset", C.c_int32),
+                ("bp_groups_full", C.c_int32), ("bp_groups_subset", C.c_int32),
+                ("bp_strip_full", C.c_int32), ("bp_strip_subset", C.c_int32),
+                ("fgp_iters", C.c_int32)]
 
 
 class SolverParams(C.Structure):
@@ -79,6 +89,10 @@ def load():
         "geometry_device_bytes": (sz, [vp]),
         "geometry_upload": (st, [vp, vp, sz, vp]),
         "subset_size": (i32, [vp, i32]),
+        "geometry_get_plan": (st, [vp, C.POINTER(Plan)]),
+        "geometry_set_plan": (st, [vp, C.POINTER(Plan)]),
+        "geometry_autotune_workspace_bytes": (sz, [vp]),
+        "geometry_autotune": (st, [vp, vp, sz, i32, vp, C.POINTER(Plan)]),
         "project_workspace_bytes": (sz, [vp, i32]),
         "project_subset": (st, [vp, i32, vp, vp, vp, sz, vp]),
         "backproject_workspace_bytes": (sz, [vp, i32]),
@@ -91,6 +105,7 @@ def load():
         "solver_init": (st, [vp, vp, vp, vp, vp, C.POINTER(SolverParams), vp, sz, C.POINTER(vp)]),
         "solver_epochs": (st, [C.POINTER(vp), i32, i32, vp]),
         "solver_steps": (st, [C.POINTER(vp), i32, i32, vp]),
+        "solver_epochs_graph": (st, [C.POINTER(vp), i32, i32, vp]),
         "solver_done": (i32, [vp]),
         "solver_query": (st, [vp, C.POINTER(SolverStats)]),
         "solver_cancel": (st, [vp]),

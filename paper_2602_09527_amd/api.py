@@ -97,6 +97,26 @@ class Geometry:
     def dual_shape(self):
         return (self.tv_dims, self.nz, self.ny, self.nx)
 
+    # -- launch plan ------------------------------------------------------------------------
+    @property
+    def key(self) -> str:
+        """Shape key of this geometry (for caches of tuned plans)."""
+        dt = "f64" if self.dtype == torch.float64 else "f32"
+        return (f"{self.nx}x{self.ny}x{self.nz}_a{self.n_angles}_b{self.n_bins}_n{self.n_subsets}"
+                f"_w{self.bin_width:g}_o{self.det_offset:g}_{dt}" + ("_custom" if self._angles is not None else ""))
+
+    def get_plan(self) -> dict:
+        """The launch plan in effect (automatic choices filled in)."""
+        p = nat.Plan()
+        nat.check(self.lib.geometry_get_plan(self.handle, C.byref(p)), "geometry_get_plan")
+        return {f: getattr(p, f) for f, _ in nat.Plan._fields_}
+
+    def set_plan(self, plan: dict) -> None:
+        """Override launch-plan fields (0 = automatic); set before sizing workspaces."""
+        p = nat.Plan(**{f: int(plan.get(f, 0)) for f, _ in nat.Plan._fields_})
+        nat.check(self.lib.geometry_set_plan(self.handle, C.byref(p)), "geometry_set_plan")
+        self._ws = {}
+
     # -- buffers ----------------------------------------------------------------------------
     def check(self, t: torch.Tensor, shape, what: str) -> torch.Tensor:
         if not isinstance(t, torch.Tensor):
@@ -235,8 +255,8 @@ class Solver:
                                     C.byref(h_)), "solver_init")
         self.handle = h_
 
-    def epochs(self, n: int, stream=None):
-        run_epochs([self], n, stream)
+    def epochs(self, n: int, stream=None, graph: bool = False):
+        run_epochs([self], n, stream, graph=graph)
 
     def done(self) -> bool:
         """True once the handle will not advance any further (no synchronisation)."""
@@ -262,15 +282,20 @@ class Solver:
             pass
 
 
-def run_epochs(solvers, n_epochs: int, stream=None):
+def run_epochs(solvers, n_epochs: int, stream=None, graph: bool = False):
     """Run ``n_epochs`` more epochs of every solver, batched in lockstep (one launch per stage
-    over all solvers); each solver's result is bit for bit its result alone."""
+    over all solvers); each solver's result is bit for bit its result alone.  graph=True issues
+    every epoch round as a captured HIP graph (solver_epochs_graph)."""
     if not solvers:
         return
     arr = (C.c_void_p * len(solvers))(*[s.handle for s in solvers])
     dev = solvers[0].g.device
     st = C.c_void_p(stream.cuda_stream) if stream is not None else _stream(dev)
-    nat.check(solvers[0].g.lib.solver_epochs(arr, len(solvers), int(n_epochs), st), "solver_epochs")
+    lib = solvers[0].g.lib
+    if graph:
+        nat.check(lib.solver_epochs_graph(arr, len(solvers), int(n_epochs), st), "solver_epochs_graph")
+    else:
+        nat.check(lib.solver_epochs(arr, len(solvers), int(n_epochs), st), "solver_epochs")
 
 
 def run_steps(solvers, n_steps: int, stream=None):
@@ -292,6 +317,38 @@ def sample_sequences(seed: int, k0: int, count: int, n_subsets: int, p: float):
                                    sub.ctypes.data_as(C.c_void_p), coin.ctypes.data_as(C.c_void_p)),
               "sample_sequences")
     return sub[:count], coin[:count]
+
+
+def autotune(g: Geometry, reps: int = 5, cache_path: str | None = None) -> dict:
+    """Time candidate launch plans on the device and keep the fastest (see geometry_autotune).
+
+    With ``cache_path`` (a JSON file), a plan tuned earlier for the same geometry key is reused
+    and a newly tuned one is stored."""
+    import json
+    import os
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as f:
+            cache = json.load(f)
+        if g.key in cache:
+            g.set_plan(cache[g.key])
+            return g.get_plan()
+    nbytes = g.lib.geometry_autotune_workspace_bytes(g.handle)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=g.device)
+    p = nat.Plan()
+    nat.check(g.lib.geometry_autotune(g.handle, _ptr(ws), nbytes, int(reps), _stream(g.device),
+                                      C.byref(p)), "geometry_autotune")
+    del ws
+    g._ws = {}
+    plan = {f: getattr(p, f) for f, _ in nat.Plan._fields_}
+    if cache_path:
+        cache = {}
+        if os.path.exists(cache_path):
+            with open(cache_path) as f:
+                cache = json.load(f)
+        cache[g.key] = plan
+        with open(cache_path, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+    return plan
 
 
 def lipschitz(g: Geometry, iters: int = 100, seed: int = 0) -> float:

@@ -28,7 +28,8 @@ BackPlan back_plan(const ps_geometry *g, int subset) {
     const int ext = std::max(d.nx, d.ny);
     p.stride = ext + 4;
     p.waves = 4;
-    p.strip = 8;
+    const int forced_strip = subset < 0 ? g->plan.bp_strip_full : g->plan.bp_strip_subset;
+    p.strip = forced_strip > 0 ? forced_strip : 8;
     const size_t budget = 80 * 1024;  // two workgroups per CU (160 KB of LDS)
     while (p.strip > 1 && static_cast<size_t>(p.waves) * p.strip * p.stride * g->elem > budget)
         p.strip >>= 1;
@@ -41,6 +42,8 @@ BackPlan back_plan(const ps_geometry *g, int subset) {
     const int most = std::max(nrow, na - nrow);
     const long per_group = static_cast<long>(p.s_row + p.s_col) * d.nz;
     long G = (512 + per_group - 1) / per_group;
+    const int forced_g = subset < 0 ? g->plan.bp_groups_full : g->plan.bp_groups_subset;
+    if (forced_g > 0) G = forced_g;
     G = std::max(1L, std::min<long>(G, std::min(16, std::max(1, most))));
     p.groups = static_cast<int>(G);
     p.lds_bytes = static_cast<size_t>(p.waves) * p.strip * p.stride * g->elem;

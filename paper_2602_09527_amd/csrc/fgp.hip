@@ -340,7 +340,11 @@ size_t fgp_workspace(const ps_geometry *g) {
 // storing the tile state, about 4 us) more often; on this chip 8 per launch is faster at every
 // size measured (512^2: 7 launches of 15.5 us against 13 of 9.9 us at 4 per launch).  The choice
 // does not change results.
-static int fgp_iters_per_launch(const ps_geometry *g) { return fgp_max_iters(g->elem); }
+int fgp_max_iters_of(const ps_geometry *g) { return fgp_max_iters(g->elem); }
+int fgp_iters_per_launch(const ps_geometry *g) {
+    const int f = g->plan.fgp_iters;
+    return f > 0 ? std::min(f, fgp_max_iters(g->elem)) : fgp_max_iters(g->elem);
+}
 
 // A 2D FGP solve as its sequence of launches, plus the copies around them.
 template <typename T>

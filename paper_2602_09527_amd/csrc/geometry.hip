@@ -136,6 +136,7 @@ extern "C" ps_status make_geometry(const ps_geometry_desc *d, ps_geometry **out)
         }
     }
     g->desc.angles = g->angles.data();
+    g->plan = ps_plan{};
     g->tv_dims = d->nz > 1 ? 3 : 2;
     g->elem = d->dtype == PS_F64 ? sizeof(double) : sizeof(float);
     g->dev = nullptr;

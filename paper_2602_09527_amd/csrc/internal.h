@@ -102,6 +102,7 @@ struct ps_geometry {
     std::vector<int32_t> order_full, order_sub, sub_off, nrow_sub;
     int nrow_full;
     size_t off_ord_full, off_ord_sub;
+    ps_plan plan;                         // launch-plan overrides (0 = automatic)
 };
 
 namespace ps {
@@ -234,6 +235,8 @@ ps_status launch_backproject(const ps_geometry *g, int subset, const void *y, vo
 // TV prox by FGP (fgp.hip).
 // ---------------------------------------------------------------------------------------------
 size_t fgp_workspace(const ps_geometry *g);
+int fgp_iters_per_launch(const ps_geometry *g);
+int fgp_max_iters_of(const ps_geometry *g);
 // Finalise modes: write z (FGP_Z) or the ProxSkip update x = z, h = hscale (z - v) (FGP_PROXSKIP).
 struct FgpOut {
     void *z;        // FGP_Z: output image (may alias v)

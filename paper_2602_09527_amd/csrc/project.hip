@@ -42,6 +42,8 @@ ProjPlan proj_plan(const ps_geometry *g, int na) {
     const int max_split = std::max(1, ext / (2 * p.strip));
     const long want = (2048 + base - 1) / base;
     p.split = static_cast<int>(std::max(1L, std::min<long>(want, max_split)));
+    const int forced = na == d.n_angles ? g->plan.proj_split_full : g->plan.proj_split_subset;
+    if (forced > 0) p.split = std::min(forced, max_split);
     p.lds_bytes = static_cast<size_t>(p.strip) * p.stride * g->elem;
     return p;
 }

@@ -13,7 +13,9 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <atomic>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "internal.h"
@@ -21,6 +23,17 @@
 namespace ps {
 
 constexpr int kNormBlocks = 1024;
+
+// Instantiated graphs of captured epoch rounds, keyed by the round's launch topology.
+struct GraphCache {
+    hipStream_t capture = nullptr;   // never runs work: launches are recorded on it
+    std::vector<std::pair<std::string, hipGraphExec_t>> execs;   // most recently used last
+    ~GraphCache() {
+        for (auto &e : execs) (void)hipGraphExecDestroy(e.second);
+        if (capture) (void)hipStreamDestroy(capture);
+    }
+};
+constexpr size_t kMaxGraphs = 64;
 
 // Partial sums of ||x - xs||^2 and ||x||^2 (FP64) per block; optionally xs = x afterwards.
 template <typename T>
@@ -174,6 +187,8 @@ struct ps_solver {
     bool pending;
     hipEvent_t ev;
     double *pinned;
+    uint64_t id;                  // unique per handle (keys of the graph cache)
+    ps::GraphCache *graphs;       // executable epoch graphs of rounds this handle led, or null
 };
 
 namespace ps {
@@ -280,8 +295,9 @@ static ps_status snapshot_many(const std::vector<ps_solver *> &hs, int do_norm, 
 //   snapshot copies (handles at an epoch start) -> projections -> backprojections with the
 //   fused SVRG/ProxSkip step -> FGP prox (handles whose coin is heads) -> epoch-end norms.
 // Every handle computes exactly what it computes alone.
-static ps_status run_step(const std::vector<ps_solver *> &hs, hipStream_t st) {
-    std::vector<ps_solver *> starting, ending;
+static ps_status run_step(const std::vector<ps_solver *> &hs, hipStream_t st,
+                          std::vector<ps_solver *> &ending) {
+    std::vector<ps_solver *> starting;
     std::vector<ProjCall> pc;
     std::vector<BackCall> bc;
     std::vector<FgpCall> fc;
@@ -336,17 +352,21 @@ static ps_status run_step(const std::vector<ps_solver *> &hs, hipStream_t st) {
     PS_TRY(launch_project_many(pc.data(), static_cast<int>(pc.size()), st));
     PS_TRY(launch_backproject_many(bc.data(), static_cast<int>(bc.size()), st));
     if (!fc.empty()) PS_TRY(launch_fgp_many(fc.data(), static_cast<int>(fc.size()), st));
-    if (!ending.empty()) {
-        PS_TRY(snapshot_many(ending, 1, st));  // ||x_e - x_{e-1}||, ||x_e||
-        for (ps_solver *s : ending) {
-            if (s->prm.tol_rel_change > 0.0) {
-                const double *src = reinterpret_cast<const double *>(s->ws + s->L.stats) + 2 * s->epochs_done;
-                PS_HIP(hipMemcpyAsync(s->pinned, src, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-                PS_HIP(hipEventRecord(s->ev, st));
-                s->pending = true;
-            }
-            s->epochs_done++;
+    if (!ending.empty()) PS_TRY(snapshot_many(ending, 1, st));  // ||x_e - x_{e-1}||, ||x_e||
+    return PS_OK;
+}
+
+// After the epoch-end norms of `ended` are queued on `st`: count the epochs and send the norms of
+// tolerance handles to pinned host memory behind their events.
+static ps_status finish_epochs(const std::vector<ps_solver *> &ended, hipStream_t st) {
+    for (ps_solver *s : ended) {
+        if (s->prm.tol_rel_change > 0.0) {
+            const double *src = reinterpret_cast<const double *>(s->ws + s->L.stats) + 2 * s->epochs_done;
+            PS_HIP(hipMemcpyAsync(s->pinned, src, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+            PS_HIP(hipEventRecord(s->ev, st));
+            s->pending = true;
         }
+        s->epochs_done++;
     }
     return PS_OK;
 }
@@ -393,6 +413,9 @@ extern "C" ps_status solver_init(const ps_geometry *g, const void *b, void *x, v
     s->pending = false;
     s->ev = nullptr;
     s->pinned = nullptr;
+    static std::atomic<uint64_t> next_id{1};
+    s->id = next_id.fetch_add(1);
+    s->graphs = nullptr;
     if (prm->tol_rel_change > 0.0) {
         // pinned host memory (no device allocation) for the per-epoch tolerance checks
         if (hipHostMalloc(reinterpret_cast<void **>(&s->pinned), 2 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
@@ -441,7 +464,9 @@ static ps_status lockstep(ps_solver *const *handles, int n_handles, const std::v
             PS_HIP(hipEventSynchronize(waiting->ev));
             continue;
         }
-        PS_TRY(run_step(ready, st));
+        std::vector<ps_solver *> ended;
+        PS_TRY(run_step(ready, st, ended));
+        PS_TRY(finish_epochs(ended, st));
         ++steps;
     }
     if (nonfinite) return fail(PS_ENONFINITE, "non-finite iterate at an epoch end");
@@ -495,6 +520,128 @@ extern "C" ps_status solver_steps(ps_solver *const *handles, int32_t n_handles, 
     return lockstep(handles, n_handles, target, n_steps, st);
 }
 
+namespace ps {
+
+// One round under graph capture: one epoch of every handle in `hs` (all at an epoch start),
+// recorded on the cache's capture stream, instantiated (or an earlier graph of the same
+// topology updated with the new kernel arguments) and launched on `st`.
+static ps_status graph_round(const std::vector<ps_solver *> &hs, hipStream_t st, GraphCache *gc) {
+    int steps = 0;
+    std::string key;
+    for (ps_solver *s : hs) {
+        const int N = s->g->desc.n_subsets;
+        steps = std::max(steps, N);
+        std::vector<uint8_t> coin(N);
+        draw_sequences(s->prm.seed, s->k, N, N, s->prm.p, nullptr, coin.data());
+        key += std::to_string(s->id) + ":" + std::to_string(N) + ":";
+        for (int t = 0; t < N; ++t) key += static_cast<char>('0' + (s->prm.plain_prox_svrg ? 1 : coin[t]));
+        key += ";";
+    }
+    if (!gc->capture) PS_HIP(hipStreamCreateWithFlags(&gc->capture, hipStreamNonBlocking));
+    PS_HIP(hipStreamBeginCapture(gc->capture, hipStreamCaptureModeRelaxed));
+    ps_status rs = PS_OK;
+    std::vector<ps_solver *> ended_all, part, ended;
+    for (int t = 0; t < steps && rs == PS_OK; ++t) {
+        part.clear();
+        for (ps_solver *s : hs)
+            if (t < s->g->desc.n_subsets) part.push_back(s);
+        ended.clear();
+        rs = run_step(part, gc->capture, ended);
+        ended_all.insert(ended_all.end(), ended.begin(), ended.end());
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(gc->capture, &graph);
+    if (rs != PS_OK) {
+        if (ec == hipSuccess && graph) (void)hipGraphDestroy(graph);
+        return rs;
+    }
+    if (ec != hipSuccess) return fail(PS_EHIP, "hipStreamEndCapture failed: %s", hipGetErrorString(ec));
+    hipGraphExec_t exec = nullptr;
+    for (size_t i = 0; i < gc->execs.size(); ++i) {
+        if (gc->execs[i].first != key) continue;
+        hipGraphNode_t err_node = nullptr;
+        hipGraphExecUpdateResult res{};
+        if (hipGraphExecUpdate(gc->execs[i].second, graph, &err_node, &res) == hipSuccess &&
+            res == hipGraphExecUpdateSuccess) {
+            exec = gc->execs[i].second;
+            std::rotate(gc->execs.begin() + i, gc->execs.begin() + i + 1, gc->execs.end());
+        } else {
+            (void)hipGetLastError();
+            (void)hipGraphExecDestroy(gc->execs[i].second);
+            gc->execs.erase(gc->execs.begin() + i);
+        }
+        break;
+    }
+    if (!exec) {
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return fail(PS_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(ei));
+        }
+        if (gc->execs.size() >= kMaxGraphs) {
+            (void)hipGraphExecDestroy(gc->execs.front().second);
+            gc->execs.erase(gc->execs.begin());
+        }
+        gc->execs.emplace_back(key, exec);
+    }
+    (void)hipGraphDestroy(graph);
+    PS_HIP(hipGraphLaunch(exec, st));
+    return finish_epochs(ended_all, st);
+}
+
+}  // namespace ps
+
+extern "C" ps_status solver_epochs_graph(ps_solver *const *handles, int32_t n_handles,
+                                         int32_t n_epochs, void *stream) {
+    clear_error();
+    if (n_epochs < 0) return fail(PS_EINVAL, "n_epochs must be >= 0");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    PS_TRY(begin_call(handles, n_handles, st));
+    if (n_handles == 0) return PS_OK;
+    for (int i = 0; i < n_handles; ++i) {
+        if (handles[i]->k % handles[i]->g->desc.n_subsets != 0)
+            return fail(PS_EINVAL, "handle %d is inside an epoch (after solver_steps): finish it with solver_steps or solver_epochs first", i);
+    }
+    ps_solver *lead = handles[0];
+    if (!lead->graphs) {
+        lead->graphs = new (std::nothrow) GraphCache();
+        if (!lead->graphs) return fail(PS_ENOMEM, "out of host memory");
+    }
+    std::vector<int> target(n_handles);
+    for (int i = 0; i < n_handles; ++i)
+        target[i] = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(handles[i]->epochs_done) + n_epochs,
+                                                       handles[i]->prm.n_epochs));
+    std::vector<ps_solver *> ready;
+    bool nonfinite = false;
+    for (;;) {
+        // tolerance checks of the previous round decide who takes part in the next one
+        ready.clear();
+        for (int i = 0; i < n_handles; ++i) {
+            ps_solver *s = handles[i];
+            if (s->pending) {
+                PS_HIP(hipEventSynchronize(s->ev));
+                take_norms(s, s->epochs_done - 1, s->pinned[0], s->pinned[1]);
+                s->pending = false;
+                if (s->nonfinite) nonfinite = true;
+            }
+            if (active(s) && s->epochs_done < target[i]) ready.push_back(s);
+        }
+        if (ready.empty()) break;
+        PS_TRY(graph_round(ready, st, lead->graphs));
+    }
+    for (int i = 0; i < n_handles; ++i) {
+        ps_solver *s = handles[i];
+        if (s->pending) {
+            PS_HIP(hipEventSynchronize(s->ev));
+            take_norms(s, s->epochs_done - 1, s->pinned[0], s->pinned[1]);
+            s->pending = false;
+            if (s->nonfinite) nonfinite = true;
+        }
+    }
+    if (nonfinite) return fail(PS_ENONFINITE, "non-finite iterate at an epoch end");
+    return PS_OK;
+}
+
 extern "C" int32_t solver_done(const ps_solver *s) {
     if (!s) return -1;
     return (!s->pending && !active(s)) ? 1 : 0;
@@ -527,6 +674,11 @@ extern "C" void solver_free(ps_solver *s) {
         (void)hipEventDestroy(s->ev);
     }
     if (s->pinned) (void)hipHostFree(s->pinned);
+    if (s->graphs) {
+        // graphs launched on the handle's stream may still run
+        (void)hipStreamSynchronize(s->stream);
+        delete s->graphs;
+    }
     delete s;
 }
 

@@ -1,0 +1,263 @@
+// tune.hip -- launch plans of a geometry: query, override, and the autotuner that times candidate
+// plans on the device and keeps the fastest.
+//
+// What is tuned: the projector's ray split (partial sums over S workgroups per ray, then a fixed
+// order reduction), the backprojector's angle groups G and strip height R, and the number of FGP
+// inner iterations per 2D launch (temporal blocking depth).  None of them changes what is
+// computed; split and grouping change the order of floating-point sums.
+#include <algorithm>
+#include <vector>
+
+#include "internal.h"
+
+namespace ps {
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_tune_fill(T *__restrict__ p, size_t n) {
+    for (size_t e = blockIdx.x * static_cast<size_t>(kBlock) + threadIdx.x; e < n;
+         e += static_cast<size_t>(gridDim.x) * kBlock)
+        p[e] = static_cast<T>(1.0 + 0.001 * static_cast<double>(e % 997));
+}
+
+static ps_status fill(const ps_geometry *g, void *p, size_t n, hipStream_t st) {
+    const unsigned blocks = static_cast<unsigned>(std::max<size_t>(1, std::min<size_t>((n + kBlock - 1) / kBlock, 4096)));
+    if (g->desc.dtype == PS_F64)
+        hipLaunchKernelGGL((k_tune_fill<double>), dim3(blocks), dim3(kBlock), 0, st, static_cast<double *>(p), n);
+    else
+        hipLaunchKernelGGL((k_tune_fill<float>), dim3(blocks), dim3(kBlock), 0, st, static_cast<float *>(p), n);
+    PS_LAUNCHED("k_tune_fill");
+    return PS_OK;
+}
+
+static size_t n_image(const ps_geometry *g) {
+    return static_cast<size_t>(g->desc.nx) * g->desc.ny * g->desc.nz;
+}
+
+static int proj_max_split(const ps_geometry *g) {
+    const ProjPlan p = proj_plan(g, g->desc.n_angles);
+    return std::max(1, std::max(g->desc.nx, g->desc.ny) / (2 * p.strip));
+}
+
+struct TuneLayout {
+    size_t x, y, img, pws, bws, fws, dual, total;
+    size_t pws_bytes, bws_bytes, fws_bytes;
+};
+
+static TuneLayout tune_layout(const ps_geometry *g) {
+    const auto &d = g->desc;
+    const size_t n = n_image(g);
+    const size_t m = static_cast<size_t>(d.nz) * d.n_angles * d.n_bins;
+    TuneLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes); return o; };
+    L.x = take(n * g->elem);
+    L.y = take(m * g->elem);
+    L.img = take(n * g->elem);
+    // the largest split any candidate can take, for all angles (subsets need less)
+    L.pws_bytes = static_cast<size_t>(proj_max_split(g)) * m * g->elem;
+    L.pws = take(L.pws_bytes);
+    L.bws_bytes = 2 * 16 * n * g->elem;  // 2 classes x up to 16 groups of partial images
+    L.bws = take(L.bws_bytes);
+    L.fws_bytes = fgp_workspace(g);
+    L.fws = take(L.fws_bytes);
+    L.dual = take(static_cast<size_t>(g->tv_dims) * n * g->elem);
+    L.total = off;
+    return L;
+}
+
+struct Timer {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Timer() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+};
+
+// Mean milliseconds per call of fn over `reps` calls after one warm-up call.
+template <typename F>
+static ps_status time_calls(F &&fn, int reps, hipStream_t st, Timer &tm, float *ms) {
+    PS_TRY(fn());
+    PS_HIP(hipEventRecord(tm.e0, st));
+    for (int r = 0; r < reps; ++r) PS_TRY(fn());
+    PS_HIP(hipEventRecord(tm.e1, st));
+    PS_HIP(hipEventSynchronize(tm.e1));
+    float t = 0.f;
+    PS_HIP(hipEventElapsedTime(&t, tm.e0, tm.e1));
+    *ms = t / static_cast<float>(std::max(reps, 1));
+    return PS_OK;
+}
+
+// An all-angle launch (run once per epoch, at the snapshot) longer than this keeps the automatic
+// plan: timing its alternatives would cost seconds on volumes.
+constexpr float kLongLaunchMs = 5.0f;
+
+}  // namespace ps
+
+using namespace ps;
+
+extern "C" ps_status geometry_get_plan(const ps_geometry *g, ps_plan *out) {
+    clear_error();
+    if (!g || !out) return fail(PS_EINVAL, "null argument");
+    const int A = g->desc.n_angles;
+    out->proj_split_full = proj_plan(g, A).split;
+    out->proj_split_subset = proj_plan(g, max_subset_count(g)).split;
+    const BackPlan bf = back_plan(g, -1), bs = back_plan(g, 0);
+    out->bp_groups_full = bf.groups;
+    out->bp_groups_subset = bs.groups;
+    out->bp_strip_full = bf.strip;
+    out->bp_strip_subset = bs.strip;
+    out->fgp_iters = fgp_iters_per_launch(g);
+    return PS_OK;
+}
+
+extern "C" ps_status geometry_set_plan(ps_geometry *g, const ps_plan *p) {
+    clear_error();
+    if (!g || !p) return fail(PS_EINVAL, "null argument");
+    auto strip_ok = [](int s) { return s == 0 || s == 1 || s == 2 || s == 4 || s == 8; };
+    if (p->proj_split_full < 0 || p->proj_split_full > 64 || p->proj_split_subset < 0 ||
+        p->proj_split_subset > 64)
+        return fail(PS_EINVAL, "projector split must be in [0, 64]");
+    if (p->bp_groups_full < 0 || p->bp_groups_full > 16 || p->bp_groups_subset < 0 ||
+        p->bp_groups_subset > 16)
+        return fail(PS_EINVAL, "backprojector groups must be in [0, 16]");
+    if (!strip_ok(p->bp_strip_full) || !strip_ok(p->bp_strip_subset))
+        return fail(PS_EINVAL, "backprojector strip must be 0, 1, 2, 4 or 8");
+    if (p->fgp_iters < 0 || p->fgp_iters > fgp_max_iters_of(g))
+        return fail(PS_EINVAL, "fgp_iters must be in [0, %d]", fgp_max_iters_of(g));
+    g->plan = *p;
+    return PS_OK;
+}
+
+extern "C" size_t geometry_autotune_workspace_bytes(const ps_geometry *g) {
+    return g ? tune_layout(g).total : 0;
+}
+
+extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t ws_bytes,
+                                       int32_t reps, void *stream, ps_plan *out) {
+    clear_error();
+    PS_TRY(check_ready(g));
+    PS_TRY(check_ptr(workspace, "workspace", kAlign));
+    if (reps < 1) return fail(PS_EINVAL, "reps must be >= 1");
+    const TuneLayout L = tune_layout(g);
+    if (ws_bytes < L.total)
+        return fail(PS_EINVAL, "autotune workspace: %zu bytes given, %zu needed", ws_bytes, L.total);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    unsigned char *w = static_cast<unsigned char *>(workspace);
+    const auto &d = g->desc;
+    const size_t n = n_image(g);
+    Timer tm;
+    PS_HIP(hipEventCreate(&tm.e0));
+    PS_HIP(hipEventCreate(&tm.e1));
+    PS_TRY(fill(g, w + L.x, n, st));
+    PS_TRY(fill(g, w + L.y, static_cast<size_t>(d.nz) * d.n_angles * d.n_bins, st));
+
+    ps_plan best = g->plan;
+    const ps_plan saved = g->plan;
+    auto restore_on_error = [&](ps_status s) {
+        if (s != PS_OK) g->plan = saved;
+        return s;
+    };
+    const int splits[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64};
+    const int max_split = proj_max_split(g);
+
+    // projector: all angles, then subset 0
+    for (int full = 1; full >= 0; --full) {
+        const int subset = full ? -1 : 0;
+        float best_ms = 0.f;
+        int best_s = 0;
+        g->plan = best;
+        const int auto_split = full ? proj_plan(g, d.n_angles).split : proj_plan(g, max_subset_count(g)).split;
+        std::vector<int> cand{auto_split};
+        for (int s : splits)
+            if (s <= max_split && s != auto_split) cand.push_back(s);
+        const int r = reps;
+        for (size_t c = 0; c < cand.size(); ++c) {
+            ps_plan trial = best;
+            (full ? trial.proj_split_full : trial.proj_split_subset) = cand[c];
+            g->plan = trial;
+            float ms = 0.f;
+            PS_TRY(restore_on_error(time_calls([&] {
+                return launch_project(g, subset, w + L.x, nullptr, nullptr, w + L.y, w + L.pws, L.pws_bytes, st);
+            }, r, st, tm, &ms)));
+            if (c == 0 || ms < best_ms) {
+                best_ms = ms;
+                best_s = cand[c];
+            }
+            if (c == 0 && full && ms > kLongLaunchMs) break;
+        }
+        (full ? best.proj_split_full : best.proj_split_subset) = best_s;
+    }
+
+    // backprojector: (strip, groups) for all angles, then subset 0
+    for (int full = 1; full >= 0; --full) {
+        const int subset = full ? -1 : 0;
+        g->plan = best;
+        const BackPlan auto_bp = back_plan(g, subset);
+        std::vector<std::pair<int, int>> cand{{auto_bp.strip, auto_bp.groups}};
+        for (int s : {8, 4, 2})
+            for (int G : {1, 2, 4, 8, 16})
+                if (!(s == auto_bp.strip && G == auto_bp.groups)) cand.push_back({s, G});
+        float best_ms = 0.f;
+        std::pair<int, int> pick = cand[0];
+        const int r = reps;
+        for (size_t c = 0; c < cand.size(); ++c) {
+            ps_plan trial = best;
+            if (full) {
+                trial.bp_strip_full = cand[c].first;
+                trial.bp_groups_full = cand[c].second;
+            } else {
+                trial.bp_strip_subset = cand[c].first;
+                trial.bp_groups_subset = cand[c].second;
+            }
+            g->plan = trial;
+            const BackPlan bp = back_plan(g, subset);
+            // skip candidates the LDS budget or the angle count clamps to one already timed
+            if (c > 0 && (bp.strip != cand[c].first || bp.groups != cand[c].second)) continue;
+            if (back_workspace(g, subset) > L.bws_bytes) continue;
+            float ms = 0.f;
+            PS_TRY(restore_on_error(time_calls([&] {
+                return launch_backproject(g, subset, w + L.y, w + L.img, BP_OVERWRITE, nullptr, w + L.bws,
+                                          L.bws_bytes, st);
+            }, r, st, tm, &ms)));
+            if (c == 0 || ms < best_ms) {
+                best_ms = ms;
+                pick = cand[c];
+            }
+            if (c == 0 && full && ms > kLongLaunchMs) break;
+        }
+        if (full) {
+            best.bp_strip_full = pick.first;
+            best.bp_groups_full = pick.second;
+        } else {
+            best.bp_strip_subset = pick.first;
+            best.bp_groups_subset = pick.second;
+        }
+    }
+
+    // FGP inner iterations per launch (2D TV only): one 50-iteration prox per timed call
+    if (g->tv_dims == 2) {
+        PS_TRY(fill(g, w + L.dual, 2 * n, st));
+        float best_ms = 0.f;
+        int pick = 0;
+        const int tmax = fgp_max_iters_of(g);
+        for (int T = tmax; T >= 2; --T) {
+            ps_plan trial = best;
+            trial.fgp_iters = T;
+            g->plan = trial;
+            FgpOut o{};
+            o.z = w + L.img;
+            float ms = 0.f;
+            PS_TRY(restore_on_error(time_calls([&] {
+                return launch_fgp(g, w + L.x, w + L.dual, 1e-3, 50, 1, o, w + L.fws, L.fws_bytes, st);
+            }, reps, st, tm, &ms)));
+            if (pick == 0 || ms < best_ms) {
+                best_ms = ms;
+                pick = T;
+            }
+        }
+        best.fgp_iters = pick;
+    }
+    g->plan = best;
+    if (out) PS_TRY(geometry_get_plan(g, out));
+    return PS_OK;
+}

@@ -118,3 +118,40 @@ def test_sequences_reject(nat):
     assert lib.sample_sequences(0, 0, 10, 0, 0.5, None, None) == nat.PS_EINVAL
     assert lib.sample_sequences(0, 0, 10, 4, 0.0, None, None) == nat.PS_EINVAL
     assert lib.sample_sequences(0, -1, 10, 4, 0.5, None, None) == nat.PS_EINVAL
+
+
+def test_plan_get_set_and_validation(nat):
+    lib = nat.load()
+    h = C.c_void_p()
+    assert lib.make_geometry(C.byref(_desc(nat, nx=64, ny=64, n_angles=60, n_bins=96, n_subsets=6)),
+                             C.byref(h)) == nat.PS_OK
+    try:
+        auto = nat.Plan()
+        assert lib.geometry_get_plan(h, C.byref(auto)) == nat.PS_OK
+        assert auto.proj_split_full >= 1 and auto.proj_split_subset >= 1
+        assert 1 <= auto.bp_groups_full <= 16 and auto.bp_strip_full in (1, 2, 4, 8)
+        assert auto.fgp_iters == 8
+        forced = nat.Plan(proj_split_full=2, proj_split_subset=1, bp_groups_full=4,
+                          bp_groups_subset=2, bp_strip_full=4, bp_strip_subset=2, fgp_iters=5)
+        assert lib.geometry_set_plan(h, C.byref(forced)) == nat.PS_OK
+        got = nat.Plan()
+        assert lib.geometry_get_plan(h, C.byref(got)) == nat.PS_OK
+        assert (got.proj_split_full, got.proj_split_subset, got.bp_groups_full,
+                got.bp_groups_subset, got.bp_strip_full, got.bp_strip_subset, got.fgp_iters) == \
+            (2, 1, 4, 2, 4, 2, 5)
+        for bad in (dict(proj_split_full=-1), dict(bp_groups_subset=17), dict(bp_strip_full=3),
+                    dict(fgp_iters=9)):
+            assert lib.geometry_set_plan(h, C.byref(nat.Plan(**bad))) == nat.PS_EINVAL
+        # a rejected plan leaves the previous one in place
+        assert lib.geometry_get_plan(h, C.byref(got)) == nat.PS_OK and got.fgp_iters == 5
+        # workspace sizes follow the plan
+        zero = nat.Plan()
+        assert lib.geometry_set_plan(h, C.byref(zero)) == nat.PS_OK
+        ws_auto = lib.backproject_workspace_bytes(h, -1)
+        assert lib.geometry_set_plan(h, C.byref(nat.Plan(bp_groups_full=1))) == nat.PS_OK
+        assert lib.backproject_workspace_bytes(h, -1) <= ws_auto
+        assert lib.geometry_autotune_workspace_bytes(h) > 0
+        # autotuning needs uploaded tables: refused on the host
+        assert lib.geometry_autotune(h, None, 0, 3, None, None) == nat.PS_EINVAL
+    finally:
+        lib.free_geometry(h)
