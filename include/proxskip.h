@@ -96,12 +96,16 @@ PS_API int32_t subset_size(const ps_geometry *geom, int32_t subset);
  *   bp_groups_*    angle groups of the backprojector (each writes its own partial image)
  *   bp_strip_*     image rows (or columns) per backprojector workgroup: 8, 4, 2 or 1
  *   fgp_iters      inner iterations per 2D FGP launch (temporal blocking): 1..8 (1..4 FP64)
+ *   bp_method_*    1 = ray-driven scatter into LDS strips + combine pass; 2 = pixel-driven gather
+ *                  with the update fused (needs bins at least one pixel apart along every ray's
+ *                  stepping axis, e.g. bin_width >= 1; otherwise scatter is used)
  * "_full" applies to all-angle calls (subset = -1), "_subset" to single subsets. */
 typedef struct {
     int32_t proj_split_full, proj_split_subset;
     int32_t bp_groups_full, bp_groups_subset;
     int32_t bp_strip_full, bp_strip_subset;
     int32_t fgp_iters;
+    int32_t bp_method_full, bp_method_subset;
 } ps_plan;
 
 /* The plan in effect (automatic choices filled in) / replace the overrides.  set: fields out of

@@ -55,6 +55,14 @@ size_t back_workspace(const ps_geometry *g, int subset) {
     return align_up(back_plan(g, subset).part_elems * g->elem);
 }
 
+int back_method(const ps_geometry *g, int subset) {
+    const int forced = subset < 0 ? g->plan.bp_method_full : g->plan.bp_method_subset;
+    if (!g->gather_ok) return BP_SCATTER;
+    if (forced == BP_SCATTER || forced == BP_GATHER) return forced;
+    // automatic: the scatter (faster on the workloads measured; the autotuner may pick the gather)
+    return BP_SCATTER;
+}
+
 // One backprojector application: partial images of A_sub^T y, one per (angle class, group).
 template <typename T>
 struct BackItem {
@@ -237,6 +245,36 @@ struct UpdateT {
     int coin, plain;
 };
 
+// The epilogue of a backprojection at pixel p, d = (A^T y)(p): overwrite, accumulate, or the fused
+// SVRG / ProxSkip gradient step (see UpdateArgs).
+template <typename T>
+__device__ inline void bp_epilogue(int mode, const UpdateT<T> &upd, T *__restrict__ out, size_t p, T d) {
+    if (mode == BP_OVERWRITE) {
+        out[p] = d;
+    } else if (mode == BP_ACCUMULATE) {
+        out[p] += d;
+    } else {
+        T G;
+        if (mode == BP_SNAPSHOT) {
+            upd.gs[p] = d;
+            G = d;
+        } else {
+            G = fma(upd.nsub, d, upd.gs[p]);
+        }
+        const T xv = upd.x[p];
+        if (upd.plain) {
+            upd.vout[p] = xv - upd.gamma * G;
+        } else {
+            const T hv = upd.h[p];
+            const T xh = xv - upd.gamma * (G - hv);
+            if (upd.coin)
+                upd.vout[p] = xh - upd.gamma_over_p * hv;
+            else
+                upd.x[p] = xh;
+        }
+    }
+}
+
 // d = sum of the 2G partial images (fixed order), then the epilogue of `mode`.
 template <typename T>
 struct CombineItem {
@@ -267,30 +305,139 @@ __global__ __launch_bounds__(kBlock) void k_backproject_combine(WorkList<Combine
             for (int q = 0; q < 8; ++q)
                 if (q0 + q < 2 * groups) d += v[q];
         }
-        if (mode == BP_OVERWRITE) {
-            out[p] = d;
-        } else if (mode == BP_ACCUMULATE) {
-            out[p] += d;
-        } else {
-            T G;
-            if (mode == BP_SNAPSHOT) {
-                upd.gs[p] = d;
-                G = d;
-            } else {
-                G = fma(upd.nsub, d, upd.gs[p]);
-            }
-            const T xv = upd.x[p];
-            if (upd.plain) {
-                upd.vout[p] = xv - upd.gamma * G;
-            } else {
-                const T hv = upd.h[p];
-                const T xh = xv - upd.gamma * (G - hv);
-                if (upd.coin)
-                    upd.vout[p] = xh - upd.gamma_over_p * hv;
-                else
-                    upd.x[p] = xh;
+        bp_epilogue(mode, upd, out, p, d);
+    }
+}
+
+// ---- pixel-driven gather (subsets) ------------------------------------------------------------
+//
+// A workgroup owns a tile of 64 columns x 16 rows of one slice (lane = column, each wave 4 rows)
+// and sums, for every pixel, the contributions of all the call's angles directly: no partial
+// images, and the epilogue (the SVRG / ProxSkip step) is applied in the same kernel.
+//   Pixel (i, j) receives from ray u of an angle the weight the projector gives it: with
+//   p the pixel's coordinate along the interpolation axis (j for row-walked angles, i for
+//   column-walked ones) and s along the stepping axis, the ray's cell at step s is
+//   c = floor(q(u, s)) and its weight w = frac(q): the pixel gets (1 - w) y_u / |.| if c = p and
+//   w y_u / |.| if c = p - 1 -- the same 32.32 fixed-point q (FP32) or FMA-evaluated q (FP64),
+//   the same products as the scatter kernel, so A^T stays the projector's transpose.
+//   When adjacent rays are at least one pixel apart (|a1| >= 1), at most two rays have c in
+//   {p - 1, p}, and they are among the three integers around u* = (p - a0 - s a2) / a1; each
+//   candidate is checked exactly.
+//   The rays an angle can send into the tile form a window of at most kGatherWin consecutive
+//   bins; the windows of up to kGatherChunk angles (y / |.|, zero outside [0, B)) are staged in
+//   LDS at a time.
+constexpr int kGatherRows = 4;                     // rows per wave
+constexpr int kGatherTX = 64, kGatherTY = 4 * kGatherRows;
+constexpr int kGatherChunk = 32;
+constexpr int kGatherWin = 96;
+
+template <typename T>
+struct GatherItem {
+    const T *y;
+    T *out;
+    UpdateT<T> upd;
+    AngleTab<T> tab;
+    int subset, nsub, na, nx, ny, nbins, tiles_x, tiles_y, mode;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_backproject_gather(WorkList<GatherItem<T>> wl) {
+    constexpr bool kFixed = std::is_same<T, float>::value;
+    __shared__ T ywin[kGatherChunk][kGatherWin];
+    __shared__ int ulo[kGatherChunk];
+    int local;
+    const GatherItem<T> &it = wl.item[work_item(wl, local)];
+    const AngleTab<T> &tab = it.tab;
+    const int tx = local % it.tiles_x, ty = (local / it.tiles_x) % it.tiles_y;
+    const int z = local / (it.tiles_x * it.tiles_y);
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    const int nx = it.nx, ny = it.ny, B = it.nbins;
+    const int j = tx * kGatherTX + lane;
+    const int i0 = ty * kGatherTY + wave * kGatherRows;
+    const T *yz = it.y + static_cast<size_t>(z) * it.na * B;
+    T acc[kGatherRows];
+#pragma unroll
+    for (int r = 0; r < kGatherRows; ++r) acc[r] = T(0);
+
+    for (int c0 = 0; c0 < it.na; c0 += kGatherChunk) {
+        const int cn = min(kGatherChunk, it.na - c0);
+        __syncthreads();  // the previous chunk's windows are no longer read
+        if (static_cast<int>(threadIdx.x) < cn) {
+            // lowest bin whose ray can reach the tile: cells d_lo - 1 .. d_hi + 1 of the
+            // interpolation axis, over the tile's span of the stepping axis
+            const int l = c0 + threadIdx.x;
+            const int k = it.subset < 0 ? l : it.subset + l * it.nsub;
+            const bool row = tab.row[k] != 0;
+            const T a0 = tab.a0[k], a2 = tab.a2[k], ia1 = tab.ia1[k];
+            const int d_lo = row ? tx * kGatherTX : ty * kGatherTY;
+            const int d_hi = d_lo + (row ? kGatherTX : kGatherTY) - 1;
+            const int s_lo = row ? ty * kGatherTY : tx * kGatherTX;
+            const int s_hi = s_lo + (row ? kGatherTY : kGatherTX) - 1;
+            const T qa = static_cast<T>(d_lo - 1) - a0, qb = static_cast<T>(d_hi + 1) - a0;
+            const T u1 = (qa - static_cast<T>(s_lo) * a2) * ia1, u2 = (qa - static_cast<T>(s_hi) * a2) * ia1;
+            const T u3 = (qb - static_cast<T>(s_lo) * a2) * ia1, u4 = (qb - static_cast<T>(s_hi) * a2) * ia1;
+            const T umin = min(min(u1, u2), min(u3, u4));
+            ulo[threadIdx.x] = static_cast<int>(floor(umin)) - 3;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < cn * kGatherWin; e += blockDim.x) {
+            const int a = e / kGatherWin, w = e - a * kGatherWin;
+            const int l = c0 + a;
+            const int k = it.subset < 0 ? l : it.subset + l * it.nsub;
+            const int u = ulo[a] + w;
+            ywin[a][w] = (u >= 0 && u < B) ? yz[static_cast<size_t>(l) * B + u] * tab.inv[k] : T(0);
+        }
+        __syncthreads();
+        for (int a = 0; a < cn; ++a) {
+            const int l = c0 + a;
+            const int k = it.subset < 0 ? l : it.subset + l * it.nsub;
+            const bool row = tab.row[k] != 0;
+            const T a0 = tab.a0[k], a1 = tab.a1[k], a2 = tab.a2[k], ia1 = tab.ia1[k];
+            const int ub = ulo[a];
+            const T *yw = ywin[a];
+#pragma unroll
+            for (int r = 0; r < kGatherRows; ++r) {
+                const int i = i0 + r;
+                const int p = row ? j : i, s = row ? i : j;
+                // u* biased up by 1/64: candidates floor(u*) - 1 .. + 1 then cover every ray
+                // with c in {p - 1, p} whatever the rounding of u* (|error| < 1e-3)
+                const T ua = (static_cast<T>(p) - fma(static_cast<T>(s), a2, a0)) * ia1 + T(0.015625);
+                const int uf = static_cast<int>(floor(ua)) - 1;
+                T contrib = T(0);
+                if constexpr (kFixed) {
+                    const int64_t q1 = tab.q1[k];
+                    int64_t Q = tab.q0[k] + static_cast<int64_t>(s) * tab.q2[k] + static_cast<int64_t>(uf) * q1;
+#pragma unroll
+                    for (int cnd = 0; cnd < 3; ++cnd) {
+                        const int h = static_cast<int>(Q >> 32) - p;
+                        const int widx = min(max(uf + cnd - ub, 0), kGatherWin - 1);
+                        const T y0 = yw[widx];
+                        const T m = static_cast<T>(static_cast<uint32_t>(Q)) * (y0 * T(0x1p-32f));
+                        contrib += h == 0 ? y0 - m : (h == -1 ? m : T(0));
+                        Q += q1;
+                    }
+                } else {
+#pragma unroll
+                    for (int cnd = 0; cnd < 3; ++cnd) {
+                        const T q = fma(static_cast<T>(uf + cnd), a1, fma(static_cast<T>(s), a2, a0));
+                        const T fl = floor(q);
+                        const int h = static_cast<int>(fl) - p;
+                        const int widx = min(max(uf + cnd - ub, 0), kGatherWin - 1);
+                        const T y0 = yw[widx];
+                        const T m = (q - fl) * y0;
+                        contrib += h == 0 ? y0 - m : (h == -1 ? m : T(0));
+                    }
+                }
+                acc[r] += contrib;
             }
         }
+    }
+    if (j >= nx) return;
+    const size_t plane = static_cast<size_t>(nx) * ny;
+#pragma unroll
+    for (int r = 0; r < kGatherRows; ++r) {
+        const int i = i0 + r;
+        if (i < ny) bp_epilogue(it.mode, it.upd, it.out, z * plane + static_cast<size_t>(i) * nx + j, acc[r]);
     }
 }
 
@@ -324,6 +471,21 @@ static ps_status launch_bp_key(int np, int strip, const WorkList<BackItem<T>> &w
     }
 }
 
+template <typename T>
+static UpdateT<T> to_update(const UpdateArgs &u) {
+    UpdateT<T> r{};
+    r.x = static_cast<T *>(u.x);
+    r.h = static_cast<const T *>(u.h);
+    r.gs = static_cast<T *>(u.gs);
+    r.vout = static_cast<T *>(u.vout);
+    r.gamma = static_cast<T>(u.gamma);
+    r.gamma_over_p = static_cast<T>(u.gamma_over_p);
+    r.nsub = static_cast<T>(u.nsub);
+    r.coin = u.coin;
+    r.plain = u.plain;
+    return r;
+}
+
 static int strip_key(int strip) { return strip == 8 || strip == 4 ? strip : 1; }
 static int np_key(int passes) { return passes >= 1 && passes <= 4 ? passes : 0; }
 
@@ -333,12 +495,41 @@ static ps_status backproject_many_t(const BackCall *calls, int n, hipStream_t st
     std::vector<BackItem<T>> items;
     std::vector<BackPlan> plans;
     std::vector<int> call_of;
+    ListBuilder<GatherItem<T>> gl;
+    auto flush_gather = [&]() -> ps_status {
+        if (gl.empty()) return PS_OK;
+        hipLaunchKernelGGL((k_backproject_gather<T>), dim3(gl.blocks), dim3(kBlock), 0, st, gl.wl);
+        PS_LAUNCHED("k_backproject_gather");
+        gl.clear();
+        return PS_OK;
+    };
     for (int c = 0; c < n; ++c) {
         const BackCall &bc = calls[c];
         const ps_geometry *g = bc.g;
         const auto &d = g->desc;
         if (bc.mode < BP_OVERWRITE || bc.mode > BP_SNAPSHOT)
             return fail(PS_EINVAL, "backprojector mode %d", bc.mode);
+        if (back_method(g, bc.subset) == BP_GATHER) {
+            GatherItem<T> gi{};
+            gi.y = static_cast<const T *>(bc.y);
+            gi.out = static_cast<T *>(bc.out);
+            gi.upd = to_update<T>(bc.upd);
+            gi.tab = angle_tab<T>(g);
+            gi.subset = bc.subset;
+            gi.nsub = d.n_subsets;
+            gi.na = subset_count(g, bc.subset);
+            gi.nx = d.nx;
+            gi.ny = d.ny;
+            gi.nbins = d.n_bins;
+            gi.tiles_x = (d.nx + kGatherTX - 1) / kGatherTX;
+            gi.tiles_y = (d.ny + kGatherTY - 1) / kGatherTY;
+            gi.mode = bc.mode;
+            const long blocks = static_cast<long>(gi.tiles_x) * gi.tiles_y * d.nz;
+            if (blocks > (1L << 30)) return fail(PS_EUNSUPPORTED, "backprojector grid too large");
+            gl.add(gi, static_cast<int>(blocks));
+            if (gl.full()) PS_TRY(flush_gather());
+            continue;
+        }
         const BackPlan bp = back_plan(g, bc.subset);
         const size_t need = back_workspace(g, bc.subset);
         if (!bc.ws || bc.ws_bytes < need)
@@ -399,16 +590,7 @@ static ps_status backproject_many_t(const BackCall *calls, int n, hipStream_t st
         CombineItem<T> ci{};
         ci.part = items[i].part;
         ci.out = static_cast<T *>(bc.out);
-        const UpdateArgs &u = bc.upd;
-        ci.upd.x = static_cast<T *>(u.x);
-        ci.upd.h = static_cast<const T *>(u.h);
-        ci.upd.gs = static_cast<T *>(u.gs);
-        ci.upd.vout = static_cast<T *>(u.vout);
-        ci.upd.gamma = static_cast<T>(u.gamma);
-        ci.upd.gamma_over_p = static_cast<T>(u.gamma_over_p);
-        ci.upd.nsub = static_cast<T>(u.nsub);
-        ci.upd.coin = u.coin;
-        ci.upd.plain = u.plain;
+        ci.upd = to_update<T>(bc.upd);
         ci.n = static_cast<size_t>(items[i].nx) * items[i].ny * items[i].nz;
         ci.groups = items[i].groups;
         ci.mode = bc.mode;
@@ -424,7 +606,7 @@ static ps_status backproject_many_t(const BackCall *calls, int n, hipStream_t st
         hipLaunchKernelGGL((k_backproject_combine<T>), dim3(lb.blocks), dim3(kBlock), 0, st, lb.wl);
         PS_LAUNCHED("k_backproject_combine");
     }
-    return PS_OK;
+    return flush_gather();
 }
 
 ps_status launch_backproject_many(const BackCall *calls, int n, hipStream_t st) {

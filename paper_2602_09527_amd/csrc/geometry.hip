@@ -180,6 +180,9 @@ extern "C" ps_status make_geometry(const ps_geometry_desc *d, ps_geometry **out)
         const int pass_fixed = static_cast<int>((two + min_q1 - 1) / min_q1);
         const int pass_double = static_cast<int>(std::ceil(2.000001 / min_a1));
         g->bp_passes = d->dtype == PS_F64 ? pass_double : pass_fixed;
+        // pixel-driven gather: at most one ray per interpolation cell, so a pixel has at most
+        // two contributing rays per angle
+        g->gather_ok = d->dtype == PS_F64 ? (min_a1 >= 1.0) : (min_q1 >= (static_cast<int64_t>(1) << 32));
         if (g->bp_passes > 64) {
             delete g;
             return fail(PS_EUNSUPPORTED, "detector bins finer than 1/32 pixel are not supported");

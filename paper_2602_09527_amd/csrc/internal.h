@@ -98,6 +98,7 @@ struct ps_geometry {
     size_t off_a0, off_a1, off_a2, off_inv, off_ia1, off_row, off_q0, off_q1, off_q2, tab_bytes;
     void *dev;                            // uploaded tables (caller-owned), or null
     int bp_passes;                        // backprojector ray passes (see BackPlan)
+    bool gather_ok;                       // adjacent rays >= 1 pixel apart at every angle
     // angle lists, row-walked first: all angles, and subset i at order_sub[sub_off[i]..]
     std::vector<int32_t> order_full, order_sub, sub_off, nrow_sub;
     int nrow_full;
@@ -217,6 +218,8 @@ struct UpdateArgs {
 };
 BackPlan back_plan(const ps_geometry *g, int subset);
 size_t back_workspace(const ps_geometry *g, int subset);
+enum BackMethod { BP_SCATTER = 1, BP_GATHER = 2 };
+int back_method(const ps_geometry *g, int subset);   // BP_SCATTER or BP_GATHER
 struct BackCall {
     const ps_geometry *g;
     int subset;

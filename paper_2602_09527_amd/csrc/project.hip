@@ -81,7 +81,7 @@ struct ProjItem {
 
 template <typename T, int RPT>
 __global__ __launch_bounds__(kBlock) void k_project(WorkList<ProjItem<T>> wl) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     T *lds = reinterpret_cast<T *>(smem_raw);
     constexpr bool kFixed = std::is_same<T, float>::value;
 
@@ -169,11 +169,16 @@ __global__ __launch_bounds__(kBlock) void k_project(WorkList<ProjItem<T>> wl) {
 #pragma unroll
                     for (int u = 0; u < 8; ++u) {
                         if (e0 + u * kBlock < cnt) {
+                            // 16-byte aligned: stride and kPad are multiples of 4 words
                             T *dst = lds + tt[u] * stride + kPad + 4 * cc[u];
-                            dst[0] = v[u].a;
-                            dst[1] = v[u].b;
-                            dst[2] = v[u].c;
-                            dst[3] = v[u].d;
+                            if constexpr (std::is_same<T, float>::value) {
+                                *reinterpret_cast<float4 *>(dst) = make_float4(v[u].a, v[u].b, v[u].c, v[u].d);
+                            } else {
+                                dst[0] = v[u].a;
+                                dst[1] = v[u].b;
+                                dst[2] = v[u].c;
+                                dst[3] = v[u].d;
+                            }
                         }
                     }
                 }

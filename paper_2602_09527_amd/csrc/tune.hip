@@ -6,6 +6,7 @@
 // inner iterations per 2D launch (temporal blocking depth).  None of them changes what is
 // computed; split and grouping change the order of floating-point sums.
 #include <algorithm>
+#include <array>
 #include <vector>
 
 #include "internal.h"
@@ -107,6 +108,8 @@ extern "C" ps_status geometry_get_plan(const ps_geometry *g, ps_plan *out) {
     out->bp_strip_full = bf.strip;
     out->bp_strip_subset = bs.strip;
     out->fgp_iters = fgp_iters_per_launch(g);
+    out->bp_method_full = back_method(g, -1);
+    out->bp_method_subset = back_method(g, 0);
     return PS_OK;
 }
 
@@ -124,6 +127,8 @@ extern "C" ps_status geometry_set_plan(ps_geometry *g, const ps_plan *p) {
         return fail(PS_EINVAL, "backprojector strip must be 0, 1, 2, 4 or 8");
     if (p->fgp_iters < 0 || p->fgp_iters > fgp_max_iters_of(g))
         return fail(PS_EINVAL, "fgp_iters must be in [0, %d]", fgp_max_iters_of(g));
+    if (p->bp_method_full < 0 || p->bp_method_full > 2 || p->bp_method_subset < 0 || p->bp_method_subset > 2)
+        return fail(PS_EINVAL, "bp_method must be 0 (automatic), 1 (scatter) or 2 (gather)");
     g->plan = *p;
     return PS_OK;
 }
@@ -188,32 +193,40 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
         (full ? best.proj_split_full : best.proj_split_subset) = best_s;
     }
 
-    // backprojector: (strip, groups) for all angles, then subset 0
+    // backprojector: scatter with (strip, groups), or the gather, for all angles then subset 0
     for (int full = 1; full >= 0; --full) {
         const int subset = full ? -1 : 0;
         g->plan = best;
+        const int auto_method = back_method(g, subset);
         const BackPlan auto_bp = back_plan(g, subset);
-        std::vector<std::pair<int, int>> cand{{auto_bp.strip, auto_bp.groups}};
+        // candidate (method, strip, groups); the automatic choice first
+        std::vector<std::array<int, 3>> cand;
+        if (auto_method == BP_GATHER) cand.push_back({BP_GATHER, 0, 0});
+        cand.push_back({BP_SCATTER, auto_bp.strip, auto_bp.groups});
         for (int s : {8, 4, 2})
             for (int G : {1, 2, 4, 8, 16})
-                if (!(s == auto_bp.strip && G == auto_bp.groups)) cand.push_back({s, G});
+                if (!(s == auto_bp.strip && G == auto_bp.groups)) cand.push_back({BP_SCATTER, s, G});
+        if (auto_method != BP_GATHER && g->gather_ok) cand.push_back({BP_GATHER, 0, 0});
         float best_ms = 0.f;
-        std::pair<int, int> pick = cand[0];
+        std::array<int, 3> pick = cand[0];
         const int r = reps;
         for (size_t c = 0; c < cand.size(); ++c) {
             ps_plan trial = best;
-            if (full) {
-                trial.bp_strip_full = cand[c].first;
-                trial.bp_groups_full = cand[c].second;
-            } else {
-                trial.bp_strip_subset = cand[c].first;
-                trial.bp_groups_subset = cand[c].second;
+            int &m = full ? trial.bp_method_full : trial.bp_method_subset;
+            int &st_ = full ? trial.bp_strip_full : trial.bp_strip_subset;
+            int &gr = full ? trial.bp_groups_full : trial.bp_groups_subset;
+            m = cand[c][0];
+            if (cand[c][0] == BP_SCATTER) {
+                st_ = cand[c][1];
+                gr = cand[c][2];
             }
             g->plan = trial;
-            const BackPlan bp = back_plan(g, subset);
-            // skip candidates the LDS budget or the angle count clamps to one already timed
-            if (c > 0 && (bp.strip != cand[c].first || bp.groups != cand[c].second)) continue;
-            if (back_workspace(g, subset) > L.bws_bytes) continue;
+            if (cand[c][0] == BP_SCATTER) {
+                const BackPlan bp = back_plan(g, subset);
+                // skip candidates the LDS budget or the angle count clamps to one already timed
+                if (c > 0 && (bp.strip != cand[c][1] || bp.groups != cand[c][2])) continue;
+                if (back_workspace(g, subset) > L.bws_bytes) continue;
+            }
             float ms = 0.f;
             PS_TRY(restore_on_error(time_calls([&] {
                 return launch_backproject(g, subset, w + L.y, w + L.img, BP_OVERWRITE, nullptr, w + L.bws,
@@ -226,11 +239,17 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
             if (c == 0 && full && ms > kLongLaunchMs) break;
         }
         if (full) {
-            best.bp_strip_full = pick.first;
-            best.bp_groups_full = pick.second;
+            best.bp_method_full = pick[0];
+            if (pick[0] == BP_SCATTER) {
+                best.bp_strip_full = pick[1];
+                best.bp_groups_full = pick[2];
+            }
         } else {
-            best.bp_strip_subset = pick.first;
-            best.bp_groups_subset = pick.second;
+            best.bp_method_subset = pick[0];
+            if (pick[0] == BP_SCATTER) {
+                best.bp_strip_subset = pick[1];
+                best.bp_groups_subset = pick[2];
+            }
         }
     }
 

@@ -131,6 +131,8 @@ def test_plan_get_set_and_validation(nat):
         assert auto.proj_split_full >= 1 and auto.proj_split_subset >= 1
         assert 1 <= auto.bp_groups_full <= 16 and auto.bp_strip_full in (1, 2, 4, 8)
         assert auto.fgp_iters == 8
+        # the scatter backprojector unless a plan asks for the gather
+        assert (auto.bp_method_full, auto.bp_method_subset) == (1, 1)
         forced = nat.Plan(proj_split_full=2, proj_split_subset=1, bp_groups_full=4,
                           bp_groups_subset=2, bp_strip_full=4, bp_strip_subset=2, fgp_iters=5)
         assert lib.geometry_set_plan(h, C.byref(forced)) == nat.PS_OK
@@ -140,7 +142,7 @@ def test_plan_get_set_and_validation(nat):
                 got.bp_groups_subset, got.bp_strip_full, got.bp_strip_subset, got.fgp_iters) == \
             (2, 1, 4, 2, 4, 2, 5)
         for bad in (dict(proj_split_full=-1), dict(bp_groups_subset=17), dict(bp_strip_full=3),
-                    dict(fgp_iters=9)):
+                    dict(fgp_iters=9), dict(bp_method_subset=3)):
             assert lib.geometry_set_plan(h, C.byref(nat.Plan(**bad))) == nat.PS_EINVAL
         # a rejected plan leaves the previous one in place
         assert lib.geometry_get_plan(h, C.byref(got)) == nat.PS_OK and got.fgp_iters == 5

@@ -173,3 +173,19 @@ def test_tv_prox_full_size_512(orc):
     dg = torch.zeros(g.dual_shape(), device="cuda")
     z = api.tv_prox(g, _dev(v, torch.float32), 2e-3, 50, nonneg=True, dual=dg)
     assert _rel(z.cpu().numpy(), zo) <= 1e-5
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float32, 1e-5), (torch.float64, 1e-12)])
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("method", [1, 2])
+def test_backproject_methods_parity(orc, shape, dtype, tol, method):
+    # both backprojector methods forced for all angles and for subsets (the gather applies where
+    # adjacent rays are at least one pixel apart; elsewhere the scatter serves the call)
+    from paper_2602_09527_amd import api
+    g, o = _pair(orc, shape, dtype)
+    g.set_plan(dict(bp_method_full=method, bp_method_subset=method))
+    rng = np.random.default_rng(40 + method)
+    for subset in [-1] + list(range(g.n_subsets)):
+        y = rng.standard_normal(g.sino_shape(subset))
+        x = api.backproject(g, _dev(y, dtype), subset).cpu().numpy()
+        assert _rel(x, orc.backproject(o, y, subset)) <= tol, (subset, method)

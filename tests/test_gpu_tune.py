@@ -24,6 +24,7 @@ def test_autotune_plan_valid_and_cached(tmp_path):
     assert 1 <= plan["proj_split_full"] <= 64 and 1 <= plan["proj_split_subset"] <= 64
     assert 1 <= plan["bp_groups_full"] <= 16 and plan["bp_strip_subset"] in (1, 2, 4, 8)
     assert 2 <= plan["fgp_iters"] <= 8
+    assert plan["bp_method_full"] in (1, 2) and plan["bp_method_subset"] in (1, 2)
     cache = json.load(open(tmp_path / "plans.json"))
     assert cache[g.key] == plan
     g2 = api.Geometry(256, 256, 360, 384, n_subsets=20)
@@ -32,9 +33,9 @@ def test_autotune_plan_valid_and_cached(tmp_path):
 
 @pytest.mark.parametrize("plan", [
     dict(proj_split_full=1, proj_split_subset=1, bp_groups_full=1, bp_groups_subset=1,
-         bp_strip_full=2, bp_strip_subset=1, fgp_iters=3),
+         bp_strip_full=2, bp_strip_subset=1, fgp_iters=3, bp_method_full=2, bp_method_subset=1),
     dict(proj_split_full=16, proj_split_subset=12, bp_groups_full=16, bp_groups_subset=8,
-         bp_strip_full=4, bp_strip_subset=8, fgp_iters=6),
+         bp_strip_full=4, bp_strip_subset=8, fgp_iters=6, bp_method_full=1, bp_method_subset=2),
 ])
 def test_forced_plans_keep_parity(orc, plan):
     from paper_2602_09527_amd import api
