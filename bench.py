@@ -176,6 +176,7 @@ def bench_batch(dev, log_fn, n_slices=64, epochs=10):
     w = workloads.SMALL_2D
     g = api.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=w.n_subsets, device=dev)
     L = stored_L(w) or api.lipschitz(g, 50)
+    api.autotune(g, reps=5)
     bs = []
     for j in range(n_slices):
         prob = synth.make_problem(w.nx, w.ny, w.n_angles, w.n_bins, seed=w.seed + 10 * j,
@@ -276,6 +277,8 @@ def main():
     L_gpu = api.lipschitz(g, 50)
     gamma = 1.0 / L_gpu
     log(f"bench: L (GPU power method) = {L_gpu:.6f}")
+    plan = api.autotune(g, reps=5)
+    log(f"bench: autotuned plan {plan}")
 
     def params(n_epochs, **kw):
         d = dict(gamma=gamma, p=p, alpha=w.alpha, fgp_inner=w.fgp_inner, n_epochs=n_epochs,
@@ -357,6 +360,7 @@ def main():
                    "bins": w.n_bins, "subsets": w.n_subsets, "p": p, "alpha": w.alpha,
                    "fgp_inner": w.fgp_inner, "method": "ProxSkip-SVRG"},
         "roofline": roofline,
+        "plan": plan,
         "projector_hbm_gbs": kern["project_full"]["algorithmic_gbs"],
         "kernels": kern,
     }

@@ -99,6 +99,7 @@ PS_API int32_t subset_size(const ps_geometry *geom, int32_t subset);
  *   bp_method_*    1 = ray-driven scatter into LDS strips + combine pass; 2 = pixel-driven gather
  *                  with the update fused (needs bins at least one pixel apart along every ray's
  *                  stepping axis, e.g. bin_width >= 1; otherwise scatter is used)
+ *   bp_gather_rows rows per wave of the gather's tiles (63 columns x 4 waves x rows): 2 or 4
  * "_full" applies to all-angle calls (subset = -1), "_subset" to single subsets. */
 typedef struct {
     int32_t proj_split_full, proj_split_subset;
@@ -106,6 +107,7 @@ typedef struct {
     int32_t bp_strip_full, bp_strip_subset;
     int32_t fgp_iters;
     int32_t bp_method_full, bp_method_subset;
+    int32_t bp_gather_rows;
 } ps_plan;
 
 /* The plan in effect (automatic choices filled in) / replace the overrides.  set: fields out of

@@ -21,6 +21,22 @@
 namespace ps {
 
 constexpr int kWave = 64;
+constexpr int kGatherTX = 63;   // output columns per gather tile (lane 0 of a wave is a halo)
+
+// Constants of one angle as the scatter kernel uses them, staged in LDS per workgroup.
+template <typename T>
+struct ScatterAngle {
+    int64_t q0, q1, q2;   // FP32 path (32.32 fixed point)
+    T a0, a1, a2;         // FP64 path
+    T inv;
+    int l;                // index within the call's angle list (row of y)
+};
+
+constexpr int kScatterAngles = 64;   // angle records staged in LDS at a time
+
+static size_t scatter_angle_bytes(size_t elem) {
+    return elem == sizeof(double) ? sizeof(ScatterAngle<double>) : sizeof(ScatterAngle<float>);
+}
 
 BackPlan back_plan(const ps_geometry *g, int subset) {
     const auto &d = g->desc;
@@ -46,7 +62,9 @@ BackPlan back_plan(const ps_geometry *g, int subset) {
     if (forced_g > 0) G = forced_g;
     G = std::max(1L, std::min<long>(G, std::min(16, std::max(1, most))));
     p.groups = static_cast<int>(G);
-    p.lds_bytes = static_cast<size_t>(p.waves) * p.strip * p.stride * g->elem;
+    const int per = (std::max(1, most) + p.groups - 1) / p.groups;   // angles per workgroup
+    p.lds_bytes = align_up(static_cast<size_t>(p.waves) * p.strip * p.stride * g->elem, 16) +
+                  static_cast<size_t>(std::min(per, kScatterAngles)) * scatter_angle_bytes(g->elem);
     p.part_elems = static_cast<size_t>(2) * p.groups * d.nx * d.ny * d.nz;
     return p;
 }
@@ -61,6 +79,15 @@ int back_method(const ps_geometry *g, int subset) {
     if (forced == BP_SCATTER || forced == BP_GATHER) return forced;
     // automatic: the scatter (faster on the workloads measured; the autotuner may pick the gather)
     return BP_SCATTER;
+}
+
+int gather_rows(const ps_geometry *g, int subset) {
+    const int forced = g->plan.bp_gather_rows;
+    if (forced == 2 || forced == 4) return forced;
+    // 4 rows per wave (tiles of 63 x 16) unless that leaves fewer than 512 workgroups
+    const auto &d = g->desc;
+    const long tiles4 = static_cast<long>((d.nx + kGatherTX - 1) / kGatherTX) * ((d.ny + 15) / 16) * d.nz;
+    return tiles4 < 512 ? 2 : 4;
 }
 
 // One backprojector application: partial images of A_sub^T y, one per (angle class, group).
@@ -108,20 +135,23 @@ __global__ __launch_bounds__(kBlock) void k_backproject(WorkList<BackItem<T>> wl
     const int e_hi = cls_lo + min(cls_cnt, (grp + 1) * per);
 
     for (int e = threadIdx.x; e < nw * strip * stride; e += blockDim.x) acc_all[e] = T(0);
-    __syncthreads();
+    // this workgroup's angles, staged once (the per-unit loads would otherwise wait on L2)
+    // this workgroup's angles, staged kScatterAngles at a time (per-unit loads of the tables would
+    // otherwise wait on L2 inside the deposit loop)
+    ScatterAngle<T> *angs = reinterpret_cast<ScatterAngle<T> *>(
+        smem_raw + ((static_cast<size_t>(nw) * strip * stride * sizeof(T) + 15) / 16) * 16);
     T *acc = acc_all + static_cast<size_t>(wave) * strip * stride;
 
     const int span = kWave * passes;               // rays per chunk
     const int chunks = (nbins + span - 1) / span;
-    const int units = max(0, e_hi - e_lo) * chunks;
     const uint32_t lim = static_cast<uint32_t>(ext + 2);
+    int units = 0;
 
     // ray values (y / |cos| or y / |sin|) of one work unit, for up to NP passes
     auto fetch = [&](int unit, T *yv) {
-        const int e = e_lo + unit / chunks, c = unit % chunks;
-        const int l = order[e];
-        const int k = subset < 0 ? l : subset + l * nsub;
-        const T inv = tab.inv[k];
+        const int e = unit / chunks, c = unit % chunks;
+        const int l = angs[e].l;
+        const T inv = angs[e].inv;
         const T *yl = yz + static_cast<size_t>(l) * nbins;
 #pragma unroll
         for (int pass = 0; pass < (NP > 0 ? NP : 1); ++pass) {
@@ -131,14 +161,12 @@ __global__ __launch_bounds__(kBlock) void k_backproject(WorkList<BackItem<T>> wl
     };
     // deposit one pass of one unit: rays u = c * span + pass + passes * lane
     auto deposit = [&](int unit, int pass, T y0) {
-        const int e = e_lo + unit / chunks, c = unit % chunks;
-        const int l = order[e];
-        const int k = subset < 0 ? l : subset + l * nsub;
+        const int e = unit / chunks, c = unit % chunks;
         const int u = c * span + pass + passes * lane;
         if constexpr (kFixed) {
             const T y1 = y0 * T(0x1p-32f);
-            const int64_t q2 = tab.q2[k];
-            int64_t q = tab.q0[k] + (static_cast<int64_t>(2) << 32) + static_cast<int64_t>(u) * tab.q1[k] +
+            const int64_t q2 = angs[e].q2;
+            int64_t q = angs[e].q0 + (static_cast<int64_t>(2) << 32) + static_cast<int64_t>(u) * angs[e].q1 +
                         static_cast<int64_t>(t_lo) * q2;
             if (nt == kStrip) {
                 // all reads of the strip's rows first (rows never alias), then the writes
@@ -172,7 +200,7 @@ __global__ __launch_bounds__(kBlock) void k_backproject(WorkList<BackItem<T>> wl
                 }
             }
         } else {
-            const T a0 = tab.a0[k], a1 = tab.a1[k], a2 = tab.a2[k];
+            const T a0 = angs[e].a0, a1 = angs[e].a1, a2 = angs[e].a2;
             for (int t = 0; t < nt; ++t) {
                 const T q = fma(static_cast<T>(u), a1, fma(static_cast<T>(t_lo + t), a2, a0));
                 const T fl = floor(q);
@@ -186,31 +214,49 @@ __global__ __launch_bounds__(kBlock) void k_backproject(WorkList<BackItem<T>> wl
         }
     };
 
-    if constexpr (NP > 0) {
-        // software pipeline: the next unit's ray values are in flight while this one deposits
-        T ynext[NP];
-        int unit = wave;
-        if (unit < units) fetch(unit, ynext);
-        while (unit < units) {
-            T ycur[NP];
-#pragma unroll
-            for (int q = 0; q < NP; ++q) ycur[q] = ynext[q];
-            const int nxt = unit + nw;
-            if (nxt < units) fetch(nxt, ynext);
-#pragma unroll
-            for (int pass = 0; pass < NP; ++pass) deposit(unit, pass, ycur[pass]);
-            unit = nxt;
+    for (int a0 = e_lo; a0 < e_hi; a0 += kScatterAngles) {
+        const int an = min(kScatterAngles, e_hi - a0);
+        __syncthreads();  // accumulators zeroed / the previous angles' records no longer read
+        for (int e = threadIdx.x; e < an; e += blockDim.x) {
+            ScatterAngle<T> ra;
+            ra.l = order[a0 + e];
+            const int k = subset < 0 ? ra.l : subset + ra.l * nsub;
+            ra.q0 = tab.q0[k];
+            ra.q1 = tab.q1[k];
+            ra.q2 = tab.q2[k];
+            ra.a0 = tab.a0[k];
+            ra.a1 = tab.a1[k];
+            ra.a2 = tab.a2[k];
+            ra.inv = tab.inv[k];
+            angs[e] = ra;
         }
-    } else {
-        for (int unit = wave; unit < units; unit += nw) {
-            const int e = e_lo + unit / chunks, c = unit % chunks;
-            const int l = order[e];
-            const int k = subset < 0 ? l : subset + l * nsub;
-            const T inv = tab.inv[k];
-            const T *yl = yz + static_cast<size_t>(l) * nbins;
-            for (int pass = 0; pass < passes; ++pass) {
-                const int u = c * span + pass + passes * lane;
-                deposit(unit, pass, u < nbins ? yl[u] * inv : T(0));
+        __syncthreads();
+        units = an * chunks;
+        if constexpr (NP > 0) {
+            // software pipeline: the next unit's ray values are in flight while this one deposits
+            T ynext[NP];
+            int unit = wave;
+            if (unit < units) fetch(unit, ynext);
+            while (unit < units) {
+                T ycur[NP];
+#pragma unroll
+                for (int q = 0; q < NP; ++q) ycur[q] = ynext[q];
+                const int nxt = unit + nw;
+                if (nxt < units) fetch(nxt, ynext);
+#pragma unroll
+                for (int pass = 0; pass < NP; ++pass) deposit(unit, pass, ycur[pass]);
+                unit = nxt;
+            }
+        } else {
+            for (int unit = wave; unit < units; unit += nw) {
+                const int e = unit / chunks, c = unit % chunks;
+                const int l = angs[e].l;
+                const T inv = angs[e].inv;
+                const T *yl = yz + static_cast<size_t>(l) * nbins;
+                for (int pass = 0; pass < passes; ++pass) {
+                    const int u = c * span + pass + passes * lane;
+                    deposit(unit, pass, u < nbins ? yl[u] * inv : T(0));
+                }
             }
         }
     }
@@ -309,25 +355,26 @@ __global__ __launch_bounds__(kBlock) void k_backproject_combine(WorkList<Combine
     }
 }
 
-// ---- pixel-driven gather (subsets) ------------------------------------------------------------
+// ---- pixel-driven gather ---------------------------------------------------------------------
 //
-// A workgroup owns a tile of 64 columns x 16 rows of one slice (lane = column, each wave 4 rows)
-// and sums, for every pixel, the contributions of all the call's angles directly: no partial
-// images, and the epilogue (the SVRG / ProxSkip step) is applied in the same kernel.
-//   Pixel (i, j) receives from ray u of an angle the weight the projector gives it: with
-//   p the pixel's coordinate along the interpolation axis (j for row-walked angles, i for
-//   column-walked ones) and s along the stepping axis, the ray's cell at step s is
-//   c = floor(q(u, s)) and its weight w = frac(q): the pixel gets (1 - w) y_u / |.| if c = p and
-//   w y_u / |.| if c = p - 1 -- the same 32.32 fixed-point q (FP32) or FMA-evaluated q (FP64),
-//   the same products as the scatter kernel, so A^T stays the projector's transpose.
-//   When adjacent rays are at least one pixel apart (|a1| >= 1), at most two rays have c in
-//   {p - 1, p}, and they are among the three integers around u* = (p - a0 - s a2) / a1; each
-//   candidate is checked exactly.
+// A workgroup owns a tile of 63 columns x 16 rows of one slice and sums, for every pixel, the
+// contributions of all the call's angles directly: no partial images, and the epilogue (the
+// SVRG / ProxSkip step) is applied in the same kernel.
+//   Pixel (i, j) receives from ray u of an angle the weight the projector gives it.  With p the
+//   pixel's coordinate along the interpolation axis (j for row-walked angles, i for column-walked
+//   ones) and s along the stepping axis, ray u's cell at step s is c = floor(q(u, s)) with weight
+//   w = frac(q): the pixel gets (1 - w) y_u / |.| from the ray with c = p and w y_u / |.| from the
+//   ray with c = p - 1 -- the same 32.32 fixed-point q (FP32) or FMA-evaluated q (FP64) and the
+//   same products as the scatter kernel, so A^T stays the projector's transpose.
+//   When adjacent rays are at least one pixel apart (|a1| >= 1) a cell holds at most one ray
+//   (FP32: exact fixed point; FP64 rounding can put two in one cell, and both are taken), found
+//   among the two integers around u* = (p - a0 - s a2) / a1 (each checked exactly).  Each
+//   lane finds the ray of its own cell; the ray of cell p - 1 is its neighbour's: the lane to the
+//   left for row-walked angles (a DPP lane shift; lane 0 is a halo column that only supplies
+//   this), the lane's previous row for column-walked ones (one extra lookup per wave).
 //   The rays an angle can send into the tile form a window of at most kGatherWin consecutive
 //   bins; the windows of up to kGatherChunk angles (y / |.|, zero outside [0, B)) are staged in
 //   LDS at a time.
-constexpr int kGatherRows = 4;                     // rows per wave
-constexpr int kGatherTX = 64, kGatherTY = 4 * kGatherRows;
 constexpr int kGatherChunk = 32;
 constexpr int kGatherWin = 96;
 
@@ -341,18 +388,136 @@ struct GatherItem {
 };
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_backproject_gather(WorkList<GatherItem<T>> wl) {
+struct GatherAngle {
+    int row;
+    int cs, co;       // candidate rule: uf = cs * floor(cr * u* + 1/64) + co (see cell_ray)
+    T a0, a1, a2, ia1, cr, inv;
+    int64_t q0, q1, q2;
+};
+
+// Wave-uniform copies (readfirstlane) of values every lane holds alike, so that arithmetic on
+// them runs on the scalar unit.
+__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline float uni(float v) { return __builtin_bit_cast(float, uni(__builtin_bit_cast(int, v))); }
+__device__ inline int64_t uni(int64_t v) {
+    const uint64_t u = static_cast<uint64_t>(v);
+    return static_cast<int64_t>((static_cast<uint64_t>(static_cast<uint32_t>(uni(static_cast<int>(u >> 32)))) << 32) |
+                                static_cast<uint32_t>(uni(static_cast<int>(u & 0xffffffffu))));
+}
+__device__ inline double uni(double v) { return __builtin_bit_cast(double, uni(__builtin_bit_cast(int64_t, v))); }
+
+template <typename T>
+__device__ inline GatherAngle<T> uni(const GatherAngle<T> &g) {
+    GatherAngle<T> r;
+    r.row = uni(g.row);
+    r.cs = uni(g.cs);
+    r.co = uni(g.co);
+    r.cr = uni(g.cr);
+    r.inv = uni(g.inv);
+    r.a0 = uni(g.a0);
+    r.a1 = uni(g.a1);
+    r.a2 = uni(g.a2);
+    r.ia1 = uni(g.ia1);
+    r.q0 = uni(g.q0);
+    r.q1 = uni(g.q1);
+    r.q2 = uni(g.q2);
+    return r;
+}
+
+template <typename T>
+__device__ inline GatherAngle<T> gather_angle(const AngleTab<T> &tab, int k) {
+    GatherAngle<T> g;
+    g.row = tab.row[k];
+    g.a0 = tab.a0[k];
+    g.a1 = tab.a1[k];
+    g.a2 = tab.a2[k];
+    g.ia1 = tab.ia1[k];
+    g.q0 = tab.q0[k];
+    g.q1 = tab.q1[k];
+    g.q2 = tab.q2[k];
+    g.inv = tab.inv[k];
+    const bool up = g.a1 > T(0);
+    g.cr = up ? T(-1) : T(1);
+    g.cs = up ? -1 : 1;
+    g.co = up ? 0 : -1;
+    return g;
+}
+
+__device__ inline float lane_from_left(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, false));
+}
+__device__ inline double lane_from_left(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(__double2loint(v)), 0x138, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(__double2hiint(v)), 0x138, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// The ray of cell p at step s: its two deposits, own = (1 - w) y and next = w y (zero when the
+// cell holds no ray).  c = fma(s, a2, a0) and base = q0 + s q2 are the step's constants; ub is
+// the first bin of the staged window yw.
+template <typename T>
+__device__ inline void cell_ray(const GatherAngle<T> &ga, int p, T c, int64_t base, const T *yw, int ub,
+                                T &own, T &next) {
     constexpr bool kFixed = std::is_same<T, float>::value;
+    // q(u) = c + u a1 is in [p, p + 1) for the bins in [u*, u* + 1/a1) (a1 > 0) or
+    // (u* + 1/a1, u*] (a1 < 0), u* = (p - c) / a1: an interval of length <= 1 holding at most the
+    // integer ceil(u*) (resp. floor(u*)).  Candidates uf and uf + 1 with uf = ceil(u* - 1/64)
+    // (resp. floor(u* + 1/64) - 1) contain it whatever the rounding of u* (|error| < 1e-3).
+    // branch-free: ceil(u* - 1/64) = -floor(1/64 - u*)
+    const T us = (static_cast<T>(p) - c) * ga.ia1;
+    const int uf = ga.cs * static_cast<int>(floor(fma(us, ga.cr, T(0.015625)))) + ga.co;
+    int u;
+    T w;
+    bool hit;
+    if constexpr (kFixed) {
+        const int64_t Q0 = base + static_cast<int64_t>(uf) * ga.q1;
+        const int64_t Q1 = Q0 + ga.q1;
+        const bool h0 = static_cast<int>(Q0 >> 32) == p;
+        hit = h0 || static_cast<int>(Q1 >> 32) == p;
+        u = h0 ? uf : uf + 1;
+        w = static_cast<T>(static_cast<uint32_t>(h0 ? Q0 : Q1));
+    } else {
+        // FP64 positions are rounded: with |a1| = 1 two adjacent rays can land in one cell (for
+        // instance q = -1 - 6e-17 rounds to -1 while the next ray has q = -6e-17), so every
+        // candidate in the cell contributes, as in the scatter
+        own = next = T(0);
+#pragma unroll
+        for (int cnd = 0; cnd < 2; ++cnd) {
+            const T q = fma(static_cast<T>(uf + cnd), ga.a1, c);
+            const T fl = floor(q);
+            if (static_cast<int>(fl) == p) {
+                const T y0 = yw[min(max(uf + cnd - ub, 0), kGatherWin - 1)];
+                const T m = (q - fl) * y0;
+                own += y0 - m;
+                next += m;
+            }
+        }
+        return;
+    }
+    const int widx = min(max(u - ub, 0), kGatherWin - 1);
+    const T y0 = yw[widx];
+    // the scatter's products: m = lo(Q) * (y * 2^-32)
+    const T m = w * (y0 * T(0x1p-32f));
+    own = hit ? y0 - m : T(0);
+    next = hit ? m : T(0);
+}
+
+template <typename T, int R>
+__global__ __launch_bounds__(kBlock) void k_backproject_gather(WorkList<GatherItem<T>> wl) {
+    constexpr int kGatherRows = R;                 // rows per wave
+    constexpr int kGatherTY = 4 * R;               // rows per tile
     __shared__ T ywin[kGatherChunk][kGatherWin];
     __shared__ int ulo[kGatherChunk];
+    __shared__ GatherAngle<T> s_ang[kGatherChunk];
     int local;
     const GatherItem<T> &it = wl.item[work_item(wl, local)];
     const AngleTab<T> &tab = it.tab;
     const int tx = local % it.tiles_x, ty = (local / it.tiles_x) % it.tiles_y;
     const int z = local / (it.tiles_x * it.tiles_y);
-    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x / kWave));
     const int nx = it.nx, ny = it.ny, B = it.nbins;
-    const int j = tx * kGatherTX + lane;
+    const int j = tx * kGatherTX - 1 + lane;           // lane 0: halo column
     const int i0 = ty * kGatherTY + wave * kGatherRows;
     const T *yz = it.y + static_cast<size_t>(z) * it.na * B;
     T acc[kGatherRows];
@@ -367,72 +532,67 @@ __global__ __launch_bounds__(kBlock) void k_backproject_gather(WorkList<GatherIt
             // interpolation axis, over the tile's span of the stepping axis
             const int l = c0 + threadIdx.x;
             const int k = it.subset < 0 ? l : it.subset + l * it.nsub;
-            const bool row = tab.row[k] != 0;
-            const T a0 = tab.a0[k], a2 = tab.a2[k], ia1 = tab.ia1[k];
-            const int d_lo = row ? tx * kGatherTX : ty * kGatherTY;
-            const int d_hi = d_lo + (row ? kGatherTX : kGatherTY) - 1;
-            const int s_lo = row ? ty * kGatherTY : tx * kGatherTX;
-            const int s_hi = s_lo + (row ? kGatherTY : kGatherTX) - 1;
+            const GatherAngle<T> ga = gather_angle(tab, k);
+            s_ang[threadIdx.x] = ga;   // the angle's constants, read below by every wave
+            const bool row = ga.row != 0;
+            const T a0 = ga.a0, a2 = ga.a2, ia1 = ga.ia1;
+            const int col_lo = tx * kGatherTX - 1, col_hi = col_lo + 63;
+            const int row_lo = ty * kGatherTY - 1, row_hi = row_lo + kGatherTY;
+            const int d_lo = row ? col_lo : row_lo, d_hi = row ? col_hi : row_hi;
+            const int s_lo = row ? row_lo : col_lo, s_hi = row ? row_hi : col_hi;
             const T qa = static_cast<T>(d_lo - 1) - a0, qb = static_cast<T>(d_hi + 1) - a0;
             const T u1 = (qa - static_cast<T>(s_lo) * a2) * ia1, u2 = (qa - static_cast<T>(s_hi) * a2) * ia1;
             const T u3 = (qb - static_cast<T>(s_lo) * a2) * ia1, u4 = (qb - static_cast<T>(s_hi) * a2) * ia1;
-            const T umin = min(min(u1, u2), min(u3, u4));
-            ulo[threadIdx.x] = static_cast<int>(floor(umin)) - 3;
+            ulo[threadIdx.x] = static_cast<int>(floor(min(min(u1, u2), min(u3, u4)))) - 3;
         }
         __syncthreads();
         for (int e = threadIdx.x; e < cn * kGatherWin; e += blockDim.x) {
             const int a = e / kGatherWin, w = e - a * kGatherWin;
             const int l = c0 + a;
-            const int k = it.subset < 0 ? l : it.subset + l * it.nsub;
             const int u = ulo[a] + w;
-            ywin[a][w] = (u >= 0 && u < B) ? yz[static_cast<size_t>(l) * B + u] * tab.inv[k] : T(0);
+            ywin[a][w] = (u >= 0 && u < B) ? yz[static_cast<size_t>(l) * B + u] * s_ang[a].inv : T(0);
         }
         __syncthreads();
+        // the next angle's record is read while this one is processed
+        GatherAngle<T> raw = s_ang[0];
+        int raw_ub = ulo[0];
         for (int a = 0; a < cn; ++a) {
-            const int l = c0 + a;
-            const int k = it.subset < 0 ? l : it.subset + l * it.nsub;
-            const bool row = tab.row[k] != 0;
-            const T a0 = tab.a0[k], a1 = tab.a1[k], a2 = tab.a2[k], ia1 = tab.ia1[k];
-            const int ub = ulo[a];
+            const GatherAngle<T> ga = uni(raw);
+            const int ub = uni(raw_ub);
+            if (a + 1 < cn) {
+                raw = s_ang[a + 1];
+                raw_ub = ulo[a + 1];
+            }
             const T *yw = ywin[a];
+            if (ga.row) {
+                // interpolation along the row: cell p = j; the ray of cell j - 1 is the left lane's
 #pragma unroll
-            for (int r = 0; r < kGatherRows; ++r) {
-                const int i = i0 + r;
-                const int p = row ? j : i, s = row ? i : j;
-                // u* biased up by 1/64: candidates floor(u*) - 1 .. + 1 then cover every ray
-                // with c in {p - 1, p} whatever the rounding of u* (|error| < 1e-3)
-                const T ua = (static_cast<T>(p) - fma(static_cast<T>(s), a2, a0)) * ia1 + T(0.015625);
-                const int uf = static_cast<int>(floor(ua)) - 1;
-                T contrib = T(0);
-                if constexpr (kFixed) {
-                    const int64_t q1 = tab.q1[k];
-                    int64_t Q = tab.q0[k] + static_cast<int64_t>(s) * tab.q2[k] + static_cast<int64_t>(uf) * q1;
-#pragma unroll
-                    for (int cnd = 0; cnd < 3; ++cnd) {
-                        const int h = static_cast<int>(Q >> 32) - p;
-                        const int widx = min(max(uf + cnd - ub, 0), kGatherWin - 1);
-                        const T y0 = yw[widx];
-                        const T m = static_cast<T>(static_cast<uint32_t>(Q)) * (y0 * T(0x1p-32f));
-                        contrib += h == 0 ? y0 - m : (h == -1 ? m : T(0));
-                        Q += q1;
-                    }
-                } else {
-#pragma unroll
-                    for (int cnd = 0; cnd < 3; ++cnd) {
-                        const T q = fma(static_cast<T>(uf + cnd), a1, fma(static_cast<T>(s), a2, a0));
-                        const T fl = floor(q);
-                        const int h = static_cast<int>(fl) - p;
-                        const int widx = min(max(uf + cnd - ub, 0), kGatherWin - 1);
-                        const T y0 = yw[widx];
-                        const T m = (q - fl) * y0;
-                        contrib += h == 0 ? y0 - m : (h == -1 ? m : T(0));
-                    }
+                for (int r = 0; r < kGatherRows; ++r) {
+                    const int i = i0 + r;
+                    const T c = fma(static_cast<T>(i), ga.a2, ga.a0);
+                    const int64_t base = ga.q0 + static_cast<int64_t>(i) * ga.q2;
+                    T own, next;
+                    cell_ray(ga, j, c, base, yw, ub, own, next);
+                    acc[r] += own + lane_from_left(next);
                 }
-                acc[r] += contrib;
+            } else {
+                // interpolation along the column: cell p = i; the ray of cell i - 1 is the
+                // previous row's, so each wave also looks up the row above its first
+                const T c = fma(static_cast<T>(j), ga.a2, ga.a0);
+                const int64_t base = ga.q0 + static_cast<int64_t>(j) * ga.q2;
+                T own, prev;
+                cell_ray(ga, i0 - 1, c, base, yw, ub, own, prev);
+#pragma unroll
+                for (int r = 0; r < kGatherRows; ++r) {
+                    T next;
+                    cell_ray(ga, i0 + r, c, base, yw, ub, own, next);
+                    acc[r] += own + prev;
+                    prev = next;
+                }
             }
         }
     }
-    if (j >= nx) return;
+    if (lane == 0 || j >= nx) return;
     const size_t plane = static_cast<size_t>(nx) * ny;
 #pragma unroll
     for (int r = 0; r < kGatherRows; ++r) {
@@ -495,12 +655,16 @@ static ps_status backproject_many_t(const BackCall *calls, int n, hipStream_t st
     std::vector<BackItem<T>> items;
     std::vector<BackPlan> plans;
     std::vector<int> call_of;
-    ListBuilder<GatherItem<T>> gl;
-    auto flush_gather = [&]() -> ps_status {
-        if (gl.empty()) return PS_OK;
-        hipLaunchKernelGGL((k_backproject_gather<T>), dim3(gl.blocks), dim3(kBlock), 0, st, gl.wl);
+    ListBuilder<GatherItem<T>> gl[2];   // rows per wave 2 and 4
+    auto flush_gather = [&](int which) -> ps_status {
+        ListBuilder<GatherItem<T>> &b = gl[which];
+        if (b.empty()) return PS_OK;
+        if (which == 0)
+            hipLaunchKernelGGL((k_backproject_gather<T, 2>), dim3(b.blocks), dim3(kBlock), 0, st, b.wl);
+        else
+            hipLaunchKernelGGL((k_backproject_gather<T, 4>), dim3(b.blocks), dim3(kBlock), 0, st, b.wl);
         PS_LAUNCHED("k_backproject_gather");
-        gl.clear();
+        b.clear();
         return PS_OK;
     };
     for (int c = 0; c < n; ++c) {
@@ -521,13 +685,15 @@ static ps_status backproject_many_t(const BackCall *calls, int n, hipStream_t st
             gi.nx = d.nx;
             gi.ny = d.ny;
             gi.nbins = d.n_bins;
+            const int rows = gather_rows(g, bc.subset);
+            const int which = rows == 2 ? 0 : 1;
             gi.tiles_x = (d.nx + kGatherTX - 1) / kGatherTX;
-            gi.tiles_y = (d.ny + kGatherTY - 1) / kGatherTY;
+            gi.tiles_y = (d.ny + 4 * rows - 1) / (4 * rows);
             gi.mode = bc.mode;
             const long blocks = static_cast<long>(gi.tiles_x) * gi.tiles_y * d.nz;
             if (blocks > (1L << 30)) return fail(PS_EUNSUPPORTED, "backprojector grid too large");
-            gl.add(gi, static_cast<int>(blocks));
-            if (gl.full()) PS_TRY(flush_gather());
+            gl[which].add(gi, static_cast<int>(blocks));
+            if (gl[which].full()) PS_TRY(flush_gather(which));
             continue;
         }
         const BackPlan bp = back_plan(g, bc.subset);
@@ -606,7 +772,8 @@ static ps_status backproject_many_t(const BackCall *calls, int n, hipStream_t st
         hipLaunchKernelGGL((k_backproject_combine<T>), dim3(lb.blocks), dim3(kBlock), 0, st, lb.wl);
         PS_LAUNCHED("k_backproject_combine");
     }
-    return flush_gather();
+    PS_TRY(flush_gather(0));
+    return flush_gather(1);
 }
 
 ps_status launch_backproject_many(const BackCall *calls, int n, hipStream_t st) {

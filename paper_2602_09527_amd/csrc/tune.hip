@@ -110,6 +110,7 @@ extern "C" ps_status geometry_get_plan(const ps_geometry *g, ps_plan *out) {
     out->fgp_iters = fgp_iters_per_launch(g);
     out->bp_method_full = back_method(g, -1);
     out->bp_method_subset = back_method(g, 0);
+    out->bp_gather_rows = gather_rows(g, 0);
     return PS_OK;
 }
 
@@ -129,6 +130,8 @@ extern "C" ps_status geometry_set_plan(ps_geometry *g, const ps_plan *p) {
         return fail(PS_EINVAL, "fgp_iters must be in [0, %d]", fgp_max_iters_of(g));
     if (p->bp_method_full < 0 || p->bp_method_full > 2 || p->bp_method_subset < 0 || p->bp_method_subset > 2)
         return fail(PS_EINVAL, "bp_method must be 0 (automatic), 1 (scatter) or 2 (gather)");
+    if (p->bp_gather_rows != 0 && p->bp_gather_rows != 2 && p->bp_gather_rows != 4)
+        return fail(PS_EINVAL, "bp_gather_rows must be 0, 2 or 4");
     g->plan = *p;
     return PS_OK;
 }
@@ -201,12 +204,14 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
         const BackPlan auto_bp = back_plan(g, subset);
         // candidate (method, strip, groups); the automatic choice first
         std::vector<std::array<int, 3>> cand;
-        if (auto_method == BP_GATHER) cand.push_back({BP_GATHER, 0, 0});
+        if (auto_method == BP_GATHER) cand.push_back({BP_GATHER, gather_rows(g, subset), 0});
         cand.push_back({BP_SCATTER, auto_bp.strip, auto_bp.groups});
         for (int s : {8, 4, 2})
             for (int G : {1, 2, 4, 8, 16})
                 if (!(s == auto_bp.strip && G == auto_bp.groups)) cand.push_back({BP_SCATTER, s, G});
-        if (auto_method != BP_GATHER && g->gather_ok) cand.push_back({BP_GATHER, 0, 0});
+        if (g->gather_ok)
+            for (int rows : {2, 4})
+                if (!(auto_method == BP_GATHER && rows == gather_rows(g, subset))) cand.push_back({BP_GATHER, rows, 0});
         float best_ms = 0.f;
         std::array<int, 3> pick = cand[0];
         const int r = reps;
@@ -219,6 +224,8 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
             if (cand[c][0] == BP_SCATTER) {
                 st_ = cand[c][1];
                 gr = cand[c][2];
+            } else {
+                trial.bp_gather_rows = cand[c][1];
             }
             g->plan = trial;
             if (cand[c][0] == BP_SCATTER) {
@@ -249,6 +256,8 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
             if (pick[0] == BP_SCATTER) {
                 best.bp_strip_subset = pick[1];
                 best.bp_groups_subset = pick[2];
+            } else {
+                best.bp_gather_rows = pick[1];   // the subset calls dominate: their tile height
             }
         }
     }

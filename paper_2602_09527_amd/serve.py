@@ -74,11 +74,13 @@ def make_trace(n_requests: int, rate: float, seed: int, sides=workloads.SERVE_SI
 
 
 class GeometryCache:
-    """One geometry (device tables) and step size gamma = 1/L per request shape."""
+    """One geometry per request shape: device tables, autotuned launch plans and the step size
+    gamma = 1/L (power method), all prepared once."""
 
-    def __init__(self, device, power_iters: int = 30):
+    def __init__(self, device, power_iters: int = 30, tune: bool = True):
         self.device = torch.device(device)
         self.power_iters = power_iters
+        self.tune = tune
         self._g = {}
 
     def get(self, r: Request):
@@ -86,6 +88,8 @@ class GeometryCache:
         if e is None:
             g = api.Geometry(r.side, r.side, r.n_angles, r.n_bins, n_subsets=r.n_subsets,
                              device=self.device)
+            if self.tune:
+                api.autotune(g, reps=3)   # launch plans of this shape, before any workspace
             e = (g, api.lipschitz(g, self.power_iters))
             self._g[r.key] = e
         return e
