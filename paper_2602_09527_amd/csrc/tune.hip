@@ -55,9 +55,9 @@ static TuneLayout tune_layout(const ps_geometry *g) {
     L.y = take(m * g->elem);
     L.img = take(n * g->elem);
     // the largest split any candidate can take, for all angles (subsets need less)
-    L.pws_bytes = static_cast<size_t>(proj_max_split(g)) * m * g->elem;
+    L.pws_bytes = align_up(static_cast<size_t>(proj_max_split(g)) * m * g->elem);
     L.pws = take(L.pws_bytes);
-    L.bws_bytes = 2 * 16 * n * g->elem;  // 2 classes x up to 16 groups of partial images
+    L.bws_bytes = align_up(2 * 16 * n * g->elem);  // 2 classes x up to 16 groups of partial images
     L.bws = take(L.bws_bytes);
     L.fws_bytes = fgp_workspace(g);
     L.fws = take(L.fws_bytes);

@@ -31,6 +31,22 @@ def test_autotune_plan_valid_and_cached(tmp_path):
     assert api.autotune(g2, cache_path=str(tmp_path / "plans.json")) == plan
 
 
+@pytest.mark.parametrize("shape", [(64, 48, 30, 45, 4, 1, torch.float32), (37, 23, 29, 41, 4, 3, torch.float32),
+                                   (60, 52, 45, 70, 5, 1, torch.float64)])
+def test_autotune_odd_shapes(orc, shape):
+    # sizes whose buffers are not multiples of the workspace alignment, a volume, FP64
+    from paper_2602_09527_amd import api
+    nx, ny, A, B, N, nz, dt = shape
+    g = api.Geometry(nx, ny, A, B, n_subsets=N, nz=nz, dtype=dt)
+    plan = api.autotune(g, reps=1)
+    assert plan == g.get_plan()
+    o = orc.Geometry(nx, ny, A, B, n_subsets=N, nz=nz)
+    rng = np.random.default_rng(9)
+    y = rng.standard_normal((nz, A, B))
+    x = api.backproject(g, torch.from_numpy(y).to("cuda", dt), -1).cpu().numpy()
+    assert _rel(x, orc.backproject(o, y, -1)) <= (1e-5 if dt == torch.float32 else 1e-12)
+
+
 @pytest.mark.parametrize("plan", [
     dict(proj_split_full=1, proj_split_subset=1, bp_groups_full=1, bp_groups_subset=1,
          bp_strip_full=2, bp_strip_subset=1, fgp_iters=3, bp_method_full=2, bp_method_subset=1),
