@@ -44,6 +44,9 @@ ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 OPS_PROJECT = 6
 OPS_BACKPROJECT = 7
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_backproject_2d-512-a720_traffic.txt")
+# launch plans tuned once on an MI355X (python -m paper_2602_09527_amd.tune_plans); a geometry
+# missing from the file is tuned on the spot
+PLANS_FILE = os.path.join(ROOT, "paper_2602_09527_amd", "plans_mi355x.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2602_09527_amd", "csrc", "backproject.hip")
 
 
@@ -176,7 +179,7 @@ def bench_batch(dev, log_fn, n_slices=64, epochs=10):
     w = workloads.SMALL_2D
     g = api.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=w.n_subsets, device=dev)
     L = stored_L(w) or api.lipschitz(g, 50)
-    api.autotune(g, reps=5)
+    api.autotune(g, reps=5, cache_path=PLANS_FILE, store=False)
     bs = []
     for j in range(n_slices):
         prob = synth.make_problem(w.nx, w.ny, w.n_angles, w.n_bins, seed=w.seed + 10 * j,
@@ -277,8 +280,8 @@ def main():
     L_gpu = api.lipschitz(g, 50)
     gamma = 1.0 / L_gpu
     log(f"bench: L (GPU power method) = {L_gpu:.6f}")
-    plan = api.autotune(g, reps=5)
-    log(f"bench: autotuned plan {plan}")
+    plan = api.autotune(g, reps=5, cache_path=PLANS_FILE, store=False)
+    log(f"bench: launch plan {plan}")
 
     def params(n_epochs, **kw):
         d = dict(gamma=gamma, p=p, alpha=w.alpha, fgp_inner=w.fgp_inner, n_epochs=n_epochs,

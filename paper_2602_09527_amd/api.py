@@ -319,11 +319,13 @@ def sample_sequences(seed: int, k0: int, count: int, n_subsets: int, p: float):
     return sub[:count], coin[:count]
 
 
-def autotune(g: Geometry, reps: int = 5, cache_path: str | None = None) -> dict:
+def autotune(g: Geometry, reps: int = 5, cache_path: str | None = None, store: bool = True,
+             tune_missing: bool = True) -> dict:
     """Time candidate launch plans on the device and keep the fastest (see geometry_autotune).
 
-    With ``cache_path`` (a JSON file), a plan tuned earlier for the same geometry key is reused
-    and a newly tuned one is stored."""
+    With ``cache_path`` (a JSON file keyed by Geometry.key), a plan stored for the same geometry
+    is used as is; otherwise the geometry is tuned (unless tune_missing is False, which keeps
+    the automatic plan) and, with ``store``, the new plan is added to the file."""
     import json
     import os
     if cache_path and os.path.exists(cache_path):
@@ -332,6 +334,8 @@ def autotune(g: Geometry, reps: int = 5, cache_path: str | None = None) -> dict:
         if g.key in cache:
             g.set_plan(cache[g.key])
             return g.get_plan()
+    if not tune_missing:
+        return g.get_plan()
     nbytes = g.lib.geometry_autotune_workspace_bytes(g.handle)
     ws = torch.empty(nbytes, dtype=torch.uint8, device=g.device)
     p = nat.Plan()
@@ -340,7 +344,7 @@ def autotune(g: Geometry, reps: int = 5, cache_path: str | None = None) -> dict:
     del ws
     g._ws = {}
     plan = {f: getattr(p, f) for f, _ in nat.Plan._fields_}
-    if cache_path:
+    if cache_path and store:
         cache = {}
         if os.path.exists(cache_path):
             with open(cache_path) as f:

@@ -74,19 +74,27 @@ struct Timer {
     }
 };
 
-// Mean milliseconds per call of fn over `reps` calls after one warm-up call.
+// Milliseconds per call of fn: the median of three rounds of `reps` calls, after one warm-up call.
 template <typename F>
 static ps_status time_calls(F &&fn, int reps, hipStream_t st, Timer &tm, float *ms) {
     PS_TRY(fn());
-    PS_HIP(hipEventRecord(tm.e0, st));
-    for (int r = 0; r < reps; ++r) PS_TRY(fn());
-    PS_HIP(hipEventRecord(tm.e1, st));
-    PS_HIP(hipEventSynchronize(tm.e1));
-    float t = 0.f;
-    PS_HIP(hipEventElapsedTime(&t, tm.e0, tm.e1));
-    *ms = t / static_cast<float>(std::max(reps, 1));
+    float t[3];
+    for (int round = 0; round < 3; ++round) {
+        PS_HIP(hipEventRecord(tm.e0, st));
+        for (int r = 0; r < reps; ++r) PS_TRY(fn());
+        PS_HIP(hipEventRecord(tm.e1, st));
+        PS_HIP(hipEventSynchronize(tm.e1));
+        PS_HIP(hipEventElapsedTime(&t[round], tm.e0, tm.e1));
+        t[round] /= static_cast<float>(std::max(reps, 1));
+    }
+    std::sort(t, t + 3);
+    *ms = t[1];
     return PS_OK;
 }
+
+// A candidate replaces the automatic plan (always the first candidate timed) only when it is
+// at least this much faster, so timing noise does not move plans between runs.
+constexpr float kMinGain = 0.97f;
 
 // An all-angle launch (run once per epoch, at the snapshot) longer than this keeps the automatic
 // plan: timing its alternatives would cost seconds on volumes.
@@ -187,7 +195,7 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
             PS_TRY(restore_on_error(time_calls([&] {
                 return launch_project(g, subset, w + L.x, nullptr, nullptr, w + L.y, w + L.pws, L.pws_bytes, st);
             }, r, st, tm, &ms)));
-            if (c == 0 || ms < best_ms) {
+            if (c == 0 || ms < best_ms * (best_s == cand[0] ? kMinGain : 1.0f)) {
                 best_ms = ms;
                 best_s = cand[c];
             }
@@ -239,7 +247,7 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
                 return launch_backproject(g, subset, w + L.y, w + L.img, BP_OVERWRITE, nullptr, w + L.bws,
                                           L.bws_bytes, st);
             }, r, st, tm, &ms)));
-            if (c == 0 || ms < best_ms) {
+            if (c == 0 || ms < best_ms * (pick == cand[0] ? kMinGain : 1.0f)) {
                 best_ms = ms;
                 pick = cand[c];
             }
@@ -278,7 +286,7 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
             PS_TRY(restore_on_error(time_calls([&] {
                 return launch_fgp(g, w + L.x, w + L.dual, 1e-3, 50, 1, o, w + L.fws, L.fws_bytes, st);
             }, reps, st, tm, &ms)));
-            if (pick == 0 || ms < best_ms) {
+            if (pick == 0 || ms < best_ms * (pick == tmax ? kMinGain : 1.0f)) {
                 best_ms = ms;
                 pick = T;
             }

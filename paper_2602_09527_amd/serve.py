@@ -19,6 +19,7 @@ from __future__ import annotations
 
 import collections
 import ctypes as C
+import os
 import dataclasses
 import threading
 import time
@@ -27,6 +28,8 @@ import numpy as np
 import torch
 
 from . import api, synth, workloads
+
+PLANS_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "plans_mi355x.json")
 
 
 @dataclasses.dataclass(frozen=True)
@@ -89,7 +92,8 @@ class GeometryCache:
             g = api.Geometry(r.side, r.side, r.n_angles, r.n_bins, n_subsets=r.n_subsets,
                              device=self.device)
             if self.tune:
-                api.autotune(g, reps=3)   # launch plans of this shape, before any workspace
+                # launch plans of this shape, before any workspace: stored ones when present
+                api.autotune(g, reps=3, cache_path=PLANS_FILE, store=False)
             e = (g, api.lipschitz(g, self.power_iters))
             self._g[r.key] = e
         return e
