@@ -116,8 +116,10 @@ PS_API ps_status geometry_get_plan(const ps_geometry *geom, ps_plan *out);
 PS_API ps_status geometry_set_plan(ps_geometry *geom, const ps_plan *plan);
 
 /* Autotuner: time candidate plans of the projector, backprojector and 2D FGP on this geometry
- * (HIP events on `stream`, `reps` timed launches each after one warm-up launch, synthetic
- * inputs), keep the fastest of each, store them as the geometry's plan and return it in `out`.
+ * (HIP events on `stream`; per candidate one warm-up launch, then the median of three rounds of
+ * `reps` launches; synthetic inputs), keep the fastest of each -- a candidate must beat the
+ * automatic plan by 3% to replace it -- store them as the geometry's plan and return it in
+ * `out`.
  * Synchronises `stream`.  workspace: device scratch of geometry_autotune_workspace_bytes bytes.
  * The geometry must be uploaded.  Errors: PS_EINVAL, PS_EHIP. */
 PS_API size_t geometry_autotune_workspace_bytes(const ps_geometry *geom);
