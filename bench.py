@@ -116,6 +116,8 @@ def bench_volume(args):
     torch.cuda.synchronize()
     log(f"bench: volume data {tuple(b.shape)} in {time.time() - t0:.1f} s")
     g = api.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=w.n_subsets, nz=w.nz, device=dev)
+    plan = api.autotune(g, reps=2, cache_path=PLANS_FILE, store=False, tune_missing=False)
+    log(f"bench: launch plan {plan}")
     L = stored_L(w) or api.lipschitz(g, 20)
     K, W = args.steps, args.warmup
     prm = api.SolverParams(gamma=1.0 / L, p=w.p, alpha=w.alpha, fgp_inner=w.fgp_inner,
@@ -145,6 +147,12 @@ def bench_volume(args):
     ysub = torch.empty(g.sino_shape(0), device=dev)
     img = torch.empty_like(s.x)
     dual = torch.zeros(g.dual_shape(), device=dev)
+    # achievable HBM rate for reference: a 1 GiB device-to-device copy (read + write bytes)
+    src_ = torch.ones(256 * 1024 * 1024, device=dev)
+    dst_ = torch.empty_like(src_)
+    t_copy = event_time(lambda: dst_.copy_(src_), reps=5)
+    copy_gbs = 2.0 * src_.numel() * 4 / t_copy / 1e9
+    del src_, dst_
     t_fp = event_time(lambda: api.project(g, s.x, 0, out=ysub))
     t_bp = event_time(lambda: api.backproject(g, ysub, 0, out=img))
     t_tv = event_time(lambda: api.tv_prox(g, s.x, 1e-4, w.fgp_inner, dual=dual, out=img), reps=1)
@@ -156,6 +164,7 @@ def bench_volume(args):
         "metric": METRIC, "value": round(K / el, 4), "unit": "epochs/s", "n_gpus": 1, "steps": K,
         "warmup": W, "ms_per_step": round(1e3 * el / K, 2), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "plan": plan,
         "config": {"workload": w.name, "volume": f"{w.nz}x{w.ny}x{w.nx}", "angles": w.n_angles,
                    "bins": w.n_bins, "subsets": w.n_subsets, "p": w.p, "alpha": w.alpha,
                    "fgp_inner": w.fgp_inner, "tv": "3D isotropic", "noise": w.noise},
@@ -166,6 +175,8 @@ def bench_volume(args):
             "tv_prox_50_ms": round(t_tv * 1e3, 3),
             "tv_prox_algorithmic_gbs": round(fgp_bytes / t_tv / 1e9, 1),
             "tv_prox_hbm_frac": round(fgp_bytes / t_tv / 1e9 / HBM_PEAK_GBS, 4),
+            "device_copy_gbs": round(copy_gbs, 1),
+            "tv_prox_frac_of_copy": round(fgp_bytes / t_tv / 1e9 / copy_gbs, 4),
         },
     }
     print(json.dumps(out), flush=True)

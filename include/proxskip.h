@@ -100,6 +100,7 @@ PS_API int32_t subset_size(const ps_geometry *geom, int32_t subset);
  *                  with the update fused (needs bins at least one pixel apart along every ray's
  *                  stepping axis, e.g. bin_width >= 1; otherwise scatter is used)
  *   bp_gather_rows rows per wave of the gather's tiles (63 columns x 4 waves x rows): 2 or 4
+ *   fgp3d_chunk    slices each workgroup of the 3D FGP marches through: 1..256 (default 4)
  * "_full" applies to all-angle calls (subset = -1), "_subset" to single subsets. */
 typedef struct {
     int32_t proj_split_full, proj_split_subset;
@@ -108,6 +109,7 @@ typedef struct {
     int32_t fgp_iters;
     int32_t bp_method_full, bp_method_subset;
     int32_t bp_gather_rows;
+    int32_t fgp3d_chunk;
 } ps_plan;
 
 /* The plan in effect (automatic choices filled in) / replace the overrides.  set: fields out of

@@ -45,7 +45,8 @@ class Plan(C.Structure):
                 ("bp_groups_full", C.c_int32), ("bp_groups_subset", C.c_int32),
                 ("bp_strip_full", C.c_int32), ("bp_strip_subset", C.c_int32),
                 ("fgp_iters", C.c_int32), ("bp_method_full", C.c_int32),
-                ("bp_method_subset", C.c_int32), ("bp_gather_rows", C.c_int32)]
+                ("bp_method_subset", C.c_int32), ("bp_gather_rows", C.c_int32),
+                ("fgp3d_chunk", C.c_int32)]
 
 
 class SolverParams(C.Structure):

@@ -284,6 +284,162 @@ __global__ __launch_bounds__(kBlock) void k_fgp3d_dual(
     }
 }
 
+// One whole 3D FGP iteration per launch:
+//     r = pa + c (pa - pb),  z = P_C(v - tau D^T r),  pn = P_unit(r + step D z)
+// without storing z.  A workgroup owns a tile of 62 columns x 14 rows (plus a halo of one on
+// each side: lane = column, each wave 4 rows) and marches along z over a chunk of slices (the
+// plan's fgp3d_chunk, 4 by default: short chunks spread the workgroups' accesses over more
+// of the volume at once, which measured faster than the halo re-reads they add),
+// keeping the previous slice's r and z in registers: every voxel's 7 inputs are read once and
+// its 3 outputs written once (40 B/voxel in FP32, plus the halo's re-reads from L2).
+//   z at (x, y, s) needs r_x at x - 1 (DPP from the left lane), r_y at y - 1 (the previous row
+//   register, or the wave above through LDS) and r_z at s - 1 (the previous step's register);
+//   pn at (x, y, s - 1) needs z at x + 1 (DPP from the right lane), y + 1 and s, so the output
+//   of a step is the slice before the one it computes z for.  Forward differences are zero at
+//   the last index and the divergence's missing neighbours are zero, as in the 2D kernel.
+constexpr int kF3Rows = 4;                    // rows per wave
+constexpr int kF3TX = 62, kF3TY = 4 * kF3Rows - 2;   // output columns and rows per tile
+constexpr int kF3Chunk = 4;                   // output slices per workgroup (default)
+
+template <typename T>
+struct Fgp3Args {
+    const T *v, *pa, *pb;
+    T *pn;
+    int nx, ny, nz, tiles_x, tiles_y, chunk;
+    T c, tau, step;
+    int nonneg;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fgp3d_iter(Fgp3Args<T> a) {
+    __shared__ T xch[2][kFgpWaves][kFgpEX];
+    const int lane = threadIdx.x % kFgpEX;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x / kFgpEX));
+    const int b = blockIdx.x;
+    const int tx = b % a.tiles_x, ty = (b / a.tiles_x) % a.tiles_y, zc = b / (a.tiles_x * a.tiles_y);
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const size_t plane = static_cast<size_t>(nx) * ny, n = plane * nz;
+    const int gx = tx * kF3TX - 1 + lane;                 // lane 0 and 63: halo columns
+    const int gy0 = ty * kF3TY - 1 + wave * kF3Rows;      // row of this wave's first register row
+    const bool col_in = gx >= 0 && gx < nx;
+    const int s_lo = zc * a.chunk, s_hi = min(nz, s_lo + a.chunk);
+    const T c = a.c, tau = a.tau, step = a.step;
+
+    T rx[kF3Rows], ry[kF3Rows], rz[kF3Rows], rzp[kF3Rows], zz[kF3Rows];
+    T prx[kF3Rows], pry[kF3Rows], prz[kF3Rows], pz[kF3Rows];   // slice s - 1
+    bool in[kF3Rows];
+#pragma unroll
+    for (int r = 0; r < kF3Rows; ++r) {
+        const int gy = gy0 + r;
+        in[r] = col_in && gy >= 0 && gy < ny;
+        rzp[r] = T(0);
+        prx[r] = pry[r] = prz[r] = pz[r] = T(0);
+    }
+    // r_z at slice s_lo - 1 (the only component of that slice that z(s_lo) needs)
+    if (s_lo > 0) {
+#pragma unroll
+        for (int r = 0; r < kF3Rows; ++r) {
+            if (!in[r]) continue;
+            const size_t e = static_cast<size_t>(s_lo - 1) * plane + static_cast<size_t>(gy0 + r) * nx + gx;
+            const T pa_ = a.pa[e + 2 * n], pb_ = a.pb[e + 2 * n];
+            rzp[r] = fma(c, pa_ - pb_, pa_);
+        }
+    }
+    const T *__restrict__ pa = a.pa;
+    const T *__restrict__ pb = a.pb;
+    const T *__restrict__ vp = a.v;
+    T *__restrict__ pn = a.pn;
+    // inputs of one slice, loaded one step ahead of their use
+    T lax[kF3Rows], lbx[kF3Rows], lay[kF3Rows], lby[kF3Rows], laz[kF3Rows], lbz[kF3Rows], lv[kF3Rows];
+    auto load_slice = [&](int s) {
+#pragma unroll
+        for (int r = 0; r < kF3Rows; ++r) {
+            lax[r] = lbx[r] = lay[r] = lby[r] = laz[r] = lbz[r] = lv[r] = T(0);
+            if (in[r] && s < nz) {
+                const size_t e = static_cast<size_t>(s) * plane + static_cast<size_t>(gy0 + r) * nx + gx;
+                lax[r] = pa[e];
+                lbx[r] = pb[e];
+                lay[r] = pa[e + n];
+                lby[r] = pb[e + n];
+                laz[r] = pa[e + 2 * n];
+                lbz[r] = pb[e + 2 * n];
+                lv[r] = vp[e];
+            }
+        }
+    };
+    load_slice(s_lo);
+    // steps s = s_lo .. s_hi (the last computes z only, for the output slice s_hi - 1)
+    for (int s = s_lo; s <= s_hi; ++s) {
+        const bool have = s < nz;
+        // r and v at slice s, then the next slice's loads go out
+        T vv[kF3Rows];
+#pragma unroll
+        for (int r = 0; r < kF3Rows; ++r) {
+            rx[r] = fma(c, lax[r] - lbx[r], lax[r]);
+            ry[r] = fma(c, lay[r] - lby[r], lay[r]);
+            rz[r] = fma(c, laz[r] - lbz[r], laz[r]);
+            vv[r] = lv[r];
+        }
+        if (s < s_hi) load_slice(s + 1);
+        // z at slice s: needs r_y of the row above (previous wave's last row)
+        __syncthreads();
+        xch[0][wave][lane] = ry[kF3Rows - 1];
+        __syncthreads();
+        const T ry_above = wave > 0 ? xch[0][wave - 1][lane] : T(0);
+#pragma unroll
+        for (int r = 0; r < kF3Rows; ++r) {
+            // D^T r: the last index's dual component has no difference to pair with
+            const int gy = gy0 + r;
+            const T rxl = lane_from_left(rx[r]);
+            const T ryu = r > 0 ? ry[r - 1] : ry_above;
+            const T rxh = gx < nx - 1 ? rx[r] : T(0);
+            const T ryh = gy < ny - 1 ? ry[r] : T(0);
+            const T rzh = s < nz - 1 ? rz[r] : T(0);
+            T zv = vv[r] - tau * (((rxl - rxh) + (ryu - ryh)) + (rzp[r] - rzh));
+            if (a.nonneg && zv < T(0)) zv = T(0);
+            zz[r] = (in[r] && have) ? zv : T(0);
+        }
+        // pn at slice s - 1: needs z at x + 1, y + 1 (next wave's first row) and s
+        if (s > s_lo) {
+            xch[1][wave][lane] = pz[0];
+            __syncthreads();
+            const T z_below = wave < kFgpWaves - 1 ? xch[1][wave + 1][lane] : T(0);
+#pragma unroll
+            for (int r = 0; r < kF3Rows; ++r) {
+                const int gy = gy0 + r;
+                const T zr = lane_from_right(pz[r]);
+                const T zb = r < kF3Rows - 1 ? pz[r + 1] : z_below;
+                const T dzx = gx < nx - 1 ? zr - pz[r] : T(0);
+                const T dzy = gy < ny - 1 ? zb - pz[r] : T(0);
+                const T dzz = s - 1 < nz - 1 ? zz[r] - pz[r] : T(0);
+                T ux = fma(step, dzx, prx[r]), uy = fma(step, dzy, pry[r]), uz = fma(step, dzz, prz[r]);
+                const T nrm = sqrt(ux * ux + uy * uy + uz * uz);
+                if (nrm > T(1)) {
+                    ux /= nrm;
+                    uy /= nrm;
+                    uz /= nrm;
+                }
+                const bool out = in[r] && lane >= 1 && lane <= kF3TX && gy >= ty * kF3TY &&
+                                 gy < ty * kF3TY + kF3TY;
+                if (out) {
+                    const size_t e = static_cast<size_t>(s - 1) * plane + static_cast<size_t>(gy) * nx + gx;
+                    pn[e] = ux;
+                    pn[e + n] = uy;
+                    pn[e + 2 * n] = uz;
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < kF3Rows; ++r) {
+            prx[r] = rx[r];
+            pry[r] = ry[r];
+            prz[r] = rz[r];
+            pz[r] = zz[r];
+            rzp[r] = rz[r];
+        }
+    }
+}
+
 // tau = 0: z = P_C(v) (and the ProxSkip outputs).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_prox_identity(const T *__restrict__ v, size_t n, int nonneg,
@@ -504,17 +660,31 @@ static ps_status fgp_single_t(const FgpCall &c, hipStream_t st) {
     const T *pb = dual_in, *pa = dual_in;
     T *rot[3] = {buf[0], buf[1], buf[2]};
     int next = 0;
+    Fgp3Args<T> fa{};
+    fa.v = vin;
+    fa.nx = d.nx;
+    fa.ny = d.ny;
+    fa.nz = d.nz;
+    fa.tiles_x = (d.nx + kF3TX - 1) / kF3TX;
+    fa.tiles_y = (d.ny + kF3TY - 1) / kF3TY;
+    fa.tau = tauT;
+    fa.step = stepT;
+    fa.nonneg = c.nonneg;
+    fa.chunk = g->plan.fgp3d_chunk > 0 ? g->plan.fgp3d_chunk : kF3Chunk;
+    const long f3_blocks = static_cast<long>(fa.tiles_x) * fa.tiles_y * ((d.nz + fa.chunk - 1) / fa.chunk);
+    if (f3_blocks > (1L << 30)) return fail(PS_EUNSUPPORTED, "3D TV grid too large");
+    (void)mid;
+    (void)zscratch;
     for (int k = 1; k <= K; ++k) {
-        const T cc = static_cast<T>(cs[k]);
-        hipLaunchKernelGGL((k_fgp3d_primal<T>), dim3(gr), dim3(kBlock), 0, st, vin, pa, pb, cc, d.nx,
-                           d.ny, d.nz, tauT, c.nonneg, zscratch, mid);
-        PS_LAUNCHED("k_fgp3d_primal");
         T *pn = rot[next];
         if (pn == pa || pn == pb) pn = rot[(next + 1) % 3];
         if (pn == pa || pn == pb) pn = rot[(next + 2) % 3];
-        hipLaunchKernelGGL((k_fgp3d_dual<T>), dim3(gr), dim3(kBlock), 0, st, zscratch, pa, pb, cc,
-                           d.nx, d.ny, d.nz, stepT, pn);
-        PS_LAUNCHED("k_fgp3d_dual");
+        fa.pa = pa;
+        fa.pb = pb;
+        fa.pn = pn;
+        fa.c = static_cast<T>(cs[k]);
+        hipLaunchKernelGGL((k_fgp3d_iter<T>), dim3(static_cast<unsigned>(f3_blocks)), dim3(kBlock), 0, st, fa);
+        PS_LAUNCHED("k_fgp3d_iter");
         pb = pa;
         pa = pn;
         next = (next + 1) % 3;

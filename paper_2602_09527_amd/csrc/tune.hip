@@ -39,6 +39,20 @@ static int proj_max_split(const ps_geometry *g) {
     return std::max(1, std::max(g->desc.nx, g->desc.ny) / (2 * p.strip));
 }
 
+// All-angle launches are tuned only when they are short (they run once per epoch, at the
+// snapshot); beyond this many samples (A B max(nx, ny) nz) the automatic plan is kept and the
+// scratch is sized for single subsets only.
+constexpr double kFullTuneSamples = 4.0e9;
+// Backprojector angle groups tried on images above this many voxels (2 x G partial images).
+constexpr size_t kBigImage = static_cast<size_t>(1) << 26;
+
+static bool tune_full(const ps_geometry *g) {
+    const auto &d = g->desc;
+    return static_cast<double>(d.n_angles) * d.n_bins * std::max(d.nx, d.ny) * d.nz <= kFullTuneSamples;
+}
+
+static int max_groups(const ps_geometry *g) { return n_image(g) > kBigImage ? 4 : 16; }
+
 struct TuneLayout {
     size_t x, y, img, pws, bws, fws, dual, total;
     size_t pws_bytes, bws_bytes, fws_bytes;
@@ -47,17 +61,19 @@ struct TuneLayout {
 static TuneLayout tune_layout(const ps_geometry *g) {
     const auto &d = g->desc;
     const size_t n = n_image(g);
-    const size_t m = static_cast<size_t>(d.nz) * d.n_angles * d.n_bins;
+    const int a_tuned = tune_full(g) ? d.n_angles : max_subset_count(g);
+    const size_t m = static_cast<size_t>(d.nz) * a_tuned * d.n_bins;
     TuneLayout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes); return o; };
     L.x = take(n * g->elem);
     L.y = take(m * g->elem);
     L.img = take(n * g->elem);
-    // the largest split any candidate can take, for all angles (subsets need less)
+    // the largest split any candidate can take, for the largest call tuned
     L.pws_bytes = align_up(static_cast<size_t>(proj_max_split(g)) * m * g->elem);
     L.pws = take(L.pws_bytes);
-    L.bws_bytes = align_up(2 * 16 * n * g->elem);  // 2 classes x up to 16 groups of partial images
+    // 2 angle classes x the most groups tried, of partial images
+    L.bws_bytes = align_up(2 * static_cast<size_t>(max_groups(g)) * n * g->elem);
     L.bws = take(L.bws_bytes);
     L.fws_bytes = fgp_workspace(g);
     L.fws = take(L.fws_bytes);
@@ -119,6 +135,7 @@ extern "C" ps_status geometry_get_plan(const ps_geometry *g, ps_plan *out) {
     out->bp_method_full = back_method(g, -1);
     out->bp_method_subset = back_method(g, 0);
     out->bp_gather_rows = gather_rows(g, 0);
+    out->fgp3d_chunk = g->plan.fgp3d_chunk > 0 ? g->plan.fgp3d_chunk : 4;
     return PS_OK;
 }
 
@@ -140,6 +157,7 @@ extern "C" ps_status geometry_set_plan(ps_geometry *g, const ps_plan *p) {
         return fail(PS_EINVAL, "bp_method must be 0 (automatic), 1 (scatter) or 2 (gather)");
     if (p->bp_gather_rows != 0 && p->bp_gather_rows != 2 && p->bp_gather_rows != 4)
         return fail(PS_EINVAL, "bp_gather_rows must be 0, 2 or 4");
+    if (p->fgp3d_chunk < 0 || p->fgp3d_chunk > 256) return fail(PS_EINVAL, "fgp3d_chunk must be in [0, 256]");
     g->plan = *p;
     return PS_OK;
 }
@@ -176,11 +194,13 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
     const int splits[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64};
     const int max_split = proj_max_split(g);
 
-    // projector: all angles, then subset 0
-    for (int full = 1; full >= 0; --full) {
+    const int first_pass = tune_full(g) ? 1 : 0;
+    // projector: all angles (when short), then subset 0
+    for (int full = first_pass; full >= 0; --full) {
         const int subset = full ? -1 : 0;
         float best_ms = 0.f;
         int best_s = 0;
+        bool have = false;
         g->plan = best;
         const int auto_split = full ? proj_plan(g, d.n_angles).split : proj_plan(g, max_subset_count(g)).split;
         std::vector<int> cand{auto_split};
@@ -195,17 +215,19 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
             PS_TRY(restore_on_error(time_calls([&] {
                 return launch_project(g, subset, w + L.x, nullptr, nullptr, w + L.y, w + L.pws, L.pws_bytes, st);
             }, r, st, tm, &ms)));
-            if (c == 0 || ms < best_ms * (best_s == cand[0] ? kMinGain : 1.0f)) {
+            if (!have || ms < best_ms * (best_s == cand[0] ? kMinGain : 1.0f)) {
                 best_ms = ms;
                 best_s = cand[c];
+                have = true;
             }
             if (c == 0 && full && ms > kLongLaunchMs) break;
         }
         (full ? best.proj_split_full : best.proj_split_subset) = best_s;
     }
 
-    // backprojector: scatter with (strip, groups), or the gather, for all angles then subset 0
-    for (int full = 1; full >= 0; --full) {
+    // backprojector: scatter with (strip, groups), or the gather, for all angles (when short)
+    // then subset 0
+    for (int full = first_pass; full >= 0; --full) {
         const int subset = full ? -1 : 0;
         g->plan = best;
         const int auto_method = back_method(g, subset);
@@ -216,12 +238,14 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
         cand.push_back({BP_SCATTER, auto_bp.strip, auto_bp.groups});
         for (int s : {8, 4, 2})
             for (int G : {1, 2, 4, 8, 16})
-                if (!(s == auto_bp.strip && G == auto_bp.groups)) cand.push_back({BP_SCATTER, s, G});
+                if (G <= max_groups(g) && !(s == auto_bp.strip && G == auto_bp.groups))
+                    cand.push_back({BP_SCATTER, s, G});
         if (g->gather_ok)
             for (int rows : {2, 4})
                 if (!(auto_method == BP_GATHER && rows == gather_rows(g, subset))) cand.push_back({BP_GATHER, rows, 0});
         float best_ms = 0.f;
         std::array<int, 3> pick = cand[0];
+        bool have = false;
         const int r = reps;
         for (size_t c = 0; c < cand.size(); ++c) {
             ps_plan trial = best;
@@ -247,9 +271,10 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
                 return launch_backproject(g, subset, w + L.y, w + L.img, BP_OVERWRITE, nullptr, w + L.bws,
                                           L.bws_bytes, st);
             }, r, st, tm, &ms)));
-            if (c == 0 || ms < best_ms * (pick == cand[0] ? kMinGain : 1.0f)) {
+            if (!have || ms < best_ms * (pick == cand[0] ? kMinGain : 1.0f)) {
                 best_ms = ms;
                 pick = cand[c];
+                have = true;
             }
             if (c == 0 && full && ms > kLongLaunchMs) break;
         }
@@ -292,6 +317,28 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
             }
         }
         best.fgp_iters = pick;
+    }
+    // 3D FGP: slices per workgroup (10 inner iterations per timed call)
+    if (g->tv_dims == 3) {
+        PS_TRY(fill(g, w + L.dual, 3 * n, st));
+        float best_ms = 0.f;
+        int pick = 0;
+        for (int ch : {4, 6, 8, 2, 16}) {
+            ps_plan trial = best;
+            trial.fgp3d_chunk = ch;
+            g->plan = trial;
+            FgpOut o{};
+            o.z = w + L.img;
+            float ms = 0.f;
+            PS_TRY(restore_on_error(time_calls([&] {
+                return launch_fgp(g, w + L.x, w + L.dual, 1e-3, 10, 1, o, w + L.fws, L.fws_bytes, st);
+            }, reps, st, tm, &ms)));
+            if (pick == 0 || ms < best_ms * (pick == 4 ? kMinGain : 1.0f)) {
+                best_ms = ms;
+                pick = ch;
+            }
+        }
+        best.fgp3d_chunk = pick;
     }
     g->plan = best;
     if (out) PS_TRY(geometry_get_plan(g, out));

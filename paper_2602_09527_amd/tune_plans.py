@@ -22,7 +22,7 @@ DEFAULT_PATH = os.path.join(HERE, "plans_mi355x.json")
 def shapes():
     from . import workloads as w
     out = []
-    for wl in (w.SINGLE_2D, w.SMALL_2D, w.AUTOGRAD_BATCH, w.VOLUME_3D_REDUCED):
+    for wl in (w.SINGLE_2D, w.SMALL_2D, w.AUTOGRAD_BATCH, w.VOLUME_3D_REDUCED, w.VOLUME_3D):
         out.append(dict(nx=wl.nx, ny=wl.ny, nz=wl.nz, n_angles=wl.n_angles, n_bins=wl.n_bins,
                         n_subsets=wl.n_subsets))
     for side in w.SERVE_SIDES:
@@ -44,8 +44,10 @@ def main(argv=None):
         g = api.Geometry(s["nx"], s["ny"], s["n_angles"], s["n_bins"], n_subsets=s["n_subsets"],
                          nz=s["nz"])
         t0 = time.perf_counter()
-        plans[g.key] = api.autotune(g, reps=args.reps, store=False)
+        reps = args.reps if s["nz"] <= 64 else max(2, args.reps // 4)   # volumes: long launches
+        plans[g.key] = api.autotune(g, reps=reps, store=False)
         print(f"tune_plans: {g.key}: {plans[g.key]} ({time.perf_counter() - t0:.2f} s)", flush=True)
+        del g
     with open(args.out, "w") as f:
         json.dump(plans, f, indent=1, sort_keys=True)
     print(f"tune_plans: wrote {len(plans)} plans to {args.out}", flush=True)
