@@ -23,10 +23,22 @@ namespace ps {
 constexpr int kWave = 64;
 constexpr int kGatherTX = 63;   // output columns per gather tile (lane 0 of a wave is a halo)
 
+// Wave-uniform copies (readfirstlane) of values every lane holds alike, so that arithmetic on
+// them runs on the scalar unit.
+__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline float uni(float v) { return __builtin_bit_cast(float, uni(__builtin_bit_cast(int, v))); }
+__device__ inline int64_t uni(int64_t v) {
+    const uint64_t u = static_cast<uint64_t>(v);
+    return static_cast<int64_t>((static_cast<uint64_t>(static_cast<uint32_t>(uni(static_cast<int>(u >> 32)))) << 32) |
+                                static_cast<uint32_t>(uni(static_cast<int>(u & 0xffffffffu))));
+}
+__device__ inline double uni(double v) { return __builtin_bit_cast(double, uni(__builtin_bit_cast(int64_t, v))); }
+
 // Constants of one angle as the scatter kernel uses them, staged in LDS per workgroup.
 template <typename T>
 struct ScatterAngle {
-    int64_t q0, q1, q2;   // FP32 path (32.32 fixed point)
+    int64_t qb, q1, q2;   // FP32 path (32.32 fixed point): qb = position of bin 0 at the strip's
+                          // first step, plus the two pad words
     T a0, a1, a2;         // FP64 path
     T inv;
     int l;                // index within the call's angle list (row of y)
@@ -115,7 +127,8 @@ __global__ __launch_bounds__(kBlock) void k_backproject(WorkList<BackItem<T>> wl
     const int nbins = it.nbins, strip = it.strip, stride = it.stride, s_row = it.s_row;
     const int groups = it.groups, passes = it.passes, nrow = it.nrow;
     const int nw = blockDim.x / kWave;
-    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x / kWave));
+    const int lane = threadIdx.x % kWave;
     // workgroup -> (strip index, angle group, slice), strip fastest
     const int nstrips = s_row + it.s_col;
     const int sx = local % nstrips, grp = (local / nstrips) % groups, z = local / (nstrips * groups);
@@ -145,73 +158,82 @@ __global__ __launch_bounds__(kBlock) void k_backproject(WorkList<BackItem<T>> wl
     const int span = kWave * passes;               // rays per chunk
     const int chunks = (nbins + span - 1) / span;
     const uint32_t lim = static_cast<uint32_t>(ext + 2);
-    int units = 0;
+    const int lp = passes * lane;                  // this lane's bin within a pass of a chunk
 
-    // ray values (y / |cos| or y / |sin|) of one work unit, for up to NP passes
-    auto fetch = [&](int unit, T *yv) {
-        const int e = unit / chunks, c = unit % chunks;
-        const int l = angs[e].l;
-        const T inv = angs[e].inv;
-        const T *yl = yz + static_cast<size_t>(l) * nbins;
-#pragma unroll
-        for (int pass = 0; pass < (NP > 0 ? NP : 1); ++pass) {
-            const int u = c * span + pass + passes * lane;
-            yv[pass] = u < nbins ? yl[u] * inv : T(0);
+    // Work unit (e, c): staged angle e, rays c * span + pass + passes * lane of every pass.  The
+    // waves take units round robin; e and c are wave-uniform (scalar registers).
+    auto advance = [&](int &e, int &c) {
+        c += nw;
+        while (c >= chunks) {
+            c -= chunks;
+            ++e;
         }
     };
-    // deposit one pass of one unit: rays u = c * span + pass + passes * lane
-    auto deposit = [&](int unit, int pass, T y0) {
-        const int e = unit / chunks, c = unit % chunks;
-        const int u = c * span + pass + passes * lane;
-        if constexpr (kFixed) {
-            const T y1 = y0 * T(0x1p-32f);
-            const int64_t q2 = angs[e].q2;
-            int64_t q = angs[e].q0 + (static_cast<int64_t>(2) << 32) + static_cast<int64_t>(u) * angs[e].q1 +
-                        static_cast<int64_t>(t_lo) * q2;
-            if (nt == kStrip) {
-                // all reads of the strip's rows first (rows never alias), then the writes
-                T *cell[kStrip];
-                T c0[kStrip], c1[kStrip], m[kStrip];
+    // ray values (y / |cos| or y / |sin|) of one work unit, for up to NP passes
+    auto fetch = [&](int e, int c, T *yv) {
+        const int l = uni(angs[e].l);
+        const T inv = uni(angs[e].inv);
+        const T *yl = yz + static_cast<size_t>(l) * nbins + c * span;
+        const int room = nbins - c * span;
 #pragma unroll
-                for (int t = 0; t < kStrip; ++t) {
-                    cell[t] = acc + t * stride + min(static_cast<uint32_t>(q >> 32), lim);
-                    m[t] = static_cast<T>(static_cast<uint32_t>(q)) * y1;  // w y
-                    q += q2;
-                }
+        for (int pass = 0; pass < (NP > 0 ? NP : 1); ++pass)
+            yv[pass] = pass + lp < room ? yl[pass + lp] * inv : T(0);
+    };
+    // deposit one ray of value y0 through the strip; FP32: q = its fixed-point position at the
+    // strip's first step (plus the pad)
+    auto deposit_fixed = [&](int64_t q, int64_t q2, T y0) {
+        const T y1 = y0 * T(0x1p-32f);
+        if (nt == kStrip) {
+            // all reads of the strip's rows first (rows never alias), then the writes
+            T *cell[kStrip];
+            T c0[kStrip], c1[kStrip], m[kStrip];
 #pragma unroll
-                for (int t = 0; t < kStrip; ++t) {
-                    c0[t] = cell[t][0];
-                    c1[t] = cell[t][1];
-                }
+            for (int t = 0; t < kStrip; ++t) {
+                cell[t] = acc + t * stride + min(static_cast<uint32_t>(q >> 32), lim);
+                m[t] = static_cast<T>(static_cast<uint32_t>(q)) * y1;  // w y
+                q += q2;
+            }
 #pragma unroll
-                for (int t = 0; t < kStrip; ++t) {
-                    cell[t][0] = c0[t] + (y0 - m[t]);
-                    cell[t][1] = c1[t] + m[t];
-                }
-            } else {
-                for (int t = 0; t < nt; ++t) {
-                    const uint32_t idx = min(static_cast<uint32_t>(q >> 32), lim);
-                    const T mm = static_cast<T>(static_cast<uint32_t>(q)) * y1;
-                    T *cl = acc + t * stride + idx;
-                    const T a = cl[0], b = cl[1];
-                    cl[0] = a + (y0 - mm);
-                    cl[1] = b + mm;
-                    q += q2;
-                }
+            for (int t = 0; t < kStrip; ++t) {
+                c0[t] = cell[t][0];
+                c1[t] = cell[t][1];
+            }
+#pragma unroll
+            for (int t = 0; t < kStrip; ++t) {
+                cell[t][0] = c0[t] + (y0 - m[t]);
+                cell[t][1] = c1[t] + m[t];
             }
         } else {
-            const T a0 = angs[e].a0, a1 = angs[e].a1, a2 = angs[e].a2;
             for (int t = 0; t < nt; ++t) {
-                const T q = fma(static_cast<T>(u), a1, fma(static_cast<T>(t_lo + t), a2, a0));
-                const T fl = floor(q);
-                const uint32_t idx = min(static_cast<uint32_t>(static_cast<int>(fl) + 2), lim);
-                const T m = (q - fl) * y0;
-                T *cell = acc + t * stride + idx;
-                const T c0 = cell[0], c1 = cell[1];
-                cell[0] = c0 + (y0 - m);
-                cell[1] = c1 + m;
+                const uint32_t idx = min(static_cast<uint32_t>(q >> 32), lim);
+                const T mm = static_cast<T>(static_cast<uint32_t>(q)) * y1;
+                T *cl = acc + t * stride + idx;
+                const T a = cl[0], b = cl[1];
+                cl[0] = a + (y0 - mm);
+                cl[1] = b + mm;
+                q += q2;
             }
         }
+    };
+    auto deposit_float = [&](int e, int u, T y0) {
+        const T a0 = uni(angs[e].a0), a1 = uni(angs[e].a1), a2 = uni(angs[e].a2);
+        for (int t = 0; t < nt; ++t) {
+            const T q = fma(static_cast<T>(u), a1, fma(static_cast<T>(t_lo + t), a2, a0));
+            const T fl = floor(q);
+            const uint32_t idx = min(static_cast<uint32_t>(static_cast<int>(fl) + 2), lim);
+            const T m = (q - fl) * y0;
+            T *cell = acc + t * stride + idx;
+            const T c0 = cell[0], c1 = cell[1];
+            cell[0] = c0 + (y0 - m);
+            cell[1] = c1 + m;
+        }
+    };
+    // position of this lane's first ray of unit (e, c): qb + (c * span + passes * lane) q1
+    auto lane_q = [&](int e, int c, int64_t &q1, int64_t &q2) {
+        q1 = uni(angs[e].q1);
+        q2 = uni(angs[e].q2);
+        const uint64_t off = static_cast<uint64_t>(static_cast<uint32_t>(lp)) * static_cast<uint64_t>(q1);
+        return uni(angs[e].qb) + static_cast<int64_t>(c * span) * q1 + static_cast<int64_t>(off);
     };
 
     for (int a0 = e_lo; a0 < e_hi; a0 += kScatterAngles) {
@@ -221,9 +243,9 @@ __global__ __launch_bounds__(kBlock) void k_backproject(WorkList<BackItem<T>> wl
             ScatterAngle<T> ra;
             ra.l = order[a0 + e];
             const int k = subset < 0 ? ra.l : subset + ra.l * nsub;
-            ra.q0 = tab.q0[k];
             ra.q1 = tab.q1[k];
             ra.q2 = tab.q2[k];
+            ra.qb = tab.q0[k] + (static_cast<int64_t>(2) << 32) + static_cast<int64_t>(t_lo) * ra.q2;
             ra.a0 = tab.a0[k];
             ra.a1 = tab.a1[k];
             ra.a2 = tab.a2[k];
@@ -231,31 +253,49 @@ __global__ __launch_bounds__(kBlock) void k_backproject(WorkList<BackItem<T>> wl
             angs[e] = ra;
         }
         __syncthreads();
-        units = an * chunks;
+        int e = wave / chunks, c = wave - e * chunks;   // this wave's first unit
         if constexpr (NP > 0) {
             // software pipeline: the next unit's ray values are in flight while this one deposits
             T ynext[NP];
-            int unit = wave;
-            if (unit < units) fetch(unit, ynext);
-            while (unit < units) {
+            if (e < an) fetch(e, c, ynext);
+            while (e < an) {
                 T ycur[NP];
 #pragma unroll
                 for (int q = 0; q < NP; ++q) ycur[q] = ynext[q];
-                const int nxt = unit + nw;
-                if (nxt < units) fetch(nxt, ynext);
+                int en = e, cn = c;
+                advance(en, cn);
+                if (en < an) fetch(en, cn, ynext);
+                if constexpr (kFixed) {
+                    int64_t q1, q2;
+                    int64_t q = lane_q(e, c, q1, q2);
 #pragma unroll
-                for (int pass = 0; pass < NP; ++pass) deposit(unit, pass, ycur[pass]);
-                unit = nxt;
+                    for (int pass = 0; pass < NP; ++pass) {
+                        deposit_fixed(q, q2, ycur[pass]);
+                        q += q1;
+                    }
+                } else {
+#pragma unroll
+                    for (int pass = 0; pass < NP; ++pass) deposit_float(e, c * span + pass + lp, ycur[pass]);
+                }
+                e = en;
+                c = cn;
             }
         } else {
-            for (int unit = wave; unit < units; unit += nw) {
-                const int e = unit / chunks, c = unit % chunks;
-                const int l = angs[e].l;
-                const T inv = angs[e].inv;
+            for (; e < an; advance(e, c)) {
+                const int l = uni(angs[e].l);
+                const T inv = uni(angs[e].inv);
                 const T *yl = yz + static_cast<size_t>(l) * nbins;
+                int64_t q1 = 0, q2 = 0, q = 0;
+                if constexpr (kFixed) q = lane_q(e, c, q1, q2);
                 for (int pass = 0; pass < passes; ++pass) {
-                    const int u = c * span + pass + passes * lane;
-                    deposit(unit, pass, u < nbins ? yl[u] * inv : T(0));
+                    const int u = c * span + pass + lp;
+                    const T y0 = u < nbins ? yl[u] * inv : T(0);
+                    if constexpr (kFixed) {
+                        deposit_fixed(q, q2, y0);
+                        q += q1;
+                    } else {
+                        deposit_float(e, u, y0);
+                    }
                 }
             }
         }
@@ -394,17 +434,6 @@ struct GatherAngle {
     T a0, a1, a2, ia1, cr, inv;
     int64_t q0, q1, q2;
 };
-
-// Wave-uniform copies (readfirstlane) of values every lane holds alike, so that arithmetic on
-// them runs on the scalar unit.
-__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ inline float uni(float v) { return __builtin_bit_cast(float, uni(__builtin_bit_cast(int, v))); }
-__device__ inline int64_t uni(int64_t v) {
-    const uint64_t u = static_cast<uint64_t>(v);
-    return static_cast<int64_t>((static_cast<uint64_t>(static_cast<uint32_t>(uni(static_cast<int>(u >> 32)))) << 32) |
-                                static_cast<uint32_t>(uni(static_cast<int>(u & 0xffffffffu))));
-}
-__device__ inline double uni(double v) { return __builtin_bit_cast(double, uni(__builtin_bit_cast(int64_t, v))); }
 
 template <typename T>
 __device__ inline GatherAngle<T> uni(const GatherAngle<T> &g) {

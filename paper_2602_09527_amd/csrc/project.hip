@@ -69,6 +69,109 @@ __device__ inline Vec4<T> load4(const T *p) {
     }
 }
 
+template <typename T>
+__device__ inline void store4(T *dst, const Vec4<T> &v) {
+    if constexpr (std::is_same<T, float>::value) {
+        *reinterpret_cast<float4 *>(dst) = make_float4(v.a, v.b, v.c, v.d);
+    } else {
+        dst[0] = v.a;
+        dst[1] = v.b;
+        dst[2] = v.c;
+        dst[3] = v.d;
+    }
+}
+
+template <typename T>
+__device__ inline Vec4<T> sub4(const Vec4<T> &v, const Vec4<T> &w) {
+    return Vec4<T>{v.a - w.a, v.b - w.b, v.c - w.c, v.d - w.d};
+}
+
+// 16-byte loads in flight per thread while staging: 8 of x, or 4 each of x and xs.
+template <bool kDiff>
+constexpr int stage_batch() { return kDiff ? 4 : 8; }
+
+// Stage rows t0 .. t0 + nt - 1 of x (minus xs when kDiff) into LDS, row t at t * stride + kPad.
+// Element e = t * (ext / 4) + c is a group of 4 columns; each thread takes every kBlock-th one.
+// Every load of a batch is issued before the first subtraction or store, so their latencies
+// overlap.  Elements past the end load element 0 instead (always in bounds) and are not stored.
+template <bool kDiff, typename T>
+__device__ inline void stage_rows(T *lds, const T *xz, const T *xsz, int t0, int nt, int ext, int nx,
+                                  int stride) {
+    constexpr int NB = stage_batch<kDiff>();
+    const int q4 = ext / 4, cnt = nt * q4;
+    // (t, c) of this thread's next element, advanced by kBlock elements without dividing
+    int t = threadIdx.x / q4, c = threadIdx.x - t * q4;
+    const int adv_t = kBlock / q4, adv_c = kBlock - adv_t * q4;
+    for (int b0 = 0; b0 < cnt; b0 += NB * kBlock) {
+        uint32_t g[NB];
+        int l[NB];
+        bool ok[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            ok[u] = b0 + u * kBlock + static_cast<int>(threadIdx.x) < cnt;
+            g[u] = ok[u] ? static_cast<uint32_t>(t0 + t) * nx + 4 * c : 0u;
+            l[u] = t * stride + kPad + 4 * c;
+            t += adv_t;
+            c += adv_c;
+            if (c >= q4) {
+                c -= q4;
+                ++t;
+            }
+        }
+        Vec4<T> v[NB], w[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) v[u] = load4(xz + g[u]);
+        if constexpr (kDiff) {
+#pragma unroll
+            for (int u = 0; u < NB; ++u) w[u] = load4(xsz + g[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u)
+            if (ok[u]) store4(lds + l[u], kDiff ? sub4(v[u], w[u]) : v[u]);
+    }
+}
+
+// Stage columns t0 .. t0 + nt - 1 of x (minus xs) into LDS transposed: column t0 + t at
+// t * stride + kPad.  Element e is a group of 4 adjacent columns (e % (strip / 4)) of image row
+// e / (strip / 4); its 4 values go to 4 staged rows.  Loads as in stage_rows.
+template <bool kDiff, typename T>
+__device__ inline void stage_cols(T *lds, const T *xz, const T *xsz, int t0, int nt, int ext, int nx,
+                                  int stride, int strip) {
+    constexpr int NB = stage_batch<kDiff>();
+    const int g4 = strip / 4, g4s = __builtin_ctz(g4), cnt = ext * g4;
+    for (int b0 = 0; b0 < cnt; b0 += NB * kBlock) {
+        uint32_t g[NB];
+        int l[NB];
+        bool ok[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int e = b0 + u * kBlock + static_cast<int>(threadIdx.x);
+            const int i = e >> g4s, cg = e & (g4 - 1);
+            ok[u] = e < cnt && 4 * cg < nt;
+            g[u] = ok[u] ? static_cast<uint32_t>(i) * nx + t0 + 4 * cg : 0u;
+            l[u] = 4 * cg * stride + kPad + i;
+        }
+        Vec4<T> v[NB], w[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) v[u] = load4(xz + g[u]);
+        if constexpr (kDiff) {
+#pragma unroll
+            for (int u = 0; u < NB; ++u) w[u] = load4(xsz + g[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            if (ok[u]) {
+                const Vec4<T> d = kDiff ? sub4(v[u], w[u]) : v[u];
+                T *dst = lds + l[u];
+                dst[0] = d.a;
+                dst[stride] = d.b;
+                dst[2 * stride] = d.c;
+                dst[3 * stride] = d.d;
+            }
+        }
+    }
+}
+
 // One projector application: y = inv * A_sub (x - xs) [- b_sub], or partial sums when split.
 template <typename T>
 struct ProjItem {
@@ -135,84 +238,13 @@ __global__ __launch_bounds__(kBlock) void k_project(WorkList<ProjItem<T>> wl) {
     for (int t0 = t_lo; t0 < t_hi; t0 += strip) {
         const int nt = min(strip, t_hi - t0);
         if (vec) {
-            // 16-byte loads: x and xs rows are 16-byte aligned (nx % 4 == 0)
+            // 16-byte loads and stores (FP32 rows are 16-byte aligned: nx % 4 == 0)
             if (row) {
-                const int q4 = ext / 4, cnt = nt * q4;
-                // element e = t * q4 + c, advanced by 8 x 256 per pass without dividing
-                int t_s = threadIdx.x / q4, c_s = threadIdx.x - t_s * q4;
-                const int adv_t = kBlock / q4, adv_c = kBlock - adv_t * q4;
-                for (int e0 = threadIdx.x; e0 < cnt; e0 += 8 * kBlock) {
-                    Vec4<T> v[8];
-                    int tt[8], cc[8];
-                    int t = t_s, c = c_s;
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        tt[u] = t;
-                        cc[u] = c;
-                        if (e0 + u * kBlock < cnt) {
-                            const size_t gi = static_cast<size_t>(t0 + t) * nx + 4 * c;
-                            v[u] = load4(xz + gi);
-                            if (xsz) {
-                                const Vec4<T> w = load4(xsz + gi);
-                                v[u] = Vec4<T>{v[u].a - w.a, v[u].b - w.b, v[u].c - w.c, v[u].d - w.d};
-                            }
-                        }
-                        t += adv_t;
-                        c += adv_c;
-                        if (c >= q4) {
-                            c -= q4;
-                            ++t;
-                        }
-                    }
-                    t_s = t;
-                    c_s = c;
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        if (e0 + u * kBlock < cnt) {
-                            // 16-byte aligned: stride and kPad are multiples of 4 words
-                            T *dst = lds + tt[u] * stride + kPad + 4 * cc[u];
-                            if constexpr (std::is_same<T, float>::value) {
-                                *reinterpret_cast<float4 *>(dst) = make_float4(v[u].a, v[u].b, v[u].c, v[u].d);
-                            } else {
-                                dst[0] = v[u].a;
-                                dst[1] = v[u].b;
-                                dst[2] = v[u].c;
-                                dst[3] = v[u].d;
-                            }
-                        }
-                    }
-                }
+                if (xsz) stage_rows<true>(lds, xz, xsz, t0, nt, ext, nx, stride);
+                else stage_rows<false>(lds, xz, xsz, t0, nt, ext, nx, stride);
             } else {
-                // column strip: groups of 4 adjacent columns of one image row, stored transposed
-                const int g4 = strip / 4, g4s = __builtin_ctz(g4), cnt = ext * g4;
-                for (int e0 = threadIdx.x; e0 < cnt; e0 += 8 * kBlock) {
-                    Vec4<T> v[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const int e = e0 + u * kBlock;
-                        const int i = e >> g4s, cg = e & (g4 - 1);
-                        if (e < cnt && 4 * cg < nt) {
-                            const size_t gi = static_cast<size_t>(i) * nx + t0 + 4 * cg;
-                            v[u] = load4(xz + gi);
-                            if (xsz) {
-                                const Vec4<T> w = load4(xsz + gi);
-                                v[u] = Vec4<T>{v[u].a - w.a, v[u].b - w.b, v[u].c - w.c, v[u].d - w.d};
-                            }
-                        }
-                    }
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const int e = e0 + u * kBlock;
-                        const int i = e >> g4s, cg = e & (g4 - 1);
-                        if (e < cnt && 4 * cg < nt) {
-                            T *dst = lds + (4 * cg) * stride + kPad + i;
-                            dst[0] = v[u].a;
-                            dst[stride] = v[u].b;
-                            dst[2 * stride] = v[u].c;
-                            dst[3 * stride] = v[u].d;
-                        }
-                    }
-                }
+                if (xsz) stage_cols<true>(lds, xz, xsz, t0, nt, ext, nx, stride, strip);
+                else stage_cols<false>(lds, xz, xsz, t0, nt, ext, nx, stride, strip);
             }
         } else if (row) {
             for (int e = threadIdx.x; e < nt * ext; e += kBlock) {
