@@ -70,6 +70,13 @@ def _load():
         "orc_proxskip_svrg": (C.c_int, [G, _D, _D, _D, _DN, C.c_double, C.c_double, C.c_double,
                                         C.c_int, C.c_int, C.c_int, C.c_int, C.c_uint64, C.c_int64,
                                         C.c_double, C.POINTER(_Stats), _DN]),
+        "orc_refresh_coins": (None, [C.c_uint64, C.c_int64, C.c_int64, C.c_int, _U8]),
+        "orc_proxskip": (C.c_int, [G, _D, _D, _D, _DN, C.c_double, C.c_double, C.c_double,
+                                   C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64, C.c_int64,
+                                   _I, C.c_void_p, C.c_void_p, C.c_double, C.POINTER(_Stats),
+                                   _DN, _DN, _DN]),
+        "orc_fista": (C.c_int, [G, _D, _D, _DN, C.c_double, C.c_double, C.c_int, C.c_int,
+                                C.c_int, _DN]),
         "orc_num_threads": (C.c_int, []),
     }
     for name, (res, args) in sig.items():
@@ -233,6 +240,73 @@ def proxskip_svrg(g: Geometry, b, *, gamma, p, alpha, fgp_inner, n_epochs, nonne
                  prox_calls=st.prox_calls, last_rel_change=st.last_rel_change)
     assert x.size == n
     return x, h, dual, stats, rel[:st.epochs_done]
+
+
+ESTIMATORS = {"svrg": 0, "lsvrg": 1, "saga": 2}
+
+
+def refresh_coins(seed: int, k0: int, count: int, n_subsets: int) -> np.ndarray:
+    """Loopless-SVRG refresh coins rho_k (probability 1/N), k = k0 .. k0 + count - 1."""
+    out = np.zeros(max(count, 1), dtype=np.uint8)
+    _load().orc_refresh_coins(seed, k0, count, n_subsets, out)
+    return out[:count]
+
+
+def proxskip(g: Geometry, b, *, estimator, gamma, p, alpha, fgp_inner, n_epochs=None,
+             n_iters=None, nonneg=True, plain=False, seed=0, k0=0, tol=0.0, sub=None, coin=None,
+             refresh=None, x=None, h=None, dual=None, return_table=False):
+    """Algorithm 1 with the SVRG, loopless-SVRG or SAGA estimator ("svrg", "lsvrg", "saga").
+
+    The random draws default to the seeded streams (sequences() and refresh_coins()) and may be
+    given instead.  Returns (x, h, dual, stats dict, per-epoch relative changes) and, with
+    return_table, also (table [N][nz][ny][nx], table_sum) of the SAGA estimator.
+    """
+    est = ESTIMATORS[estimator]
+    N = g.n_subsets
+    K = int(n_iters if n_iters is not None else n_epochs * N)
+    if sub is None or coin is None:
+        s_, c_ = sequences(seed, k0, K, N, p)
+        sub = s_ if sub is None else sub
+        coin = c_ if coin is None else coin
+    if refresh is None and est == 1:
+        refresh = refresh_coins(seed, k0, K, N)
+    sub = np.ascontiguousarray(sub, dtype=np.int32)
+    coin = np.ascontiguousarray(coin, dtype=np.uint8)
+    refresh = None if refresh is None else np.ascontiguousarray(refresh, dtype=np.uint8)
+    x = np.zeros((g.nz, g.ny, g.nx)) if x is None else _f64(x).reshape(g.nz, g.ny, g.nx).copy()
+    h = np.zeros((g.nz, g.ny, g.nx)) if h is None else _f64(h).reshape(g.nz, g.ny, g.nx).copy()
+    dual = (np.zeros((g.tv_dims, g.nz, g.ny, g.nx)) if dual is None
+            else _f64(dual).reshape(g.tv_dims, g.nz, g.ny, g.nx).copy())
+    rel = np.zeros(max(K // N + 1, 1))
+    table = np.zeros((N, g.nz, g.ny, g.nx)) if (return_table and est == 2) else None
+    tsum = np.zeros((g.nz, g.ny, g.nx)) if (return_table and est == 2) else None
+    st = _Stats()
+    rc = _load().orc_proxskip(g._c(), _f64(b), x, h, dual.ctypes.data, float(gamma), float(p),
+                              float(alpha), int(fgp_inner), int(bool(nonneg)), int(bool(plain)),
+                              est, int(k0), K, sub, coin.ctypes.data,
+                              None if refresh is None else refresh.ctypes.data, float(tol),
+                              C.byref(st), rel.ctypes.data,
+                              None if table is None else table.ctypes.data,
+                              None if tsum is None else tsum.ctypes.data)
+    if rc != 0:
+        raise ValueError("orc_proxskip: invalid arguments")
+    stats = dict(epochs_done=st.epochs_done, iters_done=st.iters_done,
+                 prox_calls=st.prox_calls, last_rel_change=st.last_rel_change)
+    out = (x, h, dual, stats, rel[:st.epochs_done])
+    return out + (table, tsum) if return_table else out
+
+
+def fista(g: Geometry, b, *, gamma, alpha, fgp_inner, n_iters, nonneg=True, x=None, dual=None):
+    """FISTA; returns (x, dual, objective f + alpha TV after each iteration)."""
+    x = np.zeros((g.nz, g.ny, g.nx)) if x is None else _f64(x).reshape(g.nz, g.ny, g.nx).copy()
+    dual = (np.zeros((g.tv_dims, g.nz, g.ny, g.nx)) if dual is None
+            else _f64(dual).reshape(g.tv_dims, g.nz, g.ny, g.nx).copy())
+    fval = np.zeros(max(n_iters, 1))
+    rc = _load().orc_fista(g._c(), _f64(b), x, dual.ctypes.data, float(gamma), float(alpha),
+                           int(fgp_inner), int(bool(nonneg)), int(n_iters), fval.ctypes.data)
+    if rc != 0:
+        raise ValueError("orc_fista: invalid arguments")
+    return x, dual, fval[:n_iters]
 
 
 def num_threads() -> int:

@@ -554,6 +554,134 @@ int orc_proxskip_svrg(const orc_geom *g, const double *b, double *x, double *h, 
     return 0;
 }
 
+void orc_refresh_coins(uint64_t seed, int64_t k0, int64_t count, int n_subsets, uint8_t *out)
+{
+    const uint64_t thresh = (1ULL << 53) / (uint64_t)n_subsets; /* floor(2^53 / N) */
+    for (int64_t t = 0; t < count; ++t) {
+        const uint64_t u = orc_splitmix64(seed, (1ULL << 62) + (uint64_t)(k0 + t));
+        out[t] = (uint8_t)((u >> 11) < thresh);
+    }
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Algorithm 1 with the SVRG, loopless SVRG and SAGA estimators (the table beside it).         */
+/* ------------------------------------------------------------------------------------------ */
+
+int orc_proxskip(const orc_geom *g, const double *b, double *x, double *h, double *dual,
+                 double gamma, double p, double alpha, int fgp_inner, int nonneg, int plain,
+                 int estimator, int64_t k0, int64_t n_iters, const int32_t *sub,
+                 const uint8_t *coin, const uint8_t *refresh, double tol, orc_stats *stats,
+                 double *rel_change_out, double *table, double *table_sum)
+{
+    const int N = g->n_subsets;
+    if (N < 1 || gamma <= 0.0 || !(p > 0.0 && p <= 1.0) || alpha < 0.0 || fgp_inner < 0 ||
+        n_iters < 0 || k0 < 0 || k0 % N != 0 || !sub || (!plain && !coin) ||
+        estimator < ORC_SVRG || estimator > ORC_SAGA || (estimator == ORC_LSVRG && !refresh))
+        return -1;
+    const size_t n = (size_t)g->nx * g->ny * g->nz;
+    double *xs = alloc_d(n), *gs = alloc_d(n), *gx = alloc_d(n), *gxs = alloc_d(n);
+    double *G = alloc_d(n), *xh = alloc_d(n), *v = alloc_d(n), *xn = alloc_d(n);
+    double *xe = alloc_d(n);                 /* x at the last epoch end (or the start) */
+    double *V = NULL, *vbar = NULL;
+    if (estimator == ORC_SAGA) {
+        V = table ? table : alloc_d(n * (size_t)N);
+        vbar = table_sum ? table_sum : alloc_d(n);
+    }
+    memcpy(xe, x, sizeof(double) * n);
+
+    orc_stats st = {0, 0, 0, 0.0};
+    for (int64_t t = 0; t < n_iters; ++t) {
+        const int64_t k = k0 + t;
+        const int i = sub[t];
+        if (estimator == ORC_SAGA) {
+            if (t == 0) {
+                /* table v_j = grad f_j(x_0), vbar = sum_j v_j in increasing j */
+                memset(vbar, 0, sizeof(double) * n);
+                for (int j = 0; j < N; ++j) {
+                    double *vj = V + (size_t)j * n;
+                    orc_grad_subset(g, j, x, b, vj);
+                    for (size_t e = 0; e < n; ++e) vbar[e] += vj[e];
+                }
+            }
+            /* Eq. 5: G = N (grad f_i(x) - v_i) + vbar, then the table entry i and the sum */
+            double *vi = V + (size_t)i * n;
+            orc_grad_subset(g, i, x, b, gx);
+            for (size_t e = 0; e < n; ++e) {
+                const double diff = gx[e] - vi[e];
+                G[e] = (double)N * diff + vbar[e];
+                vbar[e] += diff;
+                vi[e] = gx[e];
+            }
+        } else {
+            const int refresh_now = estimator == ORC_SVRG ? (k % N == 0) : (t == 0 || refresh[t]);
+            if (refresh_now) {
+                memcpy(xs, x, sizeof(double) * n);
+                orc_grad_full(g, xs, b, gs);
+            }
+            orc_grad_subset(g, i, x, b, gx);
+            orc_grad_subset(g, i, xs, b, gxs);
+            for (size_t e = 0; e < n; ++e) G[e] = (double)N * (gx[e] - gxs[e]) + gs[e];
+        }
+
+        if (plain) {
+            for (size_t e = 0; e < n; ++e) v[e] = x[e] - gamma * G[e];
+            orc_tv_prox_fgp(g->nx, g->ny, g->nz, v, x, gamma * alpha, fgp_inner, nonneg, dual);
+            st.prox_calls++;
+        } else {
+            for (size_t e = 0; e < n; ++e) xh[e] = x[e] - gamma * (G[e] - h[e]);
+            if (coin[t]) {
+                for (size_t e = 0; e < n; ++e) v[e] = xh[e] - (gamma / p) * h[e];
+                orc_tv_prox_fgp(g->nx, g->ny, g->nz, v, xn, gamma * alpha / p, fgp_inner, nonneg,
+                                dual);
+                st.prox_calls++;
+            } else {
+                memcpy(xn, xh, sizeof(double) * n);
+            }
+            for (size_t e = 0; e < n; ++e) h[e] = h[e] + (p / gamma) * (xn[e] - xh[e]);
+            memcpy(x, xn, sizeof(double) * n);
+        }
+        st.iters_done++;
+        if ((k + 1) % N == 0) {
+            st.last_rel_change = rel_change(x, xe, n);
+            if (rel_change_out) rel_change_out[st.epochs_done] = st.last_rel_change;
+            st.epochs_done++;
+            memcpy(xe, x, sizeof(double) * n);
+            if (tol > 0.0 && st.last_rel_change < tol) break;
+        }
+    }
+    if (stats) *stats = st;
+    if (V && V != table) free(V);
+    if (vbar && vbar != table_sum) free(vbar);
+    free(xs); free(gs); free(gx); free(gxs); free(G); free(xh); free(v); free(xn); free(xe);
+    return 0;
+}
+
+/* FISTA: ISTA with the acceleration step of Beck & Teboulle (2009). */
+int orc_fista(const orc_geom *g, const double *b, double *x, double *dual, double gamma,
+              double alpha, int fgp_inner, int nonneg, int n_iters, double *fval_out)
+{
+    if (gamma <= 0.0 || alpha < 0.0 || fgp_inner < 0 || n_iters < 0) return -1;
+    const size_t n = (size_t)g->nx * g->ny * g->nz;
+    double *y = alloc_d(n), *gy = alloc_d(n), *v = alloc_d(n), *xn = alloc_d(n);
+    memcpy(y, x, sizeof(double) * n);
+    double t = 1.0;
+    for (int k = 0; k < n_iters; ++k) {
+        orc_grad_full(g, y, b, gy);
+        for (size_t e = 0; e < n; ++e) v[e] = y[e] - gamma * gy[e];
+        orc_tv_prox_fgp(g->nx, g->ny, g->nz, v, xn, gamma * alpha, fgp_inner, nonneg, dual);
+        const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+        const double beta = (t - 1.0) / tn;
+        for (size_t e = 0; e < n; ++e) {
+            y[e] = xn[e] + beta * (xn[e] - x[e]);
+            x[e] = xn[e];
+        }
+        t = tn;
+        if (fval_out) fval_out[k] = orc_data_fit(g, x, b) + alpha * orc_tv(g->nx, g->ny, g->nz, x);
+    }
+    free(y); free(gy); free(v); free(xn);
+    return 0;
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

@@ -122,6 +122,47 @@ int orc_proxskip_svrg(const orc_geom *g, const double *b, double *x, double *h, 
                       int n_epochs, int plain, uint64_t seed, int64_t k0, double tol,
                       orc_stats *stats, double *rel_change_out);
 
+/* Refresh coins of the loopless SVRG estimator (Sec. 1.3: the full gradient is refreshed with
+ * probability 1/N in every iteration):
+ *   rho_k = (u(seed, 2^62 + k) >> 11) < floor(2^53 / N)      (integer division)
+ * for k = k0 .. k0 + count - 1.  The counters 2^62 + k never meet the subset and coin counters
+ * 2k and 2k + 1 while k < 2^61. */
+void orc_refresh_coins(uint64_t seed, int64_t k0, int64_t count, int n_subsets, uint8_t *out);
+
+/* Gradient estimators of the table beside Algorithm 1 (Sec. 1.3). */
+enum { ORC_SVRG = 0, ORC_LSVRG = 1, ORC_SAGA = 2 };
+
+/* Algorithm 1 with estimator G_k:
+ *   ORC_SVRG   G = N (grad f_i(x) - grad f_i(xs)) + grad f(xs), snapshot xs = x and
+ *              grad f(xs) refreshed at every k with k mod N == 0;
+ *   ORC_LSVRG  the same G, the snapshot refreshed at the run's first iteration and at every
+ *              later k with refresh[t] = 1 (before G_k is formed, so G_k = grad f(x_k) there);
+ *   ORC_SAGA   G = N (grad f_i(x) - v_i) + vbar, then vbar += grad f_i(x) - v_i and
+ *              v_i = grad f_i(x) (Eq. 5); at the run's first iteration the table is filled with
+ *              v_i = grad f_i(x) for every i and vbar = sum_i v_i (increasing i).
+ * then xh = x - gamma (G - h); theta = coin[t]: x+ = prox_{(gamma/p) g}(xh - (gamma/p) h) or
+ * x+ = xh; h+ = h + (p/gamma)(x+ - xh).  plain != 0: x+ = prox_{gamma g}(x - gamma G), h unused.
+ * The random draws are inputs: sub[t], coin[t], refresh[t] for iteration k = k0 + t,
+ * t = 0 .. n_iters - 1 (refresh may be NULL unless ORC_LSVRG; coin may be NULL when plain).
+ * Epochs are the N-iteration blocks from k0 (k0 a multiple of N); at each epoch end the relative
+ * change ||x_e - x_{e-1}|| / ||x_e|| goes to rel_change_out (may be NULL) and, with tol > 0, the
+ * run stops at the first epoch end below tol.  table (N * n) and table_sum (n) receive the SAGA
+ * state when not NULL.  Returns 0, or -1 on invalid arguments. */
+int orc_proxskip(const orc_geom *g, const double *b, double *x, double *h, double *dual,
+                 double gamma, double p, double alpha, int fgp_inner, int nonneg, int plain,
+                 int estimator, int64_t k0, int64_t n_iters, const int32_t *sub,
+                 const uint8_t *coin, const uint8_t *refresh, double tol, orc_stats *stats,
+                 double *rel_change_out, double *table, double *table_sum);
+
+/* FISTA (Beck & Teboulle 2009; the table beside Algorithm 1: ISTA with an acceleration step):
+ *   x_{k+1} = prox_{gamma g}(y_k - gamma grad f(y_k)),  t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2,
+ *   y_{k+1} = x_{k+1} + ((t_k - 1) / t_{k+1}) (x_{k+1} - x_k),   y_0 = x_0,  t_0 = 1,
+ * g = alpha TV + I_C with the prox by FGP (fgp_inner warm-started iterations, dual in/out).
+ * x: in x_0, out x_K.  fval_out (may be NULL) receives f(x_{k+1}) + alpha TV(x_{k+1}) for
+ * k = 0 .. n_iters - 1.  Returns 0, or -1 on invalid arguments. */
+int orc_fista(const orc_geom *g, const double *b, double *x, double *dual, double gamma,
+              double alpha, int fgp_inner, int nonneg, int n_iters, double *fval_out);
+
 /* Threads the OpenMP runtime will use (for reporting). */
 int orc_num_threads(void);
 
