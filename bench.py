@@ -12,7 +12,9 @@ Prints one JSON line.  Besides the timed epochs it reports:
                 with HIP events on the launching stream, and the HBM bytes per launch from the
                 committed rocprofv3 counter summary (null once the kernel source has changed);
   kernels       each operator's rate in samples/s, lane operations/s and algorithmic GB/s;
-  sweep         epochs/s and prox calls at p in {1, 0.1, 0.02} and non-skipped ProxSVRG;
+  sweep         epochs/s and prox calls at p in {1, 0.1, 0.02}, non-skipped ProxSVRG, ProxLSVRGSkip
+                and ProxSAGASkip at p = 0.1, and iterations/s (one data pass each) of ISTA,
+                deterministic ProxSkip (p = 0.1) and FISTA;
   batch         64 independent 128^2 solves batched in lockstep against one after another;
   serving       a Poisson trace of mixed-size requests with continuous batching against one
                 request at a time (p50/p99 latency, throughput);
@@ -395,7 +397,9 @@ def main():
     if not args.no_sweep:
         sweep = []
         for label, kw in (("p=1", dict(p=1.0)), ("p=0.1", dict(p=0.1)), ("p=0.02", dict(p=0.02)),
-                          ("ProxSVRG", dict(p=1.0, plain_prox_svrg=True))):
+                          ("ProxSVRG", dict(p=1.0, plain_prox_svrg=True)),
+                          ("ProxLSVRGSkip p=0.1", dict(p=0.1, estimator="lsvrg")),
+                          ("ProxSAGASkip p=0.1", dict(p=0.1, estimator="saga", gamma=gamma / 3.0))):
             E = 20
             sv = api.Solver(g, b, params(E + 2, **kw))
             sv.epochs(2)
@@ -409,6 +413,35 @@ def main():
             sweep.append({"run": label, "epochs_per_s": round(E / dt, 2),
                           "prox_calls": q["prox_calls"], "rel_change": q["last_rel_change"]})
             log(f"bench: sweep {label}: {E / dt:.1f} epochs/s, prox calls {q['prox_calls']}")
+        # deterministic methods (one data pass per iteration): ISTA and ProxSkip as Algorithm 1
+        # with one subset, and FISTA
+        g1 = api.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=1, device=dev)
+        api.autotune(g1, reps=3, cache_path=PLANS_FILE, store=False)
+        for label, kw in (("ISTA", dict(p=1.0, plain_prox_svrg=True)), ("ProxSkip p=0.1", dict(p=0.1))):
+            E = 10
+            sv = api.Solver(g1, b, params(E + 2, **kw))
+            sv.epochs(2)
+            sv.query()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            sv.epochs(E)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+            q = sv.query()
+            sweep.append({"run": label, "epochs_per_s": round(E / dt, 2),
+                          "prox_calls": q["prox_calls"], "rel_change": q["last_rel_change"]})
+            log(f"bench: sweep {label}: {E / dt:.1f} iterations/s, prox calls {q['prox_calls']}")
+        E = 10
+        xf, df = api.fista(g1, b, gamma=gamma, alpha=w.alpha, fgp_inner=w.fgp_inner, n_iters=2)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        api.fista(g1, b, gamma=gamma, alpha=w.alpha, fgp_inner=w.fgp_inner, n_iters=E, x=xf, dual=df)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        sweep.append({"run": "FISTA", "epochs_per_s": round(E / dt, 2), "prox_calls": E,
+                      "rel_change": None})
+        log(f"bench: sweep FISTA: {E / dt:.1f} iterations/s")
+        del g1
         out["sweep"] = sweep
 
     # ---- batched independent slices: 64 solves of 128^2 (180 x 128, N = 10) ----------------

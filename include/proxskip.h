@@ -2,7 +2,7 @@
  * proxskip.h -- C ABI of the MI355X (gfx950) library for TV-regularised parallel-beam tomography
  * solved by ProxSkip with the SVRG gradient estimator (ProxSVRGSkip).
  *
- * Problem (Sec. 2.1, Eq. 4, an instance of Eq. 1):
+ * Problem (Sec. 2.1, Eq. 5, an instance of Eq. 1):
  *     min_x  1/2 ||A x - b||^2 + alpha TV(x) + I_{x >= 0}(x)
  * with A the discrete Radon transform, split into N subsets of interleaved angles
  * (A_i, b_i), i = 0..N-1, subset i holding the angles {i, i+N, i+2N, ...} (Sec. 1.2, the
@@ -147,7 +147,7 @@ PS_API size_t backproject_workspace_bytes(const ps_geometry *geom, int32_t subse
 PS_API ps_status backproject_subset(const ps_geometry *geom, int32_t subset, const void *y, void *x,
                              int32_t accumulate, void *workspace, size_t ws_bytes, void *stream);
 
-/* Proximal operator of g = TV + I_C (Eq. 3 with the regulariser of Eq. 4), with weight tau:
+/* Proximal operator of g = TV + I_C (Eq. 3 with the regulariser of Eq. 5), with weight tau:
  *     z = argmin_z 1/2 ||z - v||^2 + tau TV(z) + I_C(z),   C = {z >= 0} if nonneg else R^n,
  * isotropic TV with forward differences (zero last difference), solved by n_inner iterations of
  * FGP (Beck & Teboulle 2009), warm-started from `dual` (Sec. 2.1: a fixed number of
@@ -161,7 +161,14 @@ PS_API ps_status tv_prox_fgp(const ps_geometry *geom, const void *v, void *z, do
                       int32_t n_inner, int32_t nonneg, void *dual, void *workspace,
                       size_t ws_bytes, void *stream);
 
-/* Parameters of Algorithm 1 (Sec. 1.3) with the SVRG estimator. */
+/* Gradient estimators G_k of the table beside Algorithm 1 (Sec. 1.3). */
+typedef enum {
+    PS_EST_SVRG = 0,   /* N (grad f_i(x) - grad f_i(xs)) + grad f(xs), xs refreshed every N iterations */
+    PS_EST_LSVRG = 1,  /* the same G, xs refreshed with probability 1/N per iteration (loopless)     */
+    PS_EST_SAGA = 2    /* N (grad f_i(x) - v_i) + sum_j v_j with the table v of Eq. 4              */
+} ps_estimator;
+
+/* Parameters of Algorithm 1 (Sec. 1.3). */
 typedef struct {
     double gamma;             /* step size > 0 (the paper uses 1/L, L = ||A||^2)                */
     double p;                 /* prox probability, 0 < p <= 1                                   */
@@ -175,6 +182,7 @@ typedef struct {
     int64_t k0;               /* first iteration index (resume point), a multiple of N          */
     double tol_rel_change;    /* > 0 => stop at the first epoch end with                        */
                               /*   ||x_e - x_{e-1}|| / ||x_e|| < tol; 0 => run n_epochs         */
+    int32_t estimator;        /* ps_estimator (0 = SVRG)                                        */
 } ps_solver_params;
 
 typedef struct {
@@ -184,9 +192,15 @@ typedef struct {
     double last_rel_change;   /* ||x_e - x_{e-1}|| / ||x_e|| at the last completed epoch end   */
 } ps_solver_stats;
 
-/* ProxSkip-SVRG (Algorithm 1, ProxSVRGSkip row of its table):
- *   every N iterations (k mod N == 0): snapshot xs = x_k, gs = grad f(xs) = A^T (A xs - b)
- *   G_k  = N (grad f_i(x_k) - grad f_i(xs)) + gs,   i = i_k uniform on {0..N-1}
+/* ProxSkip (Algorithm 1) with the estimator params->estimator:
+ *   PS_EST_SVRG (ProxSVRGSkip row of its table): every N iterations (k mod N == 0) snapshot
+ *     xs = x_k, gs = grad f(xs) = A^T (A xs - b);  G_k = N (grad f_i(x_k) - grad f_i(xs)) + gs
+ *   PS_EST_LSVRG (ProxLSVRGSkip): the same G_k; the snapshot is refreshed at the run's first
+ *     iteration and at every later k with rho_k = 1 (sample_refresh_coins), before G_k is formed
+ *   PS_EST_SAGA (ProxSAGASkip, Eq. 4): G_k = N (grad f_i(x_k) - v_i) + vbar, then
+ *     vbar += grad f_i(x_k) - v_i and v_i = grad f_i(x_k); the table is filled with
+ *     v_j = grad f_j(x_k0) and vbar = sum_j v_j (increasing j) at the run's first iteration
+ * then, with i = i_k uniform on {0..N-1},
  *   xh   = x_k - gamma (G_k - h_k)
  *   theta_k ~ Bernoulli(p): x_{k+1} = prox_{(gamma/p) g}(xh - (gamma/p) h_k) if theta_k = 1,
  *                           else x_{k+1} = xh
@@ -194,7 +208,9 @@ typedef struct {
  * with g = alpha TV + I_C, the prox by tv_prox_fgp with fgp_inner warm-started iterations, and
  * i_k, theta_k from sample_sequences(seed, ...).
  * b: device [nz][A][B].  x, h, dual: device, in = state at k0 (zeros for a fresh run),
- * out = state after the run.  (x, h, dual, k) is the complete resumable state.
+ * out = state after the run.  For SVRG, (x, h, dual, k) is the complete resumable state; the
+ * loopless-SVRG snapshot and the SAGA table live in the workspace, so a new run from k0 > 0
+ * starts them afresh at x_k0 (a handle keeps them across solver_epochs calls).
  * workspace: at least proxskip_workspace_bytes(geom, params) bytes.  stats_out may be NULL.
  * Synchronises `stream` once at the end (and at every epoch end when tol_rel_change > 0).
  * Errors: PS_EINVAL, PS_EHIP, PS_ENONFINITE. */
@@ -255,6 +271,25 @@ PS_API void solver_free(ps_solver *handle);
  * Either output may be NULL.  Errors: PS_EINVAL. */
 PS_API ps_status sample_sequences(uint64_t seed, int64_t k0, int64_t count, int32_t n_subsets,
                            double p, int32_t *subset_out, uint8_t *coin_out);
+
+/* Refresh coins of the loopless SVRG estimator (Sec. 1.3: the full gradient is refreshed with
+ * probability 1/N in every iteration), from the same generator at counters 2^62 + k:
+ *   rho_k = (u(seed, 2^62 + k) >> 11) < floor(2^53 / N),   k = k0 .. k0+count-1.
+ * Errors: PS_EINVAL. */
+PS_API ps_status sample_refresh_coins(uint64_t seed, int64_t k0, int64_t count, int32_t n_subsets,
+                               uint8_t *out);
+
+/* FISTA (Beck & Teboulle 2009; the table beside Algorithm 1: ISTA with an acceleration step),
+ * with the full gradient and the same prox as Algorithm 1:
+ *   x_{k+1} = prox_{gamma g}(y_k - gamma A^T (A y_k - b)),  t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2,
+ *   y_{k+1} = x_{k+1} + ((t_k - 1) / t_{k+1}) (x_{k+1} - x_k),   y_0 = x_0,  t_0 = 1.
+ * b: device [nz][A][B].  x: device, in x_0, out x_K.  dual: device [d][nz][ny][nx] FGP warm
+ * start, in/out (zeros for a fresh run).  workspace: at least fista_workspace_bytes(geom) bytes.
+ * Stream-ordered; does not synchronise.  Errors: PS_EINVAL, PS_EHIP. */
+PS_API size_t fista_workspace_bytes(const ps_geometry *geom);
+PS_API ps_status fista_run(const ps_geometry *geom, const void *b, void *x, void *dual, double gamma,
+                    double alpha, int32_t fgp_inner, int32_t nonneg, int32_t n_iters,
+                    void *workspace, size_t ws_bytes, void *stream);
 
 /* Description of the last error on the calling thread ("" if none). */
 PS_API const char *last_error_message(void);

@@ -305,7 +305,7 @@ double orc_lipschitz(const orc_geom *g, int iters)
 }
 
 /* ------------------------------------------------------------------------------------------ */
-/* Isotropic TV and its proximal operator (Sec. 2.1, Eq. 4; FGP of Beck & Teboulle 2009).      */
+/* Isotropic TV and its proximal operator (Sec. 2.1, Eq. 5; FGP of Beck & Teboulle 2009).      */
 /*   D: forward differences with a zero last difference (Neumann boundary).                     */
 /*   D^T: its exact adjoint.  ||D||^2 <= 4 d.                                                    */
 /* ------------------------------------------------------------------------------------------ */
@@ -603,7 +603,7 @@ int orc_proxskip(const orc_geom *g, const double *b, double *x, double *h, doubl
                     for (size_t e = 0; e < n; ++e) vbar[e] += vj[e];
                 }
             }
-            /* Eq. 5: G = N (grad f_i(x) - v_i) + vbar, then the table entry i and the sum */
+            /* Eq. 4: G = N (grad f_i(x) - v_i) + vbar, then the table entry i and the sum */
             double *vi = V + (size_t)i * n;
             orc_grad_subset(g, i, x, b, gx);
             for (size_t e = 0; e < n; ++e) {

@@ -5,7 +5,7 @@
  * THIS IS TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT.  Only the tests, the smoke check and the
  * CPU-baseline leg of the benchmark may load it.  It shares no source, header, table or helper
  * with the HIP library: everything here is written out from the paper's definitions
- * (Sec. 1, Eq. 1-3; Algorithm 1 and its estimator table; Sec. 2.1, Eq. 4) and from the
+ * (Sec. 1, Eq. 1-4; Algorithm 1 and its estimator table; Sec. 2.1, Eq. 5) and from the
  * published methods the paper cites (Beck & Teboulle's FGP; Joseph interpolation; SplitMix64).
  *
  * Precision: every floating-point value is IEEE double, built with -ffp-contract=off and no
@@ -138,7 +138,7 @@ enum { ORC_SVRG = 0, ORC_LSVRG = 1, ORC_SAGA = 2 };
  *   ORC_LSVRG  the same G, the snapshot refreshed at the run's first iteration and at every
  *              later k with refresh[t] = 1 (before G_k is formed, so G_k = grad f(x_k) there);
  *   ORC_SAGA   G = N (grad f_i(x) - v_i) + vbar, then vbar += grad f_i(x) - v_i and
- *              v_i = grad f_i(x) (Eq. 5); at the run's first iteration the table is filled with
+ *              v_i = grad f_i(x) (Eq. 4); at the run's first iteration the table is filled with
  *              v_i = grad f_i(x) for every i and vbar = sum_i v_i (increasing i).
  * then xh = x - gamma (G - h); theta = coin[t]: x+ = prox_{(gamma/p) g}(xh - (gamma/p) h) or
  * x+ = xh; h+ = h + (p/gamma)(x+ - xh).  plain != 0: x+ = prox_{gamma g}(x - gamma G), h unused.

@@ -27,8 +27,10 @@ EXPORTS = (
     "tv_prox_fgp", "proxskip_workspace_bytes", "proxskip_svrg_run", "solver_init",
     "solver_epochs", "solver_epochs_graph", "solver_steps", "solver_done", "solver_query",
     "solver_cancel",
-    "solver_free", "sample_sequences", "last_error_message",
+    "solver_free", "sample_sequences", "sample_refresh_coins", "fista_workspace_bytes",
+    "fista_run", "last_error_message",
 )
+PS_EST_SVRG, PS_EST_LSVRG, PS_EST_SAGA = 0, 1, 2
 
 
 class GeometryDesc(C.Structure):
@@ -54,7 +56,7 @@ class SolverParams(C.Structure):
         ("gamma", C.c_double), ("p", C.c_double), ("alpha", C.c_double),
         ("fgp_inner", C.c_int32), ("nonneg", C.c_int32), ("n_epochs", C.c_int32),
         ("plain_prox_svrg", C.c_int32), ("seed", C.c_uint64), ("k0", C.c_int64),
-        ("tol_rel_change", C.c_double),
+        ("tol_rel_change", C.c_double), ("estimator", C.c_int32),
     ]
 
 
@@ -113,6 +115,9 @@ def load():
         "solver_cancel": (st, [vp]),
         "solver_free": (None, [vp]),
         "sample_sequences": (st, [u64, i64, i64, i32, d, vp, vp]),
+        "sample_refresh_coins": (st, [u64, i64, i64, i32, vp]),
+        "fista_workspace_bytes": (sz, [vp]),
+        "fista_run": (st, [vp, vp, vp, vp, d, d, i32, i32, i32, vp, sz, vp]),
         "last_error_message": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():

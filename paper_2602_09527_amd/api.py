@@ -189,9 +189,14 @@ def tv_prox(g: Geometry, v: torch.Tensor, tau: float, n_inner: int, nonneg: bool
     return z
 
 
+ESTIMATORS = {"svrg": nat.PS_EST_SVRG, "lsvrg": nat.PS_EST_LSVRG, "saga": nat.PS_EST_SAGA}
+
+
 @dataclasses.dataclass
 class SolverParams:
-    """Algorithm 1 parameters (gamma, p), TV weight, FGP inner iterations, stopping rule."""
+    """Algorithm 1 parameters (gamma, p), TV weight, FGP inner iterations, stopping rule, and
+    the gradient estimator: "svrg" (ProxSVRGSkip), "lsvrg" (ProxLSVRGSkip) or "saga"
+    (ProxSAGASkip)."""
     gamma: float
     p: float
     alpha: float
@@ -202,12 +207,13 @@ class SolverParams:
     seed: int = 0
     k0: int = 0
     tol_rel_change: float = 0.0
+    estimator: str = "svrg"
 
     def c(self) -> nat.SolverParams:
         return nat.SolverParams(float(self.gamma), float(self.p), float(self.alpha),
                                 int(self.fgp_inner), int(bool(self.nonneg)), int(self.n_epochs),
                                 int(bool(self.plain_prox_svrg)), int(self.seed), int(self.k0),
-                                float(self.tol_rel_change))
+                                float(self.tol_rel_change), int(ESTIMATORS[self.estimator]))
 
 
 def _stats(s: nat.SolverStats) -> dict:
@@ -216,7 +222,8 @@ def _stats(s: nat.SolverStats) -> dict:
 
 
 def solve(g: Geometry, b: torch.Tensor, params: SolverParams, x=None, h=None, dual=None):
-    """Run ProxSkip-SVRG; x, h, dual (in/out, zeros if omitted) are updated in place.
+    """Run Algorithm 1 with params.estimator; x, h, dual (in/out, zeros if omitted) are updated
+    in place.
 
     Returns (x, h, dual, stats)."""
     b = g.check(b, (g.nz, g.n_angles, g.n_bins), "b")
@@ -317,6 +324,31 @@ def sample_sequences(seed: int, k0: int, count: int, n_subsets: int, p: float):
                                    sub.ctypes.data_as(C.c_void_p), coin.ctypes.data_as(C.c_void_p)),
               "sample_sequences")
     return sub[:count], coin[:count]
+
+
+def sample_refresh_coins(seed: int, k0: int, count: int, n_subsets: int):
+    """The library's loopless-SVRG refresh coins (uint8 numpy array)."""
+    lib = nat.load()
+    out = np.zeros(max(count, 1), dtype=np.uint8)
+    nat.check(lib.sample_refresh_coins(int(seed), int(k0), int(count), int(n_subsets),
+                                       out.ctypes.data_as(C.c_void_p)), "sample_refresh_coins")
+    return out[:count]
+
+
+def fista(g: Geometry, b: torch.Tensor, gamma: float, alpha: float, fgp_inner: int, n_iters: int,
+          nonneg: bool = True, x=None, dual=None):
+    """FISTA with the full gradient and the TV prox; x and dual (zeros if omitted) are updated
+    in place.  Returns (x, dual).  Stream-ordered on the current stream."""
+    b = g.check(b, (g.nz, g.n_angles, g.n_bins), "b")
+    x = g.zeros_image() if x is None else g.check(x, g.image_shape, "x")
+    dual = (torch.zeros(g.dual_shape(), dtype=g.dtype, device=g.device) if dual is None
+            else g.check(dual, g.dual_shape(), "dual"))
+    nbytes = g.lib.fista_workspace_bytes(g.handle)
+    ws = g.workspace("fista", nbytes)
+    nat.check(g.lib.fista_run(g.handle, _ptr(b), _ptr(x), _ptr(dual), float(gamma), float(alpha),
+                              int(fgp_inner), int(bool(nonneg)), int(n_iters), _ptr(ws), nbytes,
+                              _stream(g.device)), "fista_run")
+    return x, dual
 
 
 def autotune(g: Geometry, reps: int = 5, cache_path: str | None = None, store: bool = True,

@@ -327,6 +327,7 @@ struct UpdateT {
     const T *h;
     T *gs;
     T *vout;
+    T *tab, *tsum;
     T gamma, gamma_over_p, nsub;
     int coin, plain;
 };
@@ -339,11 +340,19 @@ __device__ inline void bp_epilogue(int mode, const UpdateT<T> &upd, T *__restric
         out[p] = d;
     } else if (mode == BP_ACCUMULATE) {
         out[p] += d;
+    } else if (mode == BP_GRADSTEP) {
+        upd.vout[p] = upd.x[p] - upd.gamma * d;
     } else {
         T G;
         if (mode == BP_SNAPSHOT) {
             upd.gs[p] = d;
             G = d;
+        } else if (mode == BP_SAGA) {
+            const T diff = d - upd.tab[p];
+            const T sum = upd.tsum[p];
+            G = fma(upd.nsub, diff, sum);
+            upd.tsum[p] = sum + diff;
+            upd.tab[p] = d;
         } else {
             G = fma(upd.nsub, d, upd.gs[p]);
         }
@@ -667,6 +676,8 @@ static UpdateT<T> to_update(const UpdateArgs &u) {
     r.h = static_cast<const T *>(u.h);
     r.gs = static_cast<T *>(u.gs);
     r.vout = static_cast<T *>(u.vout);
+    r.tab = static_cast<T *>(u.tab);
+    r.tsum = static_cast<T *>(u.tsum);
     r.gamma = static_cast<T>(u.gamma);
     r.gamma_over_p = static_cast<T>(u.gamma_over_p);
     r.nsub = static_cast<T>(u.nsub);
@@ -700,7 +711,7 @@ static ps_status backproject_many_t(const BackCall *calls, int n, hipStream_t st
         const BackCall &bc = calls[c];
         const ps_geometry *g = bc.g;
         const auto &d = g->desc;
-        if (bc.mode < BP_OVERWRITE || bc.mode > BP_SNAPSHOT)
+        if (bc.mode < BP_OVERWRITE || bc.mode > BP_GRADSTEP)
             return fail(PS_EINVAL, "backprojector mode %d", bc.mode);
         if (back_method(g, bc.subset) == BP_GATHER) {
             GatherItem<T> gi{};

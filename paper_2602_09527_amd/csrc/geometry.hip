@@ -71,6 +71,15 @@ void draw_sequences(uint64_t seed, int64_t k0, int64_t count, int n_subsets, dou
     }
 }
 
+void draw_refresh(uint64_t seed, int64_t k0, int64_t count, int n_subsets, uint8_t *out) {
+    // rho = 1 iff a uniform 53-bit integer falls below floor(2^53 / N), from counters 2^62 + k
+    const uint64_t limit = (static_cast<uint64_t>(1) << 53) / static_cast<uint64_t>(n_subsets);
+    for (int64_t t = 0; t < count; ++t) {
+        const uint64_t j = (static_cast<uint64_t>(1) << 62) + static_cast<uint64_t>(k0 + t);
+        out[t] = static_cast<uint8_t>((splitmix64(seed, j) >> 11) < limit);
+    }
+}
+
 template <typename T>
 static void fill_tables(ps_geometry *g, const std::vector<double> &a0, const std::vector<double> &a1,
                         const std::vector<double> &a2, const std::vector<double> &inv,
@@ -263,6 +272,16 @@ extern "C" ps_status sample_sequences(uint64_t seed, int64_t k0, int64_t count, 
     if (n_subsets < 1) return fail(PS_EINVAL, "n_subsets must be >= 1");
     if (!(p > 0.0 && p <= 1.0)) return fail(PS_EINVAL, "p must be in (0, 1]");
     draw_sequences(seed, k0, count, n_subsets, p, subset_out, coin_out);
+    return PS_OK;
+}
+
+extern "C" ps_status sample_refresh_coins(uint64_t seed, int64_t k0, int64_t count, int32_t n_subsets,
+                                          uint8_t *out) {
+    clear_error();
+    if (count < 0 || k0 < 0) return fail(PS_EINVAL, "count and k0 must be >= 0");
+    if (n_subsets < 1) return fail(PS_EINVAL, "n_subsets must be >= 1");
+    if (!out && count > 0) return fail(PS_EINVAL, "out is null");
+    draw_refresh(seed, k0, count, n_subsets, out);
     return PS_OK;
 }
 

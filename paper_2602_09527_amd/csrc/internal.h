@@ -199,12 +199,15 @@ ps_status launch_project(const ps_geometry *g, int subset, const void *x, const 
 // ---------------------------------------------------------------------------------------------
 // Backprojector with fused epilogues (backproject.hip).
 // ---------------------------------------------------------------------------------------------
-enum BackMode { BP_OVERWRITE = 0, BP_ACCUMULATE = 1, BP_SVRG = 2, BP_SNAPSHOT = 3 };
+enum BackMode { BP_OVERWRITE = 0, BP_ACCUMULATE = 1, BP_SVRG = 2, BP_SNAPSHOT = 3, BP_SAGA = 4,
+                BP_GRADSTEP = 5 };
 
-// SVRG/ProxSkip epilogue operands (BP_SVRG, BP_SNAPSHOT), all [nz][ny][nx]:
+// Gradient-step epilogue operands (BP_SVRG, BP_SNAPSHOT, BP_SAGA, BP_GRADSTEP), all [nz][ny][nx]:
 //   d = A^T y at the pixel
 //   BP_SVRG:     G = nsub * d + gs
 //   BP_SNAPSHOT: gs = d (stored), G = d         (iteration at the snapshot: x = xs)
+//   BP_SAGA:     G = nsub * (d - tab) + tsum, then tsum += d - tab, tab = d   (Eq. 4)
+//   BP_GRADSTEP: v = x - gamma d -> vout         (full-gradient step, no h)
 //   plain:       v = x - gamma G                 -> vout
 //   coin = 1:    v = x - gamma (G - h) - (gamma/p) h  -> vout
 //   coin = 0:    x = x - gamma (G - h)           (in place)
@@ -213,6 +216,7 @@ struct UpdateArgs {
     const void *h;
     void *gs;
     void *vout;
+    void *tab, *tsum;   // BP_SAGA: the table row of the subset and the table's running sum
     double gamma, gamma_over_p, nsub;
     int coin, plain;
 };
@@ -268,5 +272,6 @@ ps_status launch_fgp(const ps_geometry *g, const void *v, void *dual, double tau
 uint64_t splitmix64(uint64_t seed, uint64_t j);
 void draw_sequences(uint64_t seed, int64_t k0, int64_t count, int n_subsets, double p,
                     int32_t *subset_out, uint8_t *coin_out);
+void draw_refresh(uint64_t seed, int64_t k0, int64_t count, int n_subsets, uint8_t *out);
 
 }  // namespace ps

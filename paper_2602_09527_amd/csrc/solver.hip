@@ -1,5 +1,6 @@
-// solver.hip -- ProxSkip with the SVRG estimator (Algorithm 1, ProxSVRGSkip row), driven from
-// the host over the projector, backprojector and FGP kernels, plus the resumable handle API.
+// solver.hip -- ProxSkip (Algorithm 1) with the SVRG, loopless-SVRG and SAGA estimators of the
+// table beside it, driven from the host over the projector, backprojector and FGP kernels, plus
+// the resumable handle API and FISTA.
 //
 // Per epoch (N iterations, one data pass):
 //   k = eN      snapshot xs = x; r = A xs - b (full projection, residual fused);
@@ -10,6 +11,9 @@
 //               xh = x - gamma (G - h):  theta = 0 -> x = xh;  theta = 1 -> v = xh - (gamma/p) h,
 //               then FGP gives x = prox(v) and h = h + (p/gamma)(x - xh) = (p/gamma)(x - v).
 //   epoch end   ||x - xs||^2 and ||x||^2 (fixed-order two-level reduction in FP64).
+// Loopless SVRG takes the snapshot branch at iterations whose refresh coin is 1 instead of at
+// epoch starts.  SAGA projects x itself (y = A_i x - b_i) and updates its table in the
+// backprojector's epilogue; both keep x of the last epoch end (xe) for the epoch-end norms.
 #include <algorithm>
 #include <climits>
 #include <cmath>
@@ -113,25 +117,60 @@ __global__ __launch_bounds__(kBlock) void k_norm_final(WorkList<NormItem> wl) {
     }
 }
 
+// tsum = sum_j tab[j] in increasing j (the SAGA table's running sum at initialisation).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_table_sum(const T *__restrict__ tab, T *__restrict__ tsum,
+                                                      int nrows, size_t n) {
+    for (size_t e = blockIdx.x * static_cast<size_t>(kBlock) + threadIdx.x; e < n;
+         e += static_cast<size_t>(gridDim.x) * kBlock) {
+        T acc = T(0);
+        for (int j = 0; j < nrows; ++j) acc += tab[static_cast<size_t>(j) * n + e];
+        tsum[e] = acc;
+    }
+}
+
+// FISTA extrapolation: y = xn + beta (xn - x), then x = xn.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fista_momentum(T *__restrict__ x, const T *__restrict__ xn,
+                                                           T *__restrict__ y, T beta, size_t n) {
+    for (size_t e = blockIdx.x * static_cast<size_t>(kBlock) + threadIdx.x; e < n;
+         e += static_cast<size_t>(gridDim.x) * kBlock) {
+        const T a = xn[e];
+        y[e] = a + beta * (a - x[e]);
+        x[e] = a;
+    }
+}
+
+static int elementwise_blocks(size_t n) {
+    return static_cast<int>(std::max<size_t>(1, std::min<size_t>((n + kBlock - 1) / kBlock, 8192)));
+}
+
 static int norm_blocks(size_t n) {
     return static_cast<int>(std::max<size_t>(1, std::min<size_t>((n + kBlock - 1) / kBlock, kNormBlocks)));
 }
 
 struct Layout {
-    size_t xs, gs, v, sino, pws, bws, fws, npart, stats, total;
+    size_t xs, gs, v, xe, tab, tsum, sino, pws, bws, fws, npart, stats, total;
     size_t pws_bytes, bws_bytes, fws_bytes;
 };
 
-static Layout layout(const ps_geometry *g, int n_epochs) {
+static Layout layout(const ps_geometry *g, int n_epochs, int estimator) {
     const auto &d = g->desc;
     const size_t n = static_cast<size_t>(d.nx) * d.ny * d.nz;
     const size_t m = static_cast<size_t>(d.nz) * d.n_angles * d.n_bins;
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes); return o; };
-    L.xs = take(n * g->elem);
-    L.gs = take(n * g->elem);
+    if (estimator != PS_EST_SAGA) {
+        L.xs = take(n * g->elem);
+        L.gs = take(n * g->elem);
+    }
     L.v = take(n * g->elem);
+    if (estimator != PS_EST_SVRG) L.xe = take(n * g->elem);
+    if (estimator == PS_EST_SAGA) {
+        L.tab = take(static_cast<size_t>(d.n_subsets) * n * g->elem);
+        L.tsum = take(n * g->elem);
+    }
     L.sino = take(m * g->elem);
     L.pws_bytes = std::max(proj_workspace(g, d.n_angles), proj_workspace(g, max_subset_count(g)));
     L.pws = take(L.pws_bytes);
@@ -159,6 +198,8 @@ static ps_status check_params(const ps_geometry *g, const ps_solver_params *p) {
     if (p->k0 < 0 || p->k0 % g->desc.n_subsets != 0)
         return fail(PS_EINVAL, "k0 must be a non-negative multiple of n_subsets");
     if (!(p->tol_rel_change >= 0.0)) return fail(PS_EINVAL, "tol_rel_change must be >= 0");
+    if (p->estimator < PS_EST_SVRG || p->estimator > PS_EST_SAGA)
+        return fail(PS_EINVAL, "estimator %d is not a ps_estimator", p->estimator);
     return PS_OK;
 }
 
@@ -180,8 +221,8 @@ struct ps_solver {
     double last_rel;
     bool converged, cancelled, nonfinite;
     hipStream_t stream;
-    std::vector<int32_t> sub;   // i_k and theta_k of the current epoch
-    std::vector<uint8_t> coin;
+    std::vector<int32_t> sub;   // i_k, theta_k (and rho_k, loopless SVRG) of the current epoch
+    std::vector<uint8_t> coin, refresh;
     std::vector<double> stats_host;
     // tolerance runs: the epoch-end norms travel to pinned host memory behind an event
     bool pending;
@@ -247,32 +288,42 @@ static ps_status launch_snapshots(const std::vector<SnapItem<T>> &items, hipStre
     return PS_OK;
 }
 
-// xs = x (do_norm = 0) or the epoch-end norms (do_norm = 1) of every handle in `hs`.
-static ps_status snapshot_many(const std::vector<ps_solver *> &hs, int do_norm, hipStream_t st) {
+// One request of snapshot_many: copy x into the workspace buffer at `dst` and/or take the
+// epoch-end norms ||x - dst||^2, ||x||^2 (the copy, when both, follows the norm element-wise).
+struct SnapReq {
+    ps_solver *s;
+    size_t dst;
+    int do_norm, do_copy;
+};
+
+static ps_status snapshot_many(const std::vector<SnapReq> &reqs, hipStream_t st) {
     std::vector<SnapItem<float>> f32;
     std::vector<SnapItem<double>> f64;
     ListBuilder<NormItem> nb;
-    std::vector<WorkList<NormItem>> norm_lists;
-    std::vector<int> norm_blocks_of;
-    for (ps_solver *s : hs) {
+    bool any_norm = false;
+    for (const SnapReq &r : reqs) {
+        ps_solver *s = r.s;
         const auto &d = s->g->desc;
         const size_t n = static_cast<size_t>(d.nx) * d.ny * d.nz;
         const int nbk = norm_blocks(n);
         double *part = reinterpret_cast<double *>(s->ws + s->L.npart);
+        any_norm = any_norm || r.do_norm;
         if (d.dtype == PS_F64) {
             f64.push_back(SnapItem<double>{static_cast<const double *>(s->x),
-                                           reinterpret_cast<double *>(s->ws + s->L.xs), part, n,
-                                           do_norm, 1 - do_norm, nbk});
+                                           reinterpret_cast<double *>(s->ws + r.dst), part, n,
+                                           r.do_norm, r.do_copy, nbk});
         } else {
             f32.push_back(SnapItem<float>{static_cast<const float *>(s->x),
-                                          reinterpret_cast<float *>(s->ws + s->L.xs), part, n,
-                                          do_norm, 1 - do_norm, nbk});
+                                          reinterpret_cast<float *>(s->ws + r.dst), part, n,
+                                          r.do_norm, r.do_copy, nbk});
         }
     }
     if (!f32.empty()) PS_TRY(launch_snapshots<float>(f32, st));
     if (!f64.empty()) PS_TRY(launch_snapshots<double>(f64, st));
-    if (!do_norm) return PS_OK;
-    for (ps_solver *s : hs) {
+    if (!any_norm) return PS_OK;
+    for (const SnapReq &r : reqs) {
+        if (!r.do_norm) continue;
+        ps_solver *s = r.s;
         const auto &d = s->g->desc;
         const size_t n = static_cast<size_t>(d.nx) * d.ny * d.nz;
         NormItem ni{reinterpret_cast<const double *>(s->ws + s->L.npart),
@@ -291,13 +342,43 @@ static ps_status snapshot_many(const std::vector<ps_solver *> &hs, int do_norm, 
     return PS_OK;
 }
 
+// SAGA table at the run's first iteration: v_j = A_j^T (A_j x - b_j) for every subset j, then
+// vbar = sum_j v_j in increasing j.
+template <typename T>
+static ps_status saga_fill_t(ps_solver *s, hipStream_t st) {
+    const ps_geometry *g = s->g;
+    const auto &d = g->desc;
+    const size_t n = static_cast<size_t>(d.nx) * d.ny * d.nz;
+    unsigned char *w = s->ws;
+    T *tab = reinterpret_cast<T *>(w + s->L.tab);
+    for (int j = 0; j < d.n_subsets; ++j) {
+        PS_TRY(launch_project(g, j, s->x, nullptr, s->b, w + s->L.sino, w + s->L.pws, s->L.pws_bytes, st));
+        PS_TRY(launch_backproject(g, j, w + s->L.sino, tab + static_cast<size_t>(j) * n, BP_OVERWRITE,
+                                  nullptr, w + s->L.bws, s->L.bws_bytes, st));
+    }
+    hipLaunchKernelGGL((k_table_sum<T>), dim3(elementwise_blocks(n)), dim3(kBlock), 0, st, tab,
+                       reinterpret_cast<T *>(w + s->L.tsum), d.n_subsets, n);
+    PS_LAUNCHED("k_table_sum");
+    return PS_OK;
+}
+
+// Does iteration s->k take the snapshot branch (xs = x, full gradient)?
+static bool snapshot_now(const ps_solver *s, int t) {
+    const int est = s->prm.estimator;
+    if (est == PS_EST_SVRG) return t == 0;
+    if (est == PS_EST_LSVRG) return s->k == s->prm.k0 || s->refresh[t] != 0;
+    return false;
+}
+
 // One iteration of every handle in `hs`, each stage one batched launch (per kernel variant):
-//   snapshot copies (handles at an epoch start) -> projections -> backprojections with the
-//   fused SVRG/ProxSkip step -> FGP prox (handles whose coin is heads) -> epoch-end norms.
+//   snapshot copies (handles taking the snapshot branch, and x of the run's start) -> SAGA table
+//   fills (first iteration) -> projections -> backprojections with the fused estimator and
+//   ProxSkip step -> FGP prox (handles whose coin is heads) -> epoch-end norms.
 // Every handle computes exactly what it computes alone.
 static ps_status run_step(const std::vector<ps_solver *> &hs, hipStream_t st,
                           std::vector<ps_solver *> &ending) {
-    std::vector<ps_solver *> starting;
+    std::vector<SnapReq> copies;
+    std::vector<ps_solver *> fills;
     std::vector<ProjCall> pc;
     std::vector<BackCall> bc;
     std::vector<FgpCall> fc;
@@ -308,26 +389,42 @@ static ps_status run_step(const std::vector<ps_solver *> &hs, hipStream_t st,
         const auto &P = s->prm;
         const int N = g->desc.n_subsets;
         const int t = static_cast<int>(s->k % N);
+        const int est = P.estimator;
+        const bool first = s->k == P.k0;
         unsigned char *w = s->ws;
         if (t == 0) {
             s->sub.resize(N);
             s->coin.resize(N);
             draw_sequences(P.seed, s->k, N, N, P.p, s->sub.data(), s->coin.data());
-            starting.push_back(s);
+            if (est == PS_EST_LSVRG) {
+                s->refresh.resize(N);
+                draw_refresh(P.seed, s->k, N, N, s->refresh.data());
+            }
         }
+        const bool snap = snapshot_now(s, t);
+        if (snap) copies.push_back(SnapReq{s, s->L.xs, 0, 1});
+        if (first && est != PS_EST_SVRG) copies.push_back(SnapReq{s, s->L.xe, 0, 1});
+        if (first && est == PS_EST_SAGA) fills.push_back(s);
         const int i = s->sub[t];
         const bool prox = P.plain_prox_svrg || s->coin[t];
         UpdateArgs up{};
         up.x = s->x;
         up.h = s->h;
-        up.gs = w + s->L.gs;
+        up.gs = est == PS_EST_SAGA ? nullptr : w + s->L.gs;
         up.vout = w + s->L.v;
         up.gamma = P.gamma;
         up.gamma_over_p = P.gamma / P.p;
         up.nsub = static_cast<double>(N);
         up.plain = P.plain_prox_svrg;
         up.coin = s->coin[t];
-        if (t == 0) {
+        if (est == PS_EST_SAGA) {
+            // y = A_i x - b_i; G = N (A_i^T y - v_i) + vbar with the table updated in the epilogue
+            const size_t n = static_cast<size_t>(g->desc.nx) * g->desc.ny * g->desc.nz;
+            up.tab = w + s->L.tab + static_cast<size_t>(i) * n * g->elem;
+            up.tsum = w + s->L.tsum;
+            pc.push_back(ProjCall{g, i, s->x, nullptr, s->b, w + s->L.sino, w + s->L.pws, s->L.pws_bytes});
+            bc.push_back(BackCall{g, i, w + s->L.sino, nullptr, BP_SAGA, up, w + s->L.bws, s->L.bws_bytes});
+        } else if (snap) {
             // r = A xs - b over all angles, then gs = A^T r fused with the step (G = gs)
             pc.push_back(ProjCall{g, -1, w + s->L.xs, nullptr, s->b, w + s->L.sino, w + s->L.pws, s->L.pws_bytes});
             bc.push_back(BackCall{g, -1, w + s->L.sino, nullptr, BP_SNAPSHOT, up, w + s->L.bws, s->L.bws_bytes});
@@ -348,11 +445,20 @@ static ps_status run_step(const std::vector<ps_solver *> &hs, hipStream_t st,
         s->k++;
         if (s->k % N == 0) ending.push_back(s);
     }
-    if (!starting.empty()) PS_TRY(snapshot_many(starting, 0, st));   // xs = x
+    if (!copies.empty()) PS_TRY(snapshot_many(copies, st));
+    for (ps_solver *s : fills)
+        PS_TRY(s->g->desc.dtype == PS_F64 ? saga_fill_t<double>(s, st) : saga_fill_t<float>(s, st));
     PS_TRY(launch_project_many(pc.data(), static_cast<int>(pc.size()), st));
     PS_TRY(launch_backproject_many(bc.data(), static_cast<int>(bc.size()), st));
     if (!fc.empty()) PS_TRY(launch_fgp_many(fc.data(), static_cast<int>(fc.size()), st));
-    if (!ending.empty()) PS_TRY(snapshot_many(ending, 1, st));  // ||x_e - x_{e-1}||, ||x_e||
+    if (!ending.empty()) {
+        // ||x_e - x_{e-1}||, ||x_e||: x_{e-1} is the SVRG snapshot, else the kept copy xe
+        std::vector<SnapReq> norms;
+        for (ps_solver *s : ending)
+            norms.push_back(s->prm.estimator == PS_EST_SVRG ? SnapReq{s, s->L.xs, 1, 0}
+                                                            : SnapReq{s, s->L.xe, 1, 1});
+        PS_TRY(snapshot_many(norms, st));
+    }
     return PS_OK;
 }
 
@@ -375,7 +481,7 @@ static ps_status finish_epochs(const std::vector<ps_solver *> &ended, hipStream_
 
 extern "C" size_t proxskip_workspace_bytes(const ps_geometry *g, const ps_solver_params *p) {
     if (!g || !p) return 0;
-    return layout(g, p->n_epochs).total;
+    return layout(g, p->n_epochs, p->estimator).total;
 }
 
 extern "C" ps_status solver_init(const ps_geometry *g, const void *b, void *x, void *h, void *dual,
@@ -392,7 +498,7 @@ extern "C" ps_status solver_init(const ps_geometry *g, const void *b, void *x, v
     PS_TRY(check_ptr(h, "h", g->elem));
     PS_TRY(check_ptr(dual, "dual", g->elem));
     PS_TRY(check_ptr(workspace, "workspace", kAlign));
-    const Layout L = layout(g, prm->n_epochs);
+    const Layout L = layout(g, prm->n_epochs, prm->estimator);
     if (ws_bytes < L.total)
         return fail(PS_EINVAL, "solver workspace: %zu bytes given, %zu needed", ws_bytes, L.total);
     ps_solver *s = new (std::nothrow) ps_solver();
@@ -535,6 +641,13 @@ static ps_status graph_round(const std::vector<ps_solver *> &hs, hipStream_t st,
         draw_sequences(s->prm.seed, s->k, N, N, s->prm.p, nullptr, coin.data());
         key += std::to_string(s->id) + ":" + std::to_string(N) + ":";
         for (int t = 0; t < N; ++t) key += static_cast<char>('0' + (s->prm.plain_prox_svrg ? 1 : coin[t]));
+        if (s->prm.estimator == PS_EST_LSVRG) {
+            std::vector<uint8_t> rho(N);
+            draw_refresh(s->prm.seed, s->k, N, N, rho.data());
+            key += "/";
+            for (int t = 0; t < N; ++t) key += static_cast<char>('0' + rho[t]);
+        }
+        if (s->k == s->prm.k0) key += "/first";
         key += ";";
     }
     if (!gc->capture) PS_HIP(hipStreamCreateWithFlags(&gc->capture, hipStreamNonBlocking));
@@ -697,4 +810,98 @@ extern "C" ps_status proxskip_svrg_run(const ps_geometry *g, const void *b, void
     }
     solver_free(s);
     return st;
+}
+
+// ---------------------------------------------------------------------------------------------
+// FISTA (Beck & Teboulle 2009): per iteration one all-angle projection of y with the residual
+// fused (r = A y - b), one all-angle backprojection with the gradient step fused
+// (v = y - gamma A^T r), the FGP prox of v into xn, and the extrapolation y = xn + beta (xn - x).
+// ---------------------------------------------------------------------------------------------
+namespace ps {
+
+struct FistaLayout {
+    size_t y, v, xn, sino, pws, bws, fws, total;
+    size_t pws_bytes, bws_bytes, fws_bytes;
+};
+
+static FistaLayout fista_layout(const ps_geometry *g) {
+    const auto &d = g->desc;
+    const size_t n = static_cast<size_t>(d.nx) * d.ny * d.nz;
+    const size_t m = static_cast<size_t>(d.nz) * d.n_angles * d.n_bins;
+    FistaLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes); return o; };
+    L.y = take(n * g->elem);
+    L.v = take(n * g->elem);
+    L.xn = take(n * g->elem);
+    L.sino = take(m * g->elem);
+    L.pws_bytes = proj_workspace(g, d.n_angles);
+    L.pws = take(L.pws_bytes);
+    L.bws_bytes = back_workspace(g, -1);
+    L.bws = take(L.bws_bytes);
+    L.fws_bytes = fgp_workspace(g);
+    L.fws = take(L.fws_bytes);
+    L.total = off;
+    return L;
+}
+
+template <typename T>
+static ps_status fista_momentum(void *x, const void *xn, void *y, double beta, size_t n, hipStream_t st) {
+    hipLaunchKernelGGL((k_fista_momentum<T>), dim3(elementwise_blocks(n)), dim3(kBlock), 0, st,
+                       static_cast<T *>(x), static_cast<const T *>(xn), static_cast<T *>(y),
+                       static_cast<T>(beta), n);
+    PS_LAUNCHED("k_fista_momentum");
+    return PS_OK;
+}
+
+}  // namespace ps
+
+extern "C" size_t fista_workspace_bytes(const ps_geometry *g) {
+    if (!g) return 0;
+    return fista_layout(g).total;
+}
+
+extern "C" ps_status fista_run(const ps_geometry *g, const void *b, void *x, void *dual, double gamma,
+                               double alpha, int32_t fgp_inner, int32_t nonneg, int32_t n_iters,
+                               void *workspace, size_t ws_bytes, void *stream) {
+    clear_error();
+    if (!g) return fail(PS_EINVAL, "geometry is null");
+    PS_TRY(check_ready(g));
+    if (!(gamma > 0.0) || !std::isfinite(gamma)) return fail(PS_EINVAL, "gamma must be > 0");
+    if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(PS_EINVAL, "alpha must be >= 0");
+    if (fgp_inner < 0) return fail(PS_EINVAL, "fgp_inner must be >= 0");
+    if (nonneg != 0 && nonneg != 1) return fail(PS_EINVAL, "nonneg must be 0 or 1");
+    if (n_iters < 0) return fail(PS_EINVAL, "n_iters must be >= 0");
+    PS_TRY(check_ptr(b, "b", g->elem));
+    PS_TRY(check_ptr(x, "x", g->elem));
+    PS_TRY(check_ptr(dual, "dual", g->elem));
+    PS_TRY(check_ptr(workspace, "workspace", kAlign));
+    const FistaLayout L = fista_layout(g);
+    if (ws_bytes < L.total)
+        return fail(PS_EINVAL, "FISTA workspace: %zu bytes given, %zu needed", ws_bytes, L.total);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const auto &d = g->desc;
+    const size_t n = static_cast<size_t>(d.nx) * d.ny * d.nz;
+    unsigned char *w = static_cast<unsigned char *>(workspace);
+    if (n_iters == 0) return PS_OK;
+    PS_HIP(hipMemcpyAsync(w + L.y, x, n * g->elem, hipMemcpyDeviceToDevice, st));   // y_0 = x_0
+    double t = 1.0;
+    for (int k = 0; k < n_iters; ++k) {
+        PS_TRY(launch_project(g, -1, w + L.y, nullptr, b, w + L.sino, w + L.pws, L.pws_bytes, st));
+        UpdateArgs up{};
+        up.x = w + L.y;
+        up.vout = w + L.v;
+        up.gamma = gamma;
+        PS_TRY(launch_backproject(g, -1, w + L.sino, nullptr, BP_GRADSTEP, &up, w + L.bws, L.bws_bytes, st));
+        FgpOut fo{};
+        fo.z = w + L.xn;
+        fo.proxskip = 0;
+        PS_TRY(launch_fgp(g, w + L.v, dual, gamma * alpha, fgp_inner, nonneg, fo, w + L.fws, L.fws_bytes, st));
+        const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
+        const double beta = (t - 1.0) / tn;
+        PS_TRY(d.dtype == PS_F64 ? fista_momentum<double>(x, w + L.xn, w + L.y, beta, n, st)
+                                 : fista_momentum<float>(x, w + L.xn, w + L.y, beta, n, st));
+        t = tn;
+    }
+    return PS_OK;
 }

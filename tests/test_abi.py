@@ -85,7 +85,8 @@ def test_geometry_queries_and_not_uploaded(nat):
 @pytest.mark.parametrize("bad", [dict(gamma=0.0), dict(gamma=float("inf")), dict(p=0.0), dict(p=1.5),
                                  dict(alpha=-1.0), dict(fgp_inner=-1), dict(nonneg=2),
                                  dict(n_epochs=-1), dict(plain_prox_svrg=3), dict(k0=1),
-                                 dict(k0=-3), dict(tol_rel_change=-1.0)])
+                                 dict(k0=-3), dict(tol_rel_change=-1.0), dict(estimator=3),
+                                 dict(estimator=-1)])
 def test_solver_params_rejected(nat, bad):
     lib = nat.load()
     h = C.c_void_p()
@@ -111,6 +112,17 @@ def test_sequences_match_oracle_bitwise(nat, orc):
         s1, c1 = api.sample_sequences(seed, k0, count, N, p)
         s2, c2 = orc.sequences(seed, k0, count, N, p)
         assert np.array_equal(s1, s2) and np.array_equal(c1, c2)
+
+
+def test_refresh_coins_match_oracle_bitwise(nat, orc):
+    from paper_2602_09527_amd import api
+    for seed, k0, count, N in [(0, 0, 1_000_000, 20), (2**63 + 12345, 400, 100_000, 7),
+                               (101, 0, 300, 10), (5, 30, 1000, 1), (9, 0, 5000, 30)]:
+        assert np.array_equal(api.sample_refresh_coins(seed, k0, count, N),
+                              orc.refresh_coins(seed, k0, count, N))
+    lib = nat.load()
+    assert lib.sample_refresh_coins(0, 0, 10, 0, None) == nat.PS_EINVAL
+    assert lib.sample_refresh_coins(0, -1, 10, 4, None) == nat.PS_EINVAL
 
 
 def test_sequences_reject(nat):

@@ -1,0 +1,166 @@
+"""ProxLSVRGSkip, ProxSAGASkip (the table beside Algorithm 1) and FISTA on the GPU against the
+FP64 oracle, through the C ABI.
+
+Bars as for ProxSVRGSkip: the FP32 iterate within 1e-4 relative L2 of the oracle's after the
+fixed epochs, the FP64 instantiation within 1e-9, identical prox-call counts (the streams are
+bit-exact); batched and graph-captured runs bit for bit equal to running alone.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _L(w):
+    return json.load(open(os.path.join(GOLDEN, "lipschitz.json")))[w.key]["L"]
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _setup(w, dtype):
+    from paper_2602_09527_amd import api, synth
+    prob = synth.make_problem(w.nx, w.ny, w.n_angles, w.n_bins, seed=w.seed, nz=w.nz,
+                              noise=w.noise, with_phantom=False)
+    g = api.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=w.n_subsets, nz=w.nz, dtype=dtype)
+    b_dev = torch.from_numpy(prob.b).to(device="cuda", dtype=dtype)
+    return g, prob.b, b_dev
+
+
+@pytest.mark.parametrize("estimator", ["lsvrg", "saga"])
+@pytest.mark.parametrize("dtype,tol,epochs", [(torch.float32, 1e-4, 30), (torch.float64, 1e-9, 8)])
+def test_small_2d_against_oracle(orc, estimator, dtype, tol, epochs):
+    # 128^2, 180 angles x 128 bins, 10 subsets, p = 0.1, 100 FGP iterations
+    from paper_2602_09527_amd import api, workloads
+    w = workloads.SMALL_2D
+    g, b, b_dev = _setup(w, dtype)
+    o = orc.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=w.n_subsets)
+    L = _L(w)
+    gamma = 1.0 / L if estimator == "lsvrg" else 1.0 / (3.0 * L)
+    kw = dict(gamma=gamma, p=w.p, alpha=w.alpha, fgp_inner=w.fgp_inner, nonneg=w.nonneg,
+              seed=w.seed + 2)
+    xo, ho, _, so, relo = orc.proxskip(o, b, estimator=estimator, n_epochs=epochs, **kw)
+    x, h, _, st = api.solve(g, b_dev, api.SolverParams(n_epochs=epochs, estimator=estimator, **kw))
+    torch.cuda.synchronize()
+    x, h = x.cpu().numpy(), h.cpu().numpy()
+    assert st["epochs_done"] == so["epochs_done"] == epochs
+    assert st["prox_calls"] == so["prox_calls"]
+    assert _rel(x, xo) <= tol, _rel(x, xo)
+    assert _rel(h, ho) <= 10 * tol, _rel(h, ho)
+    assert abs(st["last_rel_change"] - relo[-1]) <= 10 * tol * relo[-1] + 1e-12
+
+
+def test_lsvrg_single_subset_is_svrg_bitwise():
+    # N = 1: the loopless refresh fires every iteration, as the SVRG epoch start does
+    from paper_2602_09527_amd import api, synth
+    prob = synth.make_problem(96, 96, 120, 144, seed=3, with_phantom=False)
+    g = api.Geometry(96, 96, 120, 144, n_subsets=1)
+    b = torch.from_numpy(prob.b).to(device="cuda", dtype=torch.float32)
+    kw = dict(gamma=1.0 / api.lipschitz(g, 30), p=0.3, alpha=0.01, fgp_inner=20, n_epochs=12, seed=4)
+    xs = api.solve(g, b, api.SolverParams(**kw))[0].clone()
+    xl = api.solve(g, b, api.SolverParams(estimator="lsvrg", **kw))[0].clone()
+    torch.cuda.synchronize()
+    assert torch.equal(xs, xl)
+
+
+MIX = [
+    # nx, ny, A, B, N, seed, dtype, overrides
+    (128, 128, 180, 128, 10, 21, torch.float32, dict(estimator="lsvrg")),
+    (96, 80, 90, 144, 5, 22, torch.float32, dict(estimator="saga", p=0.5, fgp_inner=13)),
+    (128, 128, 180, 128, 10, 23, torch.float32, {}),
+    (64, 64, 60, 96, 6, 24, torch.float64, dict(estimator="saga", p=1.0, fgp_inner=7)),
+    (120, 136, 72, 100, 8, 25, torch.float32, dict(estimator="lsvrg", plain_prox_svrg=True, p=1.0)),
+    (128, 128, 90, 192, 10, 26, torch.float32, dict(estimator="saga", n_epochs=40, tol_rel_change=0.05)),
+]
+
+
+def _problem(nx, ny, A, B, N, seed, dtype, **kw):
+    from paper_2602_09527_amd import api, synth
+    prob = synth.make_problem(nx, ny, A, B, seed=seed, with_phantom=False)
+    g = api.Geometry(nx, ny, A, B, n_subsets=N, dtype=dtype)
+    b = torch.from_numpy(prob.b).to(device="cuda", dtype=dtype)
+    L = api.lipschitz(g, 30)
+    prm = dict(gamma=1.0 / (3.0 * L), p=0.2, alpha=0.01, fgp_inner=20, n_epochs=4, seed=seed + 2)
+    prm.update(kw)
+    return g, b, api.SolverParams(**prm)
+
+
+def _state(s):
+    torch.cuda.synchronize()
+    return s.x.clone(), s.h.clone(), s.dual.clone(), s.query()
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_mixed_estimators_batch_bitwise_equals_alone(graph):
+    from paper_2602_09527_amd import api
+    probs = [_problem(*m[:7], **m[7]) for m in MIX]
+    alone = []
+    for g, b, prm in probs:
+        s = api.Solver(g, b, prm)
+        s.epochs(prm.n_epochs)
+        alone.append(_state(s))
+    solvers = [api.Solver(g, b, prm) for g, b, prm in probs]
+    api.run_epochs(solvers, max(p.n_epochs for _, _, p in probs), graph=graph)
+    for k, s in enumerate(solvers):
+        x, h, d, st = _state(s)
+        xa, ha, da, sa = alone[k]
+        assert st == sa, (k, st, sa)
+        assert torch.equal(x, xa) and torch.equal(h, ha) and torch.equal(d, da), k
+    assert 1 <= alone[-1][3]["epochs_done"] < 40
+
+
+def test_handle_split_calls_equal_one_call():
+    # the loopless snapshot and the SAGA table persist in the handle across calls
+    from paper_2602_09527_amd import api
+    for est in ("lsvrg", "saga"):
+        g, b, prm = _problem(96, 96, 120, 144, 8, 31, torch.float32, estimator=est, n_epochs=6)
+        one = api.Solver(g, b, prm)
+        one.epochs(6)
+        split = api.Solver(g, b, prm)
+        split.epochs(2)
+        api.run_steps([split], 13)
+        split.epochs(6)
+        a, c = _state(one), _state(split)
+        assert torch.equal(a[0], c[0]) and torch.equal(a[1], c[1]), est
+        assert a[3] == c[3]
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float32, 1e-4), (torch.float64, 1e-10)])
+def test_fista_against_oracle(orc, dtype, tol):
+    from paper_2602_09527_amd import api, synth
+    nx, A, B = 128, 180, 128
+    prob = synth.make_problem(nx, nx, A, B, seed=41, with_phantom=False)
+    g = api.Geometry(nx, nx, A, B, n_subsets=1, dtype=dtype)
+    o = orc.Geometry(nx, nx, A, B, n_subsets=1)
+    gamma = 1.0 / orc.lipschitz(o, 200)
+    kw = dict(gamma=gamma, alpha=0.01, fgp_inner=30, nonneg=True)
+    xo, do, _ = orc.fista(o, prob.b, n_iters=25, **kw)
+    b = torch.from_numpy(prob.b).to(device="cuda", dtype=dtype)
+    x, d = api.fista(g, b, n_iters=25, **kw)
+    torch.cuda.synchronize()
+    assert _rel(x.cpu().numpy(), xo) <= tol, _rel(x.cpu().numpy(), xo)
+    assert _rel(d.cpu().numpy(), do) <= 100 * tol, _rel(d.cpu().numpy(), do)
+
+
+def test_fista_first_iteration_is_ista_step():
+    # one FISTA iteration is one ISTA step (beta_1 = 0): Algorithm 1 with N = 1, p = 1, plain
+    from paper_2602_09527_amd import api, synth
+    prob = synth.make_problem(96, 96, 120, 144, seed=5, with_phantom=False)
+    g = api.Geometry(96, 96, 120, 144, n_subsets=1)
+    b = torch.from_numpy(prob.b).to(device="cuda", dtype=torch.float32)
+    gamma = 1.0 / api.lipschitz(g, 30)
+    xf, df = api.fista(g, b, gamma=gamma, alpha=0.02, fgp_inner=25, n_iters=1)
+    xi, _, di, _ = api.solve(g, b, api.SolverParams(gamma=gamma, p=1.0, alpha=0.02, fgp_inner=25,
+                                                   n_epochs=1, plain_prox_svrg=True))
+    torch.cuda.synchronize()
+    assert torch.equal(xf, xi) and torch.equal(df, di)

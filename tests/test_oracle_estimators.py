@@ -114,7 +114,7 @@ def test_single_subset_estimators_are_the_full_gradient(orc):
 
 
 # ---------------------------------------------------------------------------------------------
-# SAGA table (Eq. 5).
+# SAGA table (Eq. 4).
 # ---------------------------------------------------------------------------------------------
 
 def test_saga_table_state(orc):

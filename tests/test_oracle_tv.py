@@ -1,7 +1,7 @@
 """Pins of the oracle's isotropic TV and its FGP proximal operator (no GPU).
 
 prox_{tau (TV + I_C)}(v) = argmin_z 1/2 ||z - v||^2 + tau TV(z) + I_C(z)  (Eq. 3 with the
-regulariser of Eq. 4), computed by FGP (Beck & Teboulle 2009) as the paper prescribes (Sec. 2.1).
+regulariser of Eq. 5), computed by FGP (Beck & Teboulle 2009) as the paper prescribes (Sec. 2.1).
 """
 import numpy as np
 import pytest
