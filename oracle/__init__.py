@@ -77,6 +77,7 @@ def _load():
                                    _DN, _DN, _DN]),
         "orc_fista": (C.c_int, [G, _D, _D, _DN, C.c_double, C.c_double, C.c_int, C.c_int,
                                 C.c_int, _DN]),
+        "orc_pdhg": (C.c_int, [G, _D, _D, _D, _D, C.c_double, C.c_int, C.c_int]),
         "orc_num_threads": (C.c_int, []),
     }
     for name, (res, args) in sig.items():
@@ -307,6 +308,21 @@ def fista(g: Geometry, b, *, gamma, alpha, fgp_inner, n_iters, nonneg=True, x=No
     if rc != 0:
         raise ValueError("orc_fista: invalid arguments")
     return x, dual, fval[:n_iters]
+
+
+def pdhg(g: Geometry, b, *, alpha, n_iters, nonneg=True, x=None, y1=None, y2=None):
+    """Diagonally preconditioned PDHG for Eq. 5; returns (x, y1, y2) (copies of the inputs
+    advanced by n_iters iterations; zeros when omitted)."""
+    x = np.zeros((g.nz, g.ny, g.nx)) if x is None else _f64(x).reshape(g.nz, g.ny, g.nx).copy()
+    y1 = (np.zeros((g.nz, g.n_angles, g.n_bins)) if y1 is None
+          else _f64(y1).reshape(g.nz, g.n_angles, g.n_bins).copy())
+    y2 = (np.zeros((g.tv_dims, g.nz, g.ny, g.nx)) if y2 is None
+          else _f64(y2).reshape(g.tv_dims, g.nz, g.ny, g.nx).copy())
+    rc = _load().orc_pdhg(g._c(), _f64(b), x, y1, y2, float(alpha), int(bool(nonneg)),
+                          int(n_iters))
+    if rc != 0:
+        raise ValueError("orc_pdhg: invalid arguments")
+    return x, y1, y2
 
 
 def num_threads() -> int:

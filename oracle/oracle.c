@@ -682,6 +682,69 @@ int orc_fista(const orc_geom *g, const double *b, double *x, double *dual, doubl
     return 0;
 }
 
+/* ------------------------------------------------------------------------------------------ */
+/* Reference solution: diagonally preconditioned PDHG (Chambolle & Pock 2011).                 */
+/* ------------------------------------------------------------------------------------------ */
+
+int orc_pdhg(const orc_geom *g, const double *b, double *x, double *y1, double *y2, double alpha,
+             int nonneg, int n_iters)
+{
+    if (alpha < 0.0 || n_iters < 0) return -1;
+    grid G = make_grid(g->nx, g->ny, g->nz);
+    const size_t n = G.n, dn = G.d * G.n;
+    const size_t m = (size_t)g->nz * g->n_angles * g->n_bins;
+    double *tau = alloc_d(n), *sig = alloc_d(m), *ones_n = alloc_d(n), *ones_m = alloc_d(m);
+    double *kty = alloc_d(n), *dty = alloc_d(n), *xbar = alloc_d(n), *axb = alloc_d(m);
+    double *dxb = alloc_d(dn);
+    const double sig_d = 0.5;
+    /* preconditioners from the row and column sums of |K| (A >= 0 entrywise) */
+    for (size_t e = 0; e < n; ++e) ones_n[e] = 1.0;
+    for (size_t e = 0; e < m; ++e) ones_m[e] = 1.0;
+    orc_project(g, -1, ones_n, sig);     /* row sums of A    */
+    orc_backproject(g, -1, ones_m, tau); /* column sums of A */
+    for (size_t e = 0; e < m; ++e) sig[e] = sig[e] > 0.0 ? 1.0 / sig[e] : 1.0;
+    for (int zz = 0; zz < g->nz; ++zz)
+        for (int i = 0; i < g->ny; ++i)
+            for (int j = 0; j < g->nx; ++j) {
+                const size_t e = ((size_t)zz * g->ny + i) * g->nx + j;
+                /* pixel e enters the differences of itself and of its lower neighbours */
+                double cd = (j < g->nx - 1) + (j > 0) + (i < g->ny - 1) + (i > 0);
+                if (G.d == 3) cd += (zz < g->nz - 1) + (zz > 0);
+                tau[e] = 1.0 / (tau[e] + cd);
+            }
+    for (int k = 0; k < n_iters; ++k) {
+        /* primal step */
+        orc_backproject(g, -1, y1, kty);
+        op_DT(&G, y2, dty);
+        for (size_t e = 0; e < n; ++e) {
+            double w = x[e] - tau[e] * (kty[e] + dty[e]);
+            if (nonneg && w < 0.0) w = 0.0;
+            xbar[e] = 2.0 * w - x[e];
+            x[e] = w;
+        }
+        /* dual steps at the extrapolated point */
+        orc_project(g, -1, xbar, axb);
+        for (size_t e = 0; e < m; ++e) y1[e] = (y1[e] + sig[e] * (axb[e] - b[e])) / (1.0 + sig[e]);
+        op_D(&G, xbar, dxb);
+        for (size_t e = 0; e < n; ++e) {
+            double s2 = 0.0;
+            for (int c = 0; c < G.d; ++c) {
+                const double v = y2[c * n + e] + sig_d * dxb[c * n + e];
+                y2[c * n + e] = v;
+                s2 += v * v;
+            }
+            const double nrm = sqrt(s2);
+            if (nrm > alpha) {
+                const double sc = alpha > 0.0 ? alpha / nrm : 0.0;
+                for (int c = 0; c < G.d; ++c) y2[c * n + e] *= sc;
+            }
+        }
+    }
+    free(tau); free(sig); free(ones_n); free(ones_m); free(kty); free(dty); free(xbar); free(axb);
+    free(dxb);
+    return 0;
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

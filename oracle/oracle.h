@@ -163,6 +163,20 @@ int orc_proxskip(const orc_geom *g, const double *b, double *x, double *h, doubl
 int orc_fista(const orc_geom *g, const double *b, double *x, double *dual, double gamma,
               double alpha, int fgp_inner, int nonneg, int n_iters, double *fval_out);
 
+/* High-accuracy reference x* (Sec. 2.1: "a separate primal-dual proximal method", the
+ * data-splitting figure: PDHG with diagonal preconditioning, Chambolle & Pock 2011) for
+ * Eq. 5, min_x 1/2 ||Ax - b||^2 + alpha TV(x) + I_C(x), written as min F(Kx) + G(x) with
+ * K = [A; D], F(u, w) = 1/2 ||u - b||^2 + alpha sum_pixels ||w_pixel||_2, G = I_C:
+ *   tau_j   = 1 / (sum_i |A_ij| + sum_i |D_ij|)     (column sums of |K|)
+ *   sigma_i = 1 / sum_j |A_ij|  (1 where the row is zero),   sigma_D = 1/2  (row sums of |D|)
+ *   x+   = P_C(x - tau (A^T y1 + D^T y2));   xbar = 2 x+ - x
+ *   y1+  = (y1 + sigma (A xbar - b)) / (1 + sigma)               (prox of F1*)
+ *   y2+  = each pixel's d-vector of y2 + sigma_D D xbar scaled onto the ball of radius alpha
+ * x [nz][ny][nx], y1 [nz][A][B], y2 [d][nz][ny][nx]: in/out (zeros for a fresh start).
+ * Returns 0, or -1 on invalid arguments. */
+int orc_pdhg(const orc_geom *g, const double *b, double *x, double *y1, double *y2, double alpha,
+             int nonneg, int n_iters);
+
 /* Threads the OpenMP runtime will use (for reporting). */
 int orc_num_threads(void);
 
