@@ -291,6 +291,22 @@ PS_API ps_status fista_run(const ps_geometry *geom, const void *b, void *x, void
                     double alpha, int32_t fgp_inner, int32_t nonneg, int32_t n_iters,
                     void *workspace, size_t ws_bytes, void *stream);
 
+/* High-accuracy reference solution x* of Eq. 5 (Sec. 2.1: computed with a separate primal-dual
+ * method, PDHG with diagonal preconditioning, Chambolle & Pock 2011, as in the data-splitting
+ * figure), with K = [A; D]:
+ *   tau = 1 / (column sums of |K|),  sigma = 1 / (row sums of A) (1 on empty rays), 1/2 on D
+ *   x+   = P_C(x - tau (A^T y1 + D^T y2)),   xbar = 2 x+ - x
+ *   y1+  = (y1 + sigma (A xbar - b)) / (1 + sigma)
+ *   y2+  = y2 + D xbar / 2, each pixel's d-vector scaled onto the ball of radius alpha
+ * b: device [nz][A][B].  x [nz][ny][nx], y1 [nz][A][B], y2 [d][nz][ny][nx]: device, in/out (zeros
+ * for a fresh start; (x, y1, y2) is the complete state, so runs may be continued).
+ * workspace: at least pdhg_workspace_bytes(geom) bytes.  Stream-ordered; does not synchronise.
+ * Errors: PS_EINVAL, PS_EHIP. */
+PS_API size_t pdhg_workspace_bytes(const ps_geometry *geom);
+PS_API ps_status pdhg_run(const ps_geometry *geom, const void *b, void *x, void *y1, void *y2,
+                   double alpha, int32_t nonneg, int32_t n_iters, void *workspace,
+                   size_t ws_bytes, void *stream);
+
 /* Description of the last error on the calling thread ("" if none). */
 PS_API const char *last_error_message(void);
 

@@ -28,7 +28,7 @@ EXPORTS = (
     "solver_epochs", "solver_epochs_graph", "solver_steps", "solver_done", "solver_query",
     "solver_cancel",
     "solver_free", "sample_sequences", "sample_refresh_coins", "fista_workspace_bytes",
-    "fista_run", "last_error_message",
+    "fista_run", "pdhg_workspace_bytes", "pdhg_run", "last_error_message",
 )
 PS_EST_SVRG, PS_EST_LSVRG, PS_EST_SAGA = 0, 1, 2
 
@@ -118,6 +118,8 @@ def load():
         "sample_refresh_coins": (st, [u64, i64, i64, i32, vp]),
         "fista_workspace_bytes": (sz, [vp]),
         "fista_run": (st, [vp, vp, vp, vp, d, d, i32, i32, i32, vp, sz, vp]),
+        "pdhg_workspace_bytes": (sz, [vp]),
+        "pdhg_run": (st, [vp, vp, vp, vp, vp, d, i32, i32, vp, sz, vp]),
         "last_error_message": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():

@@ -351,6 +351,24 @@ def fista(g: Geometry, b: torch.Tensor, gamma: float, alpha: float, fgp_inner: i
     return x, dual
 
 
+def pdhg(g: Geometry, b: torch.Tensor, alpha: float, n_iters: int, nonneg: bool = True, x=None,
+         y1=None, y2=None):
+    """Reference solution of Eq. 5 by preconditioned PDHG; (x, y1, y2) (zeros if omitted) are
+    advanced n_iters iterations in place and returned.  Stream-ordered on the current stream."""
+    b = g.check(b, (g.nz, g.n_angles, g.n_bins), "b")
+    x = g.zeros_image() if x is None else g.check(x, g.image_shape, "x")
+    y1 = (torch.zeros((g.nz, g.n_angles, g.n_bins), dtype=g.dtype, device=g.device) if y1 is None
+          else g.check(y1, (g.nz, g.n_angles, g.n_bins), "y1"))
+    y2 = (torch.zeros(g.dual_shape(), dtype=g.dtype, device=g.device) if y2 is None
+          else g.check(y2, g.dual_shape(), "y2"))
+    nbytes = g.lib.pdhg_workspace_bytes(g.handle)
+    ws = g.workspace("pdhg", nbytes)
+    nat.check(g.lib.pdhg_run(g.handle, _ptr(b), _ptr(x), _ptr(y1), _ptr(y2), float(alpha),
+                             int(bool(nonneg)), int(n_iters), _ptr(ws), nbytes, _stream(g.device)),
+              "pdhg_run")
+    return x, y1, y2
+
+
 def autotune(g: Geometry, reps: int = 5, cache_path: str | None = None, store: bool = True,
              tune_missing: bool = True) -> dict:
     """Time candidate launch plans on the device and keep the fastest (see geometry_autotune).

@@ -330,7 +330,25 @@ struct UpdateT {
     T *tab, *tsum;
     T gamma, gamma_over_p, nsub;
     int coin, plain;
+    int nx, ny, nz, nonneg;
 };
+
+// (D^T y2) at pixel p of an nx x ny x nz grid (forward differences with a zero last difference;
+// y2 holds d = 2 or 3 components of n values each).
+template <typename T>
+__device__ inline T div_at(const T *__restrict__ y2, size_t p, int nx, int ny, int nz) {
+    const size_t plane = static_cast<size_t>(nx) * ny, n = plane * nz;
+    const int j = static_cast<int>(p % nx), i = static_cast<int>((p / nx) % ny);
+    const int z = static_cast<int>(p / plane);
+    const T *yx = y2, *yy = y2 + n;
+    T t = (j > 0 ? yx[p - 1] : T(0)) - (j < nx - 1 ? yx[p] : T(0));
+    t += (i > 0 ? yy[p - nx] : T(0)) - (i < ny - 1 ? yy[p] : T(0));
+    if (nz > 1) {
+        const T *yz = y2 + 2 * n;
+        t += (z > 0 ? yz[p - plane] : T(0)) - (z < nz - 1 ? yz[p] : T(0));
+    }
+    return t;
+}
 
 // The epilogue of a backprojection at pixel p, d = (A^T y)(p): overwrite, accumulate, or the fused
 // SVRG / ProxSkip gradient step (see UpdateArgs).
@@ -342,6 +360,12 @@ __device__ inline void bp_epilogue(int mode, const UpdateT<T> &upd, T *__restric
         out[p] += d;
     } else if (mode == BP_GRADSTEP) {
         upd.vout[p] = upd.x[p] - upd.gamma * d;
+    } else if (mode == BP_PDHG) {
+        const T xv = upd.x[p];
+        T w = xv - upd.gs[p] * (d + div_at(upd.tab, p, upd.nx, upd.ny, upd.nz));
+        if (upd.nonneg && w < T(0)) w = T(0);
+        upd.vout[p] = T(2) * w - xv;
+        upd.x[p] = w;
     } else {
         T G;
         if (mode == BP_SNAPSHOT) {
@@ -678,6 +702,10 @@ static UpdateT<T> to_update(const UpdateArgs &u) {
     r.vout = static_cast<T *>(u.vout);
     r.tab = static_cast<T *>(u.tab);
     r.tsum = static_cast<T *>(u.tsum);
+    r.nx = u.nx;
+    r.ny = u.ny;
+    r.nz = u.nz;
+    r.nonneg = u.nonneg;
     r.gamma = static_cast<T>(u.gamma);
     r.gamma_over_p = static_cast<T>(u.gamma_over_p);
     r.nsub = static_cast<T>(u.nsub);
@@ -711,7 +739,7 @@ static ps_status backproject_many_t(const BackCall *calls, int n, hipStream_t st
         const BackCall &bc = calls[c];
         const ps_geometry *g = bc.g;
         const auto &d = g->desc;
-        if (bc.mode < BP_OVERWRITE || bc.mode > BP_GRADSTEP)
+        if (bc.mode < BP_OVERWRITE || bc.mode > BP_PDHG)
             return fail(PS_EINVAL, "backprojector mode %d", bc.mode);
         if (back_method(g, bc.subset) == BP_GATHER) {
             GatherItem<T> gi{};

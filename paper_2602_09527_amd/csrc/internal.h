@@ -191,6 +191,7 @@ struct ProjCall {
     const void *x, *xs, *b;
     void *y, *ws;
     size_t ws_bytes;
+    const void *sig = nullptr;   // PDHG dual step: y = (y + sig (A x - b)) / (1 + sig), per ray
 };
 ps_status launch_project_many(const ProjCall *calls, int n, hipStream_t st);
 ps_status launch_project(const ps_geometry *g, int subset, const void *x, const void *xs,
@@ -200,7 +201,7 @@ ps_status launch_project(const ps_geometry *g, int subset, const void *x, const 
 // Backprojector with fused epilogues (backproject.hip).
 // ---------------------------------------------------------------------------------------------
 enum BackMode { BP_OVERWRITE = 0, BP_ACCUMULATE = 1, BP_SVRG = 2, BP_SNAPSHOT = 3, BP_SAGA = 4,
-                BP_GRADSTEP = 5 };
+                BP_GRADSTEP = 5, BP_PDHG = 6 };
 
 // Gradient-step epilogue operands (BP_SVRG, BP_SNAPSHOT, BP_SAGA, BP_GRADSTEP), all [nz][ny][nx]:
 //   d = A^T y at the pixel
@@ -208,6 +209,8 @@ enum BackMode { BP_OVERWRITE = 0, BP_ACCUMULATE = 1, BP_SVRG = 2, BP_SNAPSHOT = 
 //   BP_SNAPSHOT: gs = d (stored), G = d         (iteration at the snapshot: x = xs)
 //   BP_SAGA:     G = nsub * (d - tab) + tsum, then tsum += d - tab, tab = d   (Eq. 4)
 //   BP_GRADSTEP: v = x - gamma d -> vout         (full-gradient step, no h)
+//   BP_PDHG:     w = P_C(x - tau (d + D^T y2)), vout = 2 w - x, x = w   (PDHG primal step;
+//                tau per pixel in `gs`, y2 [d][n] in `tab`, the grid in nx, ny, nz)
 //   plain:       v = x - gamma G                 -> vout
 //   coin = 1:    v = x - gamma (G - h) - (gamma/p) h  -> vout
 //   coin = 0:    x = x - gamma (G - h)           (in place)
@@ -219,6 +222,7 @@ struct UpdateArgs {
     void *tab, *tsum;   // BP_SAGA: the table row of the subset and the table's running sum
     double gamma, gamma_over_p, nsub;
     int coin, plain;
+    int nx, ny, nz, nonneg;   // BP_PDHG
 };
 BackPlan back_plan(const ps_geometry *g, int subset);
 size_t back_workspace(const ps_geometry *g, int subset);

@@ -175,7 +175,7 @@ __device__ inline void stage_cols(T *lds, const T *xz, const T *xsz, int t0, int
 // One projector application: y = inv * A_sub (x - xs) [- b_sub], or partial sums when split.
 template <typename T>
 struct ProjItem {
-    const T *x, *xs, *b;
+    const T *x, *xs, *b, *sig;
     T *out, *part;
     AngleTab<T> tab;
     int subset, nsub, na, nx, ny, nz, nbins, n_angles;
@@ -310,7 +310,12 @@ __global__ __launch_bounds__(kBlock) void k_project(WorkList<ProjItem<T>> wl) {
         if (split == 1) {
             T val = acc * inv;
             if (b) val -= b[(static_cast<size_t>(z) * n_angles + k) * nbins + u];
-            out[(static_cast<size_t>(z) * na + l) * nbins + u] = val;
+            const size_t o = (static_cast<size_t>(z) * na + l) * nbins + u;
+            if (it.sig) {
+                const T sg = it.sig[o];
+                val = (out[o] + sg * val) / (T(1) + sg);
+            }
+            out[o] = val;
         } else {
             part[((static_cast<size_t>(s) * nz_ + z) * na + l) * nbins + u] = acc;
         }
@@ -321,6 +326,7 @@ __global__ __launch_bounds__(kBlock) void k_project(WorkList<ProjItem<T>> wl) {
 template <typename T>
 struct ReduceItem {
     const T *part, *b, *inv;
+    const T *sig;   // PDHG dual step (see ProjItem), or null
     T *y;
     int subset, nsub, na, nz, nbins, split, n_angles, blocks;
 };
@@ -352,6 +358,10 @@ __global__ __launch_bounds__(kBlock) void k_project_reduce(WorkList<ReduceItem<T
         }
         T val = acc * it.inv[k];
         if (b) val -= b[(static_cast<size_t>(z) * it.n_angles + k) * nbins + u];
+        if (it.sig) {
+            const T sg = it.sig[e];
+            val = (y[e] + sg * val) / (T(1) + sg);
+        }
         y[e] = val;
     }
 }
@@ -408,6 +418,7 @@ static ps_status project_many_t(const ProjCall *calls, int n, hipStream_t st) {
         it.x = static_cast<const T *>(pc.x);
         it.xs = static_cast<const T *>(pc.xs);
         it.b = static_cast<const T *>(pc.b);
+        it.sig = static_cast<const T *>(pc.sig);
         it.out = static_cast<T *>(pc.y);
         it.part = part;
         it.tab = angle_tab<T>(g);
@@ -452,6 +463,7 @@ static ps_status project_many_t(const ProjCall *calls, int n, hipStream_t st) {
         ReduceItem<T> r{};
         r.part = pi.part;
         r.b = pi.b;
+        r.sig = pi.sig;
         r.inv = pi.tab.inv;
         r.y = pi.out;
         r.subset = pi.subset;
