@@ -283,13 +283,16 @@ PS_API ps_status sample_refresh_coins(uint64_t seed, int64_t k0, int64_t count, 
  * with the full gradient and the same prox as Algorithm 1:
  *   x_{k+1} = prox_{gamma g}(y_k - gamma A^T (A y_k - b)),  t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2,
  *   y_{k+1} = x_{k+1} + ((t_k - 1) / t_{k+1}) (x_{k+1} - x_k),   y_0 = x_0,  t_0 = 1.
- * b: device [nz][A][B].  x: device, in x_0, out x_K.  dual: device [d][nz][ny][nx] FGP warm
- * start, in/out (zeros for a fresh run).  workspace: at least fista_workspace_bytes(geom) bytes.
- * Stream-ordered; does not synchronise.  Errors: PS_EINVAL, PS_EHIP. */
+ * b: device [nz][A][B].  x: device, in x_k, out x_{k+n_iters}.  y: device [nz][ny][nx], in y_k,
+ * out y_{k+n_iters} (a copy of x_0 for a fresh run).  t: host, in t_k, out t_{k+n_iters} (1 for
+ * a fresh run).  dual: device [d][nz][ny][nx] FGP warm start, in/out (zeros for a fresh run).
+ * (x, y, dual, t) is the complete state: consecutive calls continue one run.
+ * workspace: at least fista_workspace_bytes(geom) bytes.  Stream-ordered; does not
+ * synchronise.  Errors: PS_EINVAL, PS_EHIP. */
 PS_API size_t fista_workspace_bytes(const ps_geometry *geom);
-PS_API ps_status fista_run(const ps_geometry *geom, const void *b, void *x, void *dual, double gamma,
-                    double alpha, int32_t fgp_inner, int32_t nonneg, int32_t n_iters,
-                    void *workspace, size_t ws_bytes, void *stream);
+PS_API ps_status fista_run(const ps_geometry *geom, const void *b, void *x, void *y, void *dual,
+                    double *t, double gamma, double alpha, int32_t fgp_inner, int32_t nonneg,
+                    int32_t n_iters, void *workspace, size_t ws_bytes, void *stream);
 
 /* High-accuracy reference solution x* of Eq. 5 (Sec. 2.1: computed with a separate primal-dual
  * method, PDHG with diagonal preconditioning, Chambolle & Pock 2011, as in the data-splitting

@@ -117,7 +117,7 @@ def load():
         "sample_sequences": (st, [u64, i64, i64, i32, d, vp, vp]),
         "sample_refresh_coins": (st, [u64, i64, i64, i32, vp]),
         "fista_workspace_bytes": (sz, [vp]),
-        "fista_run": (st, [vp, vp, vp, vp, d, d, i32, i32, i32, vp, sz, vp]),
+        "fista_run": (st, [vp, vp, vp, vp, vp, C.POINTER(d), d, d, i32, i32, i32, vp, sz, vp]),
         "pdhg_workspace_bytes": (sz, [vp]),
         "pdhg_run": (st, [vp, vp, vp, vp, vp, d, i32, i32, vp, sz, vp]),
         "last_error_message": (C.c_char_p, []),

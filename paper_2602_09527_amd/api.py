@@ -335,20 +335,41 @@ def sample_refresh_coins(seed: int, k0: int, count: int, n_subsets: int):
     return out[:count]
 
 
+class Fista:
+    """FISTA with the full gradient and the TV prox (resumable: each call continues the run).
+
+    State: x, the extrapolated point y, the FGP dual and the momentum scalar t (zeros / x_0 / 1
+    for a fresh run).  Stream-ordered on the current stream."""
+
+    def __init__(self, g: Geometry, b: torch.Tensor, gamma: float, alpha: float, fgp_inner: int,
+                 nonneg: bool = True, x=None, dual=None):
+        self.g = g
+        self.b = g.check(b, (g.nz, g.n_angles, g.n_bins), "b")
+        self.x = g.zeros_image() if x is None else g.check(x, g.image_shape, "x")
+        self.y = self.x.clone()
+        self.dual = (torch.zeros(g.dual_shape(), dtype=g.dtype, device=g.device) if dual is None
+                     else g.check(dual, g.dual_shape(), "dual"))
+        self.t = C.c_double(1.0)
+        self.gamma, self.alpha, self.fgp_inner, self.nonneg = gamma, alpha, fgp_inner, nonneg
+        self.nbytes = g.lib.fista_workspace_bytes(g.handle)
+        self.ws = torch.empty(max(self.nbytes, 1), dtype=torch.uint8, device=g.device)
+
+    def run(self, n_iters: int):
+        g = self.g
+        nat.check(g.lib.fista_run(g.handle, _ptr(self.b), _ptr(self.x), _ptr(self.y),
+                                  _ptr(self.dual), C.byref(self.t), float(self.gamma),
+                                  float(self.alpha), int(self.fgp_inner), int(bool(self.nonneg)),
+                                  int(n_iters), _ptr(self.ws), self.nbytes, _stream(g.device)),
+                  "fista_run")
+        return self
+
+
 def fista(g: Geometry, b: torch.Tensor, gamma: float, alpha: float, fgp_inner: int, n_iters: int,
           nonneg: bool = True, x=None, dual=None):
-    """FISTA with the full gradient and the TV prox; x and dual (zeros if omitted) are updated
-    in place.  Returns (x, dual).  Stream-ordered on the current stream."""
-    b = g.check(b, (g.nz, g.n_angles, g.n_bins), "b")
-    x = g.zeros_image() if x is None else g.check(x, g.image_shape, "x")
-    dual = (torch.zeros(g.dual_shape(), dtype=g.dtype, device=g.device) if dual is None
-            else g.check(dual, g.dual_shape(), "dual"))
-    nbytes = g.lib.fista_workspace_bytes(g.handle)
-    ws = g.workspace("fista", nbytes)
-    nat.check(g.lib.fista_run(g.handle, _ptr(b), _ptr(x), _ptr(dual), float(gamma), float(alpha),
-                              int(fgp_inner), int(bool(nonneg)), int(n_iters), _ptr(ws), nbytes,
-                              _stream(g.device)), "fista_run")
-    return x, dual
+    """A fresh FISTA run of n_iters iterations from x (zeros if omitted); x and dual are
+    updated in place.  Returns (x, dual)."""
+    f = Fista(g, b, gamma, alpha, fgp_inner, nonneg=nonneg, x=x, dual=dual).run(n_iters)
+    return f.x, f.dual
 
 
 def pdhg(g: Geometry, b: torch.Tensor, alpha: float, n_iters: int, nonneg: bool = True, x=None,

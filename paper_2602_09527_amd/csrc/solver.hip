@@ -820,7 +820,7 @@ extern "C" ps_status proxskip_svrg_run(const ps_geometry *g, const void *b, void
 namespace ps {
 
 struct FistaLayout {
-    size_t y, v, xn, sino, pws, bws, fws, total;
+    size_t v, xn, sino, pws, bws, fws, total;
     size_t pws_bytes, bws_bytes, fws_bytes;
 };
 
@@ -831,7 +831,6 @@ static FistaLayout fista_layout(const ps_geometry *g) {
     FistaLayout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes); return o; };
-    L.y = take(n * g->elem);
     L.v = take(n * g->elem);
     L.xn = take(n * g->elem);
     L.sino = take(m * g->elem);
@@ -861,9 +860,10 @@ extern "C" size_t fista_workspace_bytes(const ps_geometry *g) {
     return fista_layout(g).total;
 }
 
-extern "C" ps_status fista_run(const ps_geometry *g, const void *b, void *x, void *dual, double gamma,
-                               double alpha, int32_t fgp_inner, int32_t nonneg, int32_t n_iters,
-                               void *workspace, size_t ws_bytes, void *stream) {
+extern "C" ps_status fista_run(const ps_geometry *g, const void *b, void *x, void *y, void *dual,
+                               double *t_io, double gamma, double alpha, int32_t fgp_inner,
+                               int32_t nonneg, int32_t n_iters, void *workspace, size_t ws_bytes,
+                               void *stream) {
     clear_error();
     if (!g) return fail(PS_EINVAL, "geometry is null");
     PS_TRY(check_ready(g));
@@ -872,8 +872,10 @@ extern "C" ps_status fista_run(const ps_geometry *g, const void *b, void *x, voi
     if (fgp_inner < 0) return fail(PS_EINVAL, "fgp_inner must be >= 0");
     if (nonneg != 0 && nonneg != 1) return fail(PS_EINVAL, "nonneg must be 0 or 1");
     if (n_iters < 0) return fail(PS_EINVAL, "n_iters must be >= 0");
+    if (!t_io || !(*t_io >= 1.0) || !std::isfinite(*t_io)) return fail(PS_EINVAL, "t must point to a value >= 1");
     PS_TRY(check_ptr(b, "b", g->elem));
     PS_TRY(check_ptr(x, "x", g->elem));
+    PS_TRY(check_ptr(y, "y", g->elem));
     PS_TRY(check_ptr(dual, "dual", g->elem));
     PS_TRY(check_ptr(workspace, "workspace", kAlign));
     const FistaLayout L = fista_layout(g);
@@ -883,13 +885,11 @@ extern "C" ps_status fista_run(const ps_geometry *g, const void *b, void *x, voi
     const auto &d = g->desc;
     const size_t n = static_cast<size_t>(d.nx) * d.ny * d.nz;
     unsigned char *w = static_cast<unsigned char *>(workspace);
-    if (n_iters == 0) return PS_OK;
-    PS_HIP(hipMemcpyAsync(w + L.y, x, n * g->elem, hipMemcpyDeviceToDevice, st));   // y_0 = x_0
-    double t = 1.0;
+    double t = *t_io;
     for (int k = 0; k < n_iters; ++k) {
-        PS_TRY(launch_project(g, -1, w + L.y, nullptr, b, w + L.sino, w + L.pws, L.pws_bytes, st));
+        PS_TRY(launch_project(g, -1, y, nullptr, b, w + L.sino, w + L.pws, L.pws_bytes, st));
         UpdateArgs up{};
-        up.x = w + L.y;
+        up.x = y;
         up.vout = w + L.v;
         up.gamma = gamma;
         PS_TRY(launch_backproject(g, -1, w + L.sino, nullptr, BP_GRADSTEP, &up, w + L.bws, L.bws_bytes, st));
@@ -899,9 +899,10 @@ extern "C" ps_status fista_run(const ps_geometry *g, const void *b, void *x, voi
         PS_TRY(launch_fgp(g, w + L.v, dual, gamma * alpha, fgp_inner, nonneg, fo, w + L.fws, L.fws_bytes, st));
         const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
         const double beta = (t - 1.0) / tn;
-        PS_TRY(d.dtype == PS_F64 ? fista_momentum<double>(x, w + L.xn, w + L.y, beta, n, st)
-                                 : fista_momentum<float>(x, w + L.xn, w + L.y, beta, n, st));
+        PS_TRY(d.dtype == PS_F64 ? fista_momentum<double>(x, w + L.xn, y, beta, n, st)
+                                 : fista_momentum<float>(x, w + L.xn, y, beta, n, st));
         t = tn;
     }
+    *t_io = t;
     return PS_OK;
 }

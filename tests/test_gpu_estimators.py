@@ -164,3 +164,15 @@ def test_fista_first_iteration_is_ista_step():
                                                    n_epochs=1, plain_prox_svrg=True))
     torch.cuda.synchronize()
     assert torch.equal(xf, xi) and torch.equal(df, di)
+
+
+def test_fista_continuation_bitwise():
+    from paper_2602_09527_amd import api, synth
+    prob = synth.make_problem(96, 96, 120, 144, seed=6, with_phantom=False)
+    g = api.Geometry(96, 96, 120, 144, n_subsets=1)
+    b = torch.from_numpy(prob.b).to(device="cuda", dtype=torch.float32)
+    kw = dict(gamma=1.0 / api.lipschitz(g, 30), alpha=0.02, fgp_inner=20)
+    one = api.Fista(g, b, **kw).run(25)
+    two = api.Fista(g, b, **kw).run(10).run(15)
+    torch.cuda.synchronize()
+    assert torch.equal(one.x, two.x) and torch.equal(one.y, two.y) and one.t.value == two.t.value
