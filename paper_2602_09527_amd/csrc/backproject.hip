@@ -45,6 +45,7 @@ struct ScatterAngle {
 };
 
 constexpr int kScatterAngles = 64;   // angle records staged in LDS at a time
+constexpr int kPrefetch = 4;         // work units whose ray values are loaded ahead
 
 static size_t scatter_angle_bytes(size_t elem) {
     return elem == sizeof(double) ? sizeof(ScatterAngle<double>) : sizeof(ScatterAngle<float>);
@@ -169,15 +170,19 @@ __global__ __launch_bounds__(kBlock) void k_backproject(WorkList<BackItem<T>> wl
             ++e;
         }
     };
-    // ray values (y / |cos| or y / |sin|) of one work unit, for up to NP passes
+    // raw ray values of one work unit, for up to NP passes: plain loads from a clamped (always
+    // valid) bin, so that nothing waits for them until they are used (scaled by ray_value)
     auto fetch = [&](int e, int c, T *yv) {
         const int l = uni(angs[e].l);
-        const T inv = uni(angs[e].inv);
         const T *yl = yz + static_cast<size_t>(l) * nbins + c * span;
-        const int room = nbins - c * span;
+        const int last = nbins - 1 - c * span;   // >= 0: c < chunks
 #pragma unroll
-        for (int pass = 0; pass < (NP > 0 ? NP : 1); ++pass)
-            yv[pass] = pass + lp < room ? yl[pass + lp] * inv : T(0);
+        for (int pass = 0; pass < (NP > 0 ? NP : 1); ++pass) yv[pass] = yl[min(pass + lp, last)];
+    };
+    // the deposited value y / |cos| (or y / |sin|), zero for lanes past the last bin
+    auto ray_value = [&](int e, int c, int pass, T raw) {
+        const T v = raw * uni(angs[e].inv);
+        return pass + lp < nbins - c * span ? v : T(0);   // a select, not a branch
     };
     // deposit one ray of value y0 through the strip; FP32: q = its fixed-point position at the
     // strip's first step (plus the pad)
@@ -255,30 +260,48 @@ __global__ __launch_bounds__(kBlock) void k_backproject(WorkList<BackItem<T>> wl
         __syncthreads();
         int e = wave / chunks, c = wave - e * chunks;   // this wave's first unit
         if constexpr (NP > 0) {
-            // software pipeline: the next unit's ray values are in flight while this one deposits
-            T ynext[NP];
-            if (e < an) fetch(e, c, ynext);
+            // software pipeline: the ray values of the next kPrefetch units are in flight while
+            // this one deposits (a unit's deposits take far less time than a load that misses
+            // the XCD's L2, as the values written by the previous launch on another XCD do)
+            // every fetch is issued (past the last unit it reloads unit (an - 1, 0), unused), so
+            // the number of loads in flight is the same on every path and a use waits only for
+            // its own slot
+            T ybuf[kPrefetch][NP];
+            int fe = e, fc = c;   // the next unit to fetch
+            auto fetch_any = [&](T *yv) {
+                if (fe < an) fetch(fe, fc, yv);
+                else fetch(an - 1, 0, yv);
+            };
+#pragma unroll
+            for (int d = 0; d < kPrefetch; ++d) {
+                fetch_any(ybuf[d]);
+                advance(fe, fc);
+            }
             while (e < an) {
-                T ycur[NP];
 #pragma unroll
-                for (int q = 0; q < NP; ++q) ycur[q] = ynext[q];
-                int en = e, cn = c;
-                advance(en, cn);
-                if (en < an) fetch(en, cn, ynext);
-                if constexpr (kFixed) {
-                    int64_t q1, q2;
-                    int64_t q = lane_q(e, c, q1, q2);
+                for (int d = 0; d < kPrefetch; ++d) {
+                    if (e < an) {
+                        T ycur[NP];
 #pragma unroll
-                    for (int pass = 0; pass < NP; ++pass) {
-                        deposit_fixed(q, q2, ycur[pass]);
-                        q += q1;
+                        for (int q = 0; q < NP; ++q) ycur[q] = ray_value(e, c, q, ybuf[d][q]);
+                        fetch_any(ybuf[d]);
+                        advance(fe, fc);
+                        if constexpr (kFixed) {
+                            int64_t q1, q2;
+                            int64_t q = lane_q(e, c, q1, q2);
+#pragma unroll
+                            for (int pass = 0; pass < NP; ++pass) {
+                                deposit_fixed(q, q2, ycur[pass]);
+                                q += q1;
+                            }
+                        } else {
+#pragma unroll
+                            for (int pass = 0; pass < NP; ++pass)
+                                deposit_float(e, c * span + pass + lp, ycur[pass]);
+                        }
+                        advance(e, c);
                     }
-                } else {
-#pragma unroll
-                    for (int pass = 0; pass < NP; ++pass) deposit_float(e, c * span + pass + lp, ycur[pass]);
                 }
-                e = en;
-                c = cn;
             }
         } else {
             for (; e < an; advance(e, c)) {
@@ -415,14 +438,16 @@ __global__ __launch_bounds__(kBlock) void k_backproject_combine(WorkList<Combine
     const int groups = it.groups, mode = it.mode;
     for (size_t p = local * static_cast<size_t>(kBlock) + threadIdx.x; p < n;
          p += static_cast<size_t>(it.blocks) * kBlock) {
+        // fixed order over the 2G partials; the loads of a batch of 8 are unconditional (clamped
+        // to the last partial) so that they are all in flight before the first add
+        const int np = 2 * groups;
         T d = T(0);
-        for (int q0 = 0; q0 < 2 * groups; q0 += 8) {
+        for (int q0 = 0; q0 < np; q0 += 8) {
             T v[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) v[q] = q0 + q < 2 * groups ? part[(q0 + q) * n + p] : T(0);
+            for (int q = 0; q < 8; ++q) v[q] = part[static_cast<size_t>(min(q0 + q, np - 1)) * n + p];
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
-                if (q0 + q < 2 * groups) d += v[q];
+            for (int q = 0; q < 8; ++q) d = q0 + q < np ? d + v[q] : d;
         }
         bp_epilogue(mode, upd, out, p, d);
     }
@@ -608,11 +633,28 @@ __global__ __launch_bounds__(kBlock) void k_backproject_gather(WorkList<GatherIt
             ulo[threadIdx.x] = static_cast<int>(floor(min(min(u1, u2), min(u3, u4)))) - 3;
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < cn * kGatherWin; e += blockDim.x) {
-            const int a = e / kGatherWin, w = e - a * kGatherWin;
-            const int l = c0 + a;
-            const int u = ulo[a] + w;
-            ywin[a][w] = (u >= 0 && u < B) ? yz[static_cast<size_t>(l) * B + u] * s_ang[a].inv : T(0);
+        // each thread's window entries: all loads first (bins clamped into range), then the
+        // scaled values (zero outside the detector) go to LDS
+        constexpr int kWinPer = (kGatherChunk * kGatherWin + kBlock - 1) / kBlock;
+        {
+            T raw[kWinPer];
+#pragma unroll
+            for (int r = 0; r < kWinPer; ++r) {
+                const int e = static_cast<int>(threadIdx.x) + r * kBlock;
+                const int a = min(e / kGatherWin, cn - 1), w = e - (e / kGatherWin) * kGatherWin;
+                const int u = min(max(ulo[a] + w, 0), B - 1);
+                raw[r] = yz[static_cast<size_t>(c0 + a) * B + u];
+            }
+#pragma unroll
+            for (int r = 0; r < kWinPer; ++r) {
+                const int e = static_cast<int>(threadIdx.x) + r * kBlock;
+                const int a = e / kGatherWin, w = e - a * kGatherWin;
+                if (a < cn) {
+                    const int u = ulo[a] + w;
+                    const T v = raw[r] * s_ang[a].inv;
+                    ywin[a][w] = (u >= 0 && u < B) ? v : T(0);
+                }
+            }
         }
         __syncthreads();
         // the next angle's record is read while this one is processed

@@ -347,14 +347,15 @@ __global__ __launch_bounds__(kBlock) void k_project_reduce(WorkList<ReduceItem<T
         const int l = static_cast<int>(zl % na);
         const int z = static_cast<int>(zl / na);
         const int k = it.subset < 0 ? l : it.subset + l * it.nsub;
+        // fixed order over the split partials; a batch's 8 loads are unconditional (clamped to
+        // the last partial) so that they are all in flight before the first add
         T acc = T(0);
         for (int s0 = 0; s0 < split; s0 += 8) {
             T v[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) v[q] = s0 + q < split ? part[(s0 + q) * total + e] : T(0);
+            for (int q = 0; q < 8; ++q) v[q] = part[static_cast<size_t>(min(s0 + q, split - 1)) * total + e];
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
-                if (s0 + q < split) acc += v[q];
+            for (int q = 0; q < 8; ++q) acc = s0 + q < split ? acc + v[q] : acc;
         }
         T val = acc * it.inv[k];
         if (b) val -= b[(static_cast<size_t>(z) * it.n_angles + k) * nbins + u];
