@@ -351,6 +351,8 @@ struct UpdateT {
     T *gs;
     T *vout;
     T *tab, *tsum;
+    const T *xs;
+    T *dx;
     T gamma, gamma_over_p, nsub;
     int coin, plain;
     int nx, ny, nz, nonneg;
@@ -409,10 +411,12 @@ __device__ inline void bp_epilogue(int mode, const UpdateT<T> &upd, T *__restric
         } else {
             const T hv = upd.h[p];
             const T xh = xv - upd.gamma * (G - hv);
-            if (upd.coin)
+            if (upd.coin) {
                 upd.vout[p] = xh - upd.gamma_over_p * hv;
-            else
+            } else {
                 upd.x[p] = xh;
+                if (upd.dx) upd.dx[p] = xh - upd.xs[p];
+            }
         }
     }
 }
@@ -744,6 +748,8 @@ static UpdateT<T> to_update(const UpdateArgs &u) {
     r.vout = static_cast<T *>(u.vout);
     r.tab = static_cast<T *>(u.tab);
     r.tsum = static_cast<T *>(u.tsum);
+    r.xs = static_cast<const T *>(u.xs);
+    r.dx = static_cast<T *>(u.dx);
     r.nx = u.nx;
     r.ny = u.ny;
     r.nz = u.nz;

@@ -220,6 +220,8 @@ struct UpdateArgs {
     void *gs;
     void *vout;
     void *tab, *tsum;   // BP_SAGA: the table row of the subset and the table's running sum
+    const void *xs;     // with dx: the snapshot, and
+    void *dx;           //   dx = x - xs written beside x (coin = 0 steps of BP_SVRG / BP_SNAPSHOT)
     double gamma, gamma_over_p, nsub;
     int coin, plain;
     int nx, ny, nz, nonneg;   // BP_PDHG

@@ -141,6 +141,15 @@ __global__ __launch_bounds__(kBlock) void k_fista_momentum(T *__restrict__ x, co
     }
 }
 
+// dx = x - xs (the SVRG difference after a prox step rewrote x).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_diff(const T *__restrict__ x, const T *__restrict__ xs,
+                                                 T *__restrict__ dx, size_t n) {
+    for (size_t e = blockIdx.x * static_cast<size_t>(kBlock) + threadIdx.x; e < n;
+         e += static_cast<size_t>(gridDim.x) * kBlock)
+        dx[e] = x[e] - xs[e];
+}
+
 static int elementwise_blocks(size_t n) {
     return static_cast<int>(std::max<size_t>(1, std::min<size_t>((n + kBlock - 1) / kBlock, 8192)));
 }
@@ -150,9 +159,20 @@ static int norm_blocks(size_t n) {
 }
 
 struct Layout {
-    size_t xs, gs, v, xe, tab, tsum, sino, pws, bws, fws, npart, stats, total;
+    size_t xs, gs, v, xe, tab, tsum, dx, sino, pws, bws, fws, npart, stats, total;
     size_t pws_bytes, bws_bytes, fws_bytes;
 };
+
+// The SVRG difference dx = x - xs kept in the workspace for the subset projector, once x and xs
+// together outgrow an XCD's 4 MiB L2: the projector then reads one image instead of two, which
+// it would otherwise fetch from HBM for every angle's rows.  dx is written where x is written
+// (the backprojector epilogue, or k_diff after a prox), with the projector's own subtraction, so
+// the results are bit for bit the same either way.
+static bool keeps_difference(const ps_geometry *g, int estimator) {
+    const auto &d = g->desc;
+    const size_t n = static_cast<size_t>(d.nx) * d.ny * d.nz;
+    return estimator != PS_EST_SAGA && 2 * n * g->elem > (static_cast<size_t>(4) << 20);
+}
 
 static Layout layout(const ps_geometry *g, int n_epochs, int estimator) {
     const auto &d = g->desc;
@@ -171,6 +191,7 @@ static Layout layout(const ps_geometry *g, int n_epochs, int estimator) {
         L.tab = take(static_cast<size_t>(d.n_subsets) * n * g->elem);
         L.tsum = take(n * g->elem);
     }
+    if (keeps_difference(g, estimator)) L.dx = take(n * g->elem);
     L.sino = take(m * g->elem);
     L.pws_bytes = std::max(proj_workspace(g, d.n_angles), proj_workspace(g, max_subset_count(g)));
     L.pws = take(L.pws_bytes);
@@ -378,7 +399,7 @@ static bool snapshot_now(const ps_solver *s, int t) {
 static ps_status run_step(const std::vector<ps_solver *> &hs, hipStream_t st,
                           std::vector<ps_solver *> &ending) {
     std::vector<SnapReq> copies;
-    std::vector<ps_solver *> fills;
+    std::vector<ps_solver *> fills, refresh_diff;
     std::vector<ProjCall> pc;
     std::vector<BackCall> bc;
     std::vector<FgpCall> fc;
@@ -417,6 +438,12 @@ static ps_status run_step(const std::vector<ps_solver *> &hs, hipStream_t st,
         up.nsub = static_cast<double>(N);
         up.plain = P.plain_prox_svrg;
         up.coin = s->coin[t];
+        const bool diff = s->L.dx != 0;
+        if (diff) {
+            up.xs = w + s->L.xs;
+            up.dx = w + s->L.dx;
+            if (prox) refresh_diff.push_back(s);   // x is rewritten by the prox: dx after it
+        }
         if (est == PS_EST_SAGA) {
             // y = A_i x - b_i; G = N (A_i^T y - v_i) + vbar with the table updated in the epilogue
             const size_t n = static_cast<size_t>(g->desc.nx) * g->desc.ny * g->desc.nz;
@@ -429,7 +456,10 @@ static ps_status run_step(const std::vector<ps_solver *> &hs, hipStream_t st,
             pc.push_back(ProjCall{g, -1, w + s->L.xs, nullptr, s->b, w + s->L.sino, w + s->L.pws, s->L.pws_bytes});
             bc.push_back(BackCall{g, -1, w + s->L.sino, nullptr, BP_SNAPSHOT, up, w + s->L.bws, s->L.bws_bytes});
         } else {
-            pc.push_back(ProjCall{g, i, s->x, w + s->L.xs, nullptr, w + s->L.sino, w + s->L.pws, s->L.pws_bytes});
+            if (diff)
+                pc.push_back(ProjCall{g, i, w + s->L.dx, nullptr, nullptr, w + s->L.sino, w + s->L.pws, s->L.pws_bytes});
+            else
+                pc.push_back(ProjCall{g, i, s->x, w + s->L.xs, nullptr, w + s->L.sino, w + s->L.pws, s->L.pws_bytes});
             bc.push_back(BackCall{g, i, w + s->L.sino, nullptr, BP_SVRG, up, w + s->L.bws, s->L.bws_bytes});
         }
         if (prox) {
@@ -451,6 +481,19 @@ static ps_status run_step(const std::vector<ps_solver *> &hs, hipStream_t st,
     PS_TRY(launch_project_many(pc.data(), static_cast<int>(pc.size()), st));
     PS_TRY(launch_backproject_many(bc.data(), static_cast<int>(bc.size()), st));
     if (!fc.empty()) PS_TRY(launch_fgp_many(fc.data(), static_cast<int>(fc.size()), st));
+    for (ps_solver *s : refresh_diff) {
+        const auto &d = s->g->desc;
+        const size_t n = static_cast<size_t>(d.nx) * d.ny * d.nz;
+        if (d.dtype == PS_F64)
+            hipLaunchKernelGGL((k_diff<double>), dim3(elementwise_blocks(n)), dim3(kBlock), 0, st,
+                               static_cast<const double *>(s->x), reinterpret_cast<const double *>(s->ws + s->L.xs),
+                               reinterpret_cast<double *>(s->ws + s->L.dx), n);
+        else
+            hipLaunchKernelGGL((k_diff<float>), dim3(elementwise_blocks(n)), dim3(kBlock), 0, st,
+                               static_cast<const float *>(s->x), reinterpret_cast<const float *>(s->ws + s->L.xs),
+                               reinterpret_cast<float *>(s->ws + s->L.dx), n);
+        PS_LAUNCHED("k_diff");
+    }
     if (!ending.empty()) {
         // ||x_e - x_{e-1}||, ||x_e||: x_{e-1} is the SVRG snapshot, else the kept copy xe
         std::vector<SnapReq> norms;

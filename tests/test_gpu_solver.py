@@ -151,3 +151,22 @@ def test_volume_3d_reduced_10_epochs(orc):
     assert st["prox_calls"] == so["prox_calls"] > 0
     assert _rel(x, xo) <= 1e-4, _rel(x, xo)
     assert _rel(d, do) <= 1e-3, _rel(d, do)
+
+
+@pytest.mark.parametrize("estimator", ["svrg", "lsvrg"])
+def test_large_image_keeps_the_difference(orc, estimator):
+    # 768^2: x and the snapshot outgrow one XCD's L2, so the solver keeps dx = x - xs for the
+    # subset projector (written by the step's epilogue, or after a prox); p = 0.5 takes both paths
+    from paper_2602_09527_amd import api, synth
+    nx, A, B, N = 768, 180, 1024, 10
+    prob = synth.make_problem(nx, nx, A, B, seed=61, with_phantom=False)
+    g = api.Geometry(nx, nx, A, B, n_subsets=N)
+    o = orc.Geometry(nx, nx, A, B, n_subsets=N)
+    kw = dict(gamma=1.0 / api.lipschitz(g, 30), p=0.5, alpha=0.01, fgp_inner=20, n_epochs=2,
+              nonneg=True, seed=62)
+    xo, _, _, so, _ = orc.proxskip(o, prob.b, estimator=estimator, **kw)
+    b = torch.from_numpy(prob.b).to(device="cuda", dtype=torch.float32)
+    x, _, _, st = api.solve(g, b, api.SolverParams(estimator=estimator, **kw))
+    torch.cuda.synchronize()
+    assert st["prox_calls"] == so["prox_calls"] and st["prox_calls"] > 0
+    assert _rel(x.cpu().numpy(), xo) <= 1e-4, _rel(x.cpu().numpy(), xo)
