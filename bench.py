@@ -102,6 +102,9 @@ def parse():
                     help="only run a plain 256 MiB device copy (for HBM counter scaling)")
     ap.add_argument("--volume", action="store_true",
                     help="time the 256 x 1024^2 volume workload (1800 x 1448, 30 subsets) instead")
+    ap.add_argument("--volume-ops", action="store_true",
+                    help="only run one subset projection, one subset backprojection and a 10-iteration "
+                         "3D prox on the volume geometry with random inputs (for counter collection)")
     return ap.parse_args()
 
 
@@ -191,6 +194,30 @@ def time_to_eps(api, torch, g, b, w, gamma, ref_iters, passes, alpha):
                           "seconds": round(t_ref, 2), "sq_change_last_half": ref_change},
             "criterion": "||x - x*||^2 / ||x*||^2 < eps, at most %d data passes" % passes,
             "runs": runs}
+
+
+def volume_ops():
+    """One subset projection, one subset backprojection and a 10-iteration 3D TV prox on the
+    256 x 1024^2 volume geometry with its stored plan and random inputs: a short program for
+    hardware counters (under counter collection the synthetic sinogram takes minutes)."""
+    import torch
+    from paper_2602_09527_amd import api, workloads
+    w = workloads.VOLUME_3D
+    g = api.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=w.n_subsets, nz=w.nz)
+    plan = api.autotune(g, reps=2, cache_path=PLANS_FILE, store=False, tune_missing=False)
+    log(f"bench: volume ops, launch plan {plan}")
+    x = torch.rand(g.image_shape, device="cuda")
+    y = torch.empty(g.sino_shape(0), device="cuda")
+    api.project(g, x, 0, out=y)
+    torch.cuda.synchronize()
+    log("bench: volume ops: subset projection done")
+    api.backproject(g, y, 0, out=x)
+    torch.cuda.synchronize()
+    log("bench: volume ops: subset backprojection done")
+    dual = torch.zeros(g.dual_shape(), device="cuda")
+    api.tv_prox(g, x, 1e-4, 10, dual=dual, out=torch.empty_like(x))
+    torch.cuda.synchronize()
+    log("bench: volume ops: 10-iteration prox done")
 
 
 def bench_volume(args):
@@ -362,6 +389,9 @@ def main():
 
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.volume_ops:
+        volume_ops()
         return
     if args.volume:
         bench_volume(args)
