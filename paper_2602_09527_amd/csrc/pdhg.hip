@@ -165,10 +165,10 @@ extern "C" ps_status pdhg_run(const ps_geometry *g, const void *b, void *x, void
                               size_t ws_bytes, void *stream) {
     clear_error();
     if (!g) return fail(PS_EINVAL, "geometry is null");
-    PS_TRY(check_ready(g));
     if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(PS_EINVAL, "alpha must be >= 0");
     if (nonneg != 0 && nonneg != 1) return fail(PS_EINVAL, "nonneg must be 0 or 1");
     if (n_iters < 0) return fail(PS_EINVAL, "n_iters must be >= 0");
+    PS_TRY(check_ready(g));
     PS_TRY(check_ptr(b, "b", g->elem));
     PS_TRY(check_ptr(x, "x", g->elem));
     PS_TRY(check_ptr(y1, "y1", g->elem));

@@ -909,13 +909,13 @@ extern "C" ps_status fista_run(const ps_geometry *g, const void *b, void *x, voi
                                void *stream) {
     clear_error();
     if (!g) return fail(PS_EINVAL, "geometry is null");
-    PS_TRY(check_ready(g));
     if (!(gamma > 0.0) || !std::isfinite(gamma)) return fail(PS_EINVAL, "gamma must be > 0");
     if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(PS_EINVAL, "alpha must be >= 0");
     if (fgp_inner < 0) return fail(PS_EINVAL, "fgp_inner must be >= 0");
     if (nonneg != 0 && nonneg != 1) return fail(PS_EINVAL, "nonneg must be 0 or 1");
     if (n_iters < 0) return fail(PS_EINVAL, "n_iters must be >= 0");
     if (!t_io || !(*t_io >= 1.0) || !std::isfinite(*t_io)) return fail(PS_EINVAL, "t must point to a value >= 1");
+    PS_TRY(check_ready(g));
     PS_TRY(check_ptr(b, "b", g->elem));
     PS_TRY(check_ptr(x, "x", g->elem));
     PS_TRY(check_ptr(y, "y", g->elem));

@@ -169,3 +169,43 @@ def test_plan_get_set_and_validation(nat):
         assert lib.geometry_autotune(h, None, 0, 3, None, None) == nat.PS_EINVAL
     finally:
         lib.free_geometry(h)
+
+
+@pytest.mark.parametrize("bad", [dict(gamma=0.0), dict(gamma=float("nan")), dict(alpha=-1.0),
+                                 dict(fgp_inner=-1), dict(nonneg=2), dict(n_iters=-1), dict(t=0.5),
+                                 dict(t=None)])
+def test_fista_arguments_rejected(nat, bad):
+    lib = nat.load()
+    h = C.c_void_p()
+    assert lib.make_geometry(C.byref(_desc(nat)), C.byref(h)) == nat.PS_OK
+    try:
+        assert lib.fista_workspace_bytes(h) > 0 and lib.fista_workspace_bytes(None) == 0
+        a = dict(gamma=1e-3, alpha=0.1, fgp_inner=5, nonneg=1, n_iters=3, t=1.0)
+        a.update(bad)
+        t = None if a["t"] is None else C.byref(C.c_double(a["t"]))
+        fake = C.c_void_p(256)
+        st = lib.fista_run(h, fake, fake, fake, fake, t, a["gamma"], a["alpha"], a["fgp_inner"],
+                           a["nonneg"], a["n_iters"], fake, 1 << 30, None)
+        assert st == nat.PS_EINVAL
+    finally:
+        lib.free_geometry(h)
+
+
+@pytest.mark.parametrize("bad", [dict(alpha=-1.0), dict(alpha=float("inf")), dict(nonneg=3),
+                                 dict(n_iters=-2)])
+def test_pdhg_arguments_rejected(nat, bad):
+    lib = nat.load()
+    h = C.c_void_p()
+    assert lib.make_geometry(C.byref(_desc(nat)), C.byref(h)) == nat.PS_OK
+    try:
+        assert lib.pdhg_workspace_bytes(h) > 0 and lib.pdhg_workspace_bytes(None) == 0
+        a = dict(alpha=0.1, nonneg=1, n_iters=3)
+        a.update(bad)
+        fake = C.c_void_p(256)
+        st = lib.pdhg_run(h, fake, fake, fake, fake, a["alpha"], a["nonneg"], a["n_iters"], fake,
+                          1 << 30, None)
+        assert st == nat.PS_EINVAL
+        assert b"alpha" in lib.last_error_message() or b"nonneg" in lib.last_error_message() \
+            or b"n_iters" in lib.last_error_message()
+    finally:
+        lib.free_geometry(h)
