@@ -161,6 +161,7 @@ static int norm_blocks(size_t n) {
 struct Layout {
     size_t xs, gs, v, xe, tab, tsum, dx, sino, pws, bws, fws, npart, stats, total;
     size_t pws_bytes, bws_bytes, fws_bytes;
+    bool has_dx;   // the difference buffer dx is kept (keeps_difference)
 };
 
 // The SVRG difference dx = x - xs kept in the workspace for the subset projector, once x and xs
@@ -191,7 +192,8 @@ static Layout layout(const ps_geometry *g, int n_epochs, int estimator) {
         L.tab = take(static_cast<size_t>(d.n_subsets) * n * g->elem);
         L.tsum = take(n * g->elem);
     }
-    if (keeps_difference(g, estimator)) L.dx = take(n * g->elem);
+    L.has_dx = keeps_difference(g, estimator);
+    if (L.has_dx) L.dx = take(n * g->elem);
     L.sino = take(m * g->elem);
     L.pws_bytes = std::max(proj_workspace(g, d.n_angles), proj_workspace(g, max_subset_count(g)));
     L.pws = take(L.pws_bytes);
@@ -438,7 +440,7 @@ static ps_status run_step(const std::vector<ps_solver *> &hs, hipStream_t st,
         up.nsub = static_cast<double>(N);
         up.plain = P.plain_prox_svrg;
         up.coin = s->coin[t];
-        const bool diff = s->L.dx != 0;
+        const bool diff = s->L.has_dx;
         if (diff) {
             up.xs = w + s->L.xs;
             up.dx = w + s->L.dx;
