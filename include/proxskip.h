@@ -95,12 +95,19 @@ PS_API int32_t subset_size(const ps_geometry *geom, int32_t subset);
  *   proj_split_*   workgroups along each ray (projector; partial sums added by a second pass)
  *   bp_groups_*    angle groups of the backprojector (each writes its own partial image)
  *   bp_strip_*     image rows (or columns) per backprojector workgroup: 8, 4, 2 or 1
- *   fgp_iters      inner iterations per 2D FGP launch (temporal blocking): 1..8 (1..4 FP64)
+ *   fgp_iters      inner iterations per 2D FGP launch (temporal blocking): 1..8, capped at
+ *                  (fgp_waves x fgp_rows) / 2 - 2 so that every tile keeps interior rows
  *   bp_method_*    1 = ray-driven scatter into LDS strips + combine pass; 2 = pixel-driven gather
  *                  with the update fused (needs bins at least one pixel apart along every ray's
  *                  stepping axis, e.g. bin_width >= 1; otherwise scatter is used)
  *   bp_gather_rows rows per wave of the gather's tiles (63 columns x 4 waves x rows): 2 or 4
  *   fgp3d_chunk    slices each workgroup of the 3D FGP marches through: 1..256 (default 4)
+ *   fgp_waves, fgp_rows  2D FGP tile: waves per workgroup and image rows per wave, one of
+ *                  (4,4) (4,8) (8,2) (8,4) (8,8) (16,2) (16,4); both 0 = automatic (8,4 FP32;
+ *                  16,2 FP64).  The tile does not change results, not even their rounding.
+ *                  fgp_iters and the tile apply to a prox computed alone: the proxes of several
+ *                  handles advanced together (solver_epochs / solver_steps over several
+ *                  handles) share launches on the automatic tile at its largest depth.
  * "_full" applies to all-angle calls (subset = -1), "_subset" to single subsets. */
 typedef struct {
     int32_t proj_split_full, proj_split_subset;
@@ -110,6 +117,7 @@ typedef struct {
     int32_t bp_method_full, bp_method_subset;
     int32_t bp_gather_rows;
     int32_t fgp3d_chunk;
+    int32_t fgp_waves, fgp_rows;
 } ps_plan;
 
 /* The plan in effect (automatic choices filled in) / replace the overrides.  set: fields out of

@@ -48,7 +48,7 @@ class Plan(C.Structure):
                 ("bp_strip_full", C.c_int32), ("bp_strip_subset", C.c_int32),
                 ("fgp_iters", C.c_int32), ("bp_method_full", C.c_int32),
                 ("bp_method_subset", C.c_int32), ("bp_gather_rows", C.c_int32),
-                ("fgp3d_chunk", C.c_int32)]
+                ("fgp3d_chunk", C.c_int32), ("fgp_waves", C.c_int32), ("fgp_rows", C.c_int32)]
 
 
 class SolverParams(C.Structure):

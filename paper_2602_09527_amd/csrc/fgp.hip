@@ -7,10 +7,10 @@
 // 2D (one slice): temporal blocking in registers.  A workgroup owns a 64-column x EY-row tile
 // (its interior plus a halo of H = T + 1 pixels) and runs T inner iterations on it before writing
 // back; every iteration reaches one pixel further, so the interior is computed exactly as one
-// global iteration at a time would.  Lane = column; each of the 4 waves keeps a contiguous block
-// of RW = EY/4 rows of (v, p, r, z) in registers, takes horizontal neighbours from lane shuffles
-// and exchanges only its first and last rows through LDS.  Between launches the state is
-// (p_k, r_{k+1}), the dual and its extrapolation.
+// global iteration at a time would, whatever the tile shape.  Lane = column; each of the W waves
+// keeps a contiguous block of RW = EY/W rows of (v, p, r, z) in registers, takes horizontal
+// neighbours from lane shuffles and exchanges only its first and last rows through LDS.  Between
+// launches the state is (p_k, r_{k+1}), the dual and its extrapolation.
 // 3D (slices coupled): one launch per half-iteration over global memory (HBM-bound volumes).
 #include <algorithm>
 #include <cmath>
@@ -37,10 +37,19 @@ struct FgpFinal {
     T *dual_out;
 };
 
-template <typename T>
-constexpr int fgp_rw() { return std::is_same<T, double>::value ? 4 : 8; }
-static int fgp_rows(size_t elem) { return kFgpWaves * (elem == sizeof(double) ? 4 : 8); }
-static int fgp_max_iters(size_t elem) { return elem == sizeof(double) ? 4 : kFgpMaxIters; }
+// 2D kernel tile: `waves` waves of `rows` image rows each; the tile is waves x rows high
+// (halos included).  More waves per tile shorten each wave's serial chain and raise occupancy;
+// taller tiles recompute less halo but give fewer workgroups.
+struct FgpTile {
+    int waves, rows;
+};
+constexpr FgpTile kFgpTiles[] = {{4, 4}, {4, 8}, {8, 2}, {8, 4}, {8, 8}, {16, 2}, {16, 4}};
+
+bool fgp_tile_ok(int waves, int rows) {
+    for (const FgpTile &t : kFgpTiles)
+        if (t.waves == waves && t.rows == rows) return true;
+    return false;
+}
 
 // Whole-wave lane shifts through DPP (no LDS traffic): lane i receives lane i - 1 (shr) or
 // lane i + 1 (shl); the lane with no source receives 0.
@@ -73,10 +82,10 @@ struct FgpItem {
     FgpFinal<T> fin;
 };
 
-template <typename T, int RW>
-__global__ __launch_bounds__(kBlock) void k_fgp2d(WorkList<FgpItem<T>> wl) {
-    constexpr int EY = kFgpWaves * RW;
-    __shared__ T xch[2][kFgpWaves][kFgpEX];   // last-row values (down) and first-row values (up)
+template <typename T, int W, int RW>
+__global__ __launch_bounds__(W * kFgpEX) void k_fgp2d(WorkList<FgpItem<T>> wl) {
+    constexpr int EY = W * RW;
+    __shared__ T xch[2][W][kFgpEX];   // last-row values (down) and first-row values (up)
     int local;
     const FgpItem<T> &it = wl.item[work_item(wl, local)];
     const int nx = it.nx, ny = it.ny, halo = it.halo, iters = it.iters, nonneg = it.nonneg;
@@ -134,7 +143,7 @@ __global__ __launch_bounds__(kBlock) void k_fgp2d(WorkList<FgpItem<T>> wl) {
         // p+ = P_P(r + step D z); r+ = p+ + c (p+ - p): needs z of the right neighbour and below
         xch[1][wave][lane] = zz[0];
         __syncthreads();
-        const T z_below = wave < kFgpWaves - 1 ? xch[1][wave + 1][lane] : T(0);
+        const T z_below = wave < W - 1 ? xch[1][wave + 1][lane] : T(0);
         const T c = it.cf.c[t];
 #pragma unroll
         for (int r = 0; r < RW; ++r) {
@@ -493,13 +502,30 @@ size_t fgp_workspace(const ps_geometry *g) {
 
 // Inner iterations per 2D launch.  A launch recomputes a halo of T + 1 pixels around every tile,
 // so fewer iterations per launch waste less arithmetic but pay the per-launch cost (loading and
-// storing the tile state, about 4 us) more often; on this chip 8 per launch is faster at every
-// size measured (512^2: 7 launches of 15.5 us against 13 of 9.9 us at 4 per launch).  The choice
-// does not change results.
-int fgp_max_iters_of(const ps_geometry *g) { return fgp_max_iters(g->elem); }
+// storing the tile state) more often; the largest T the tile allows was the fastest at every size
+// measured with the automatic tiles.  Neither choice changes results.
+// A tile of height EY leaves EY - 2 (T + 1) interior rows, so T is capped at EY / 2 - 2.
+int fgp_max_iters_of(const ps_geometry *) { return kFgpMaxIters; }
+static void fgp_auto_tile(const ps_geometry *g, int *waves, int *rows) {
+    // 8 x 4 (FP32), 16 x 2 (FP64): at or near the fastest from 256^2 to 512^2 alone, and the
+    // best throughput measured for batches (64 x 128^2)
+    *waves = g->elem == sizeof(double) ? 16 : 8;
+    *rows = g->elem == sizeof(double) ? 2 : 4;
+}
+void fgp_tile_of(const ps_geometry *g, int *waves, int *rows) {
+    if (g->plan.fgp_waves > 0) {
+        *waves = g->plan.fgp_waves;
+        *rows = g->plan.fgp_rows;
+    } else {
+        fgp_auto_tile(g, waves, rows);
+    }
+}
+static int fgp_cap(int waves, int rows) { return std::min(kFgpMaxIters, waves * rows / 2 - 2); }
 int fgp_iters_per_launch(const ps_geometry *g) {
+    int waves, rows;
+    fgp_tile_of(g, &waves, &rows);
     const int f = g->plan.fgp_iters;
-    return f > 0 ? std::min(f, fgp_max_iters(g->elem)) : fgp_max_iters(g->elem);
+    return f > 0 ? std::min(f, fgp_cap(waves, rows)) : fgp_cap(waves, rows);
 }
 
 // A 2D FGP solve as its sequence of launches, plus the copies around them.
@@ -512,10 +538,15 @@ struct FgpProgram {
     size_t n = 0, dn = 0;
     T *post_copy_dst = nullptr;       // final dual written to a work buffer, copied back
     const T *post_copy_src = nullptr;
+    FgpTile tile{};
 };
 
+// `shared`: the solve shares its launches with other 2D solves.  The plan's tile and depth are
+// tuned on one solve alone; with many workgroups in flight the automatic tile at its full depth
+// has the better throughput (64 x 128^2: 19.8k slice-epochs/s against 16.3k with the tile tuned
+// alone), so shared solves use it.  The tile never changes the bits.
 template <typename T>
-static ps_status fgp2d_program(const FgpCall &c, FgpProgram<T> &prog) {
+static ps_status fgp2d_program(const FgpCall &c, bool shared, FgpProgram<T> &prog) {
     const ps_geometry *g = c.g;
     const auto &d = g->desc;
     const size_t n = static_cast<size_t>(d.nx) * d.ny * d.nz;
@@ -552,7 +583,15 @@ static ps_status fgp2d_program(const FgpCall &c, FgpProgram<T> &prog) {
     }
     const T tauT = static_cast<T>(c.tau);
     const T stepT = static_cast<T>(1.0 / (8.0 * c.tau));
-    const int tmax = fgp_iters_per_launch(g), EY = fgp_rows(g->elem);
+    int tmax;
+    if (shared) {
+        fgp_auto_tile(g, &prog.tile.waves, &prog.tile.rows);
+        tmax = fgp_cap(prog.tile.waves, prog.tile.rows);
+    } else {
+        fgp_tile_of(g, &prog.tile.waves, &prog.tile.rows);
+        tmax = fgp_iters_per_launch(g);
+    }
+    const int EY = prog.tile.waves * prog.tile.rows;
     const int launches = std::max(1, (K + tmax - 1) / tmax);
     const std::vector<double> cn = momentum(K + 1);
     int done = 0;
@@ -603,9 +642,23 @@ static ps_status fgp2d_program(const FgpCall &c, FgpProgram<T> &prog) {
     return PS_OK;
 }
 
+template <typename T, int W, int RW>
+static void launch_fgp2d_tile(const WorkList<FgpItem<T>> &wl, int blocks, hipStream_t st) {
+    hipLaunchKernelGGL((k_fgp2d<T, W, RW>), dim3(blocks), dim3(W * kFgpEX), 0, st, wl);
+}
+
 template <typename T>
-static ps_status launch_fgp2d_list(const WorkList<FgpItem<T>> &wl, int blocks, hipStream_t st) {
-    hipLaunchKernelGGL((k_fgp2d<T, fgp_rw<T>()>), dim3(blocks), dim3(kBlock), 0, st, wl);
+static ps_status launch_fgp2d_list(const WorkList<FgpItem<T>> &wl, int blocks, FgpTile tile, hipStream_t st) {
+    switch (tile.waves * 100 + tile.rows) {
+    case 404: launch_fgp2d_tile<T, 4, 4>(wl, blocks, st); break;
+    case 408: launch_fgp2d_tile<T, 4, 8>(wl, blocks, st); break;
+    case 802: launch_fgp2d_tile<T, 8, 2>(wl, blocks, st); break;
+    case 804: launch_fgp2d_tile<T, 8, 4>(wl, blocks, st); break;
+    case 808: launch_fgp2d_tile<T, 8, 8>(wl, blocks, st); break;
+    case 1602: launch_fgp2d_tile<T, 16, 2>(wl, blocks, st); break;
+    case 1604: launch_fgp2d_tile<T, 16, 4>(wl, blocks, st); break;
+    default: return fail(PS_EINVAL, "FGP tile %d x %d not built", tile.waves, tile.rows);
+    }
     PS_LAUNCHED("k_fgp2d");
     return PS_OK;
 }
@@ -707,6 +760,8 @@ static ps_status fgp_single_t(const FgpCall &c, hipStream_t st) {
 template <typename T>
 static ps_status fgp_many_t(const FgpCall *calls, int n, hipStream_t st) {
     std::vector<FgpProgram<T>> progs;
+    int n2d = 0;
+    for (int i = 0; i < n; ++i) n2d += calls[i].g->tv_dims == 2 && calls[i].tau != 0.0;
     for (int i = 0; i < n; ++i) {
         const FgpCall &c = calls[i];
         const size_t need = fgp_workspace(c.g);
@@ -717,7 +772,7 @@ static ps_status fgp_many_t(const FgpCall *calls, int n, hipStream_t st) {
             continue;
         }
         progs.emplace_back();
-        PS_TRY(fgp2d_program<T>(c, progs.back()));
+        PS_TRY(fgp2d_program<T>(c, n2d > 1, progs.back()));
     }
     size_t rounds = 0;
     for (const auto &p : progs) {
@@ -731,19 +786,28 @@ static ps_status fgp_many_t(const FgpCall *calls, int n, hipStream_t st) {
             PS_LAUNCHED("k_fill");
         }
     }
+    // solves of one tile shape share launches
+    std::vector<FgpTile> tiles;
+    for (const auto &p : progs) {
+        bool seen = false;
+        for (const FgpTile &t : tiles) seen = seen || (t.waves == p.tile.waves && t.rows == p.tile.rows);
+        if (!seen) tiles.push_back(p.tile);
+    }
     for (size_t r = 0; r < rounds; ++r) {
-        ListBuilder<FgpItem<T>> lb;
-        for (const auto &p : progs) {
-            if (r >= p.launches.size()) continue;
-            const FgpItem<T> &it = p.launches[r];
-            const long blocks = static_cast<long>(it.tiles_x) * it.tiles_y * (it.ncomp / (static_cast<size_t>(it.nx) * it.ny));
-            lb.add(it, static_cast<int>(blocks));
-            if (lb.full()) {
-                PS_TRY(launch_fgp2d_list<T>(lb.wl, lb.blocks, st));
-                lb.clear();
+        for (const FgpTile &tile : tiles) {
+            ListBuilder<FgpItem<T>> lb;
+            for (const auto &p : progs) {
+                if (r >= p.launches.size() || p.tile.waves != tile.waves || p.tile.rows != tile.rows) continue;
+                const FgpItem<T> &it = p.launches[r];
+                const long blocks = static_cast<long>(it.tiles_x) * it.tiles_y * (it.ncomp / (static_cast<size_t>(it.nx) * it.ny));
+                lb.add(it, static_cast<int>(blocks));
+                if (lb.full()) {
+                    PS_TRY(launch_fgp2d_list<T>(lb.wl, lb.blocks, tile, st));
+                    lb.clear();
+                }
             }
+            if (!lb.empty()) PS_TRY(launch_fgp2d_list<T>(lb.wl, lb.blocks, tile, st));
         }
-        if (!lb.empty()) PS_TRY(launch_fgp2d_list<T>(lb.wl, lb.blocks, st));
     }
     for (const auto &p : progs) {
         if (p.post_copy_dst) {

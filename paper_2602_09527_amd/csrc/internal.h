@@ -251,6 +251,8 @@ ps_status launch_backproject(const ps_geometry *g, int subset, const void *y, vo
 size_t fgp_workspace(const ps_geometry *g);
 int fgp_iters_per_launch(const ps_geometry *g);
 int fgp_max_iters_of(const ps_geometry *g);
+bool fgp_tile_ok(int waves, int rows);                 // a built 2D FGP tile shape
+void fgp_tile_of(const ps_geometry *g, int *waves, int *rows);   // the shape in effect
 // Finalise modes: write z (FGP_Z) or the ProxSkip update x = z, h = hscale (z - v) (FGP_PROXSKIP).
 struct FgpOut {
     void *z;        // FGP_Z: output image (may alias v)

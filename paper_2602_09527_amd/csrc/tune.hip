@@ -7,6 +7,7 @@
 // computed; split and grouping change the order of floating-point sums.
 #include <algorithm>
 #include <array>
+#include <utility>
 #include <vector>
 
 #include "internal.h"
@@ -136,6 +137,7 @@ extern "C" ps_status geometry_get_plan(const ps_geometry *g, ps_plan *out) {
     out->bp_method_subset = back_method(g, 0);
     out->bp_gather_rows = gather_rows(g, 0);
     out->fgp3d_chunk = g->plan.fgp3d_chunk > 0 ? g->plan.fgp3d_chunk : 4;
+    fgp_tile_of(g, &out->fgp_waves, &out->fgp_rows);
     return PS_OK;
 }
 
@@ -158,6 +160,9 @@ extern "C" ps_status geometry_set_plan(ps_geometry *g, const ps_plan *p) {
     if (p->bp_gather_rows != 0 && p->bp_gather_rows != 2 && p->bp_gather_rows != 4)
         return fail(PS_EINVAL, "bp_gather_rows must be 0, 2 or 4");
     if (p->fgp3d_chunk < 0 || p->fgp3d_chunk > 256) return fail(PS_EINVAL, "fgp3d_chunk must be in [0, 256]");
+    if (!(p->fgp_waves == 0 && p->fgp_rows == 0) && !fgp_tile_ok(p->fgp_waves, p->fgp_rows))
+        return fail(PS_EINVAL, "FGP tile %d x %d: waves x rows must be 4x4, 4x8, 8x2, 8x4, 8x8, 16x2, 16x4 or 0x0",
+                    p->fgp_waves, p->fgp_rows);
     g->plan = *p;
     return PS_OK;
 }
@@ -295,28 +300,48 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
         }
     }
 
-    // FGP inner iterations per launch (2D TV only): one 50-iteration prox per timed call
+    // 2D FGP tile shape and inner iterations per launch: one 50-iteration prox per timed call;
+    // the automatic tile at its largest iteration count is timed first and is the one to beat
     if (g->tv_dims == 2) {
         PS_TRY(fill(g, w + L.dual, 2 * n, st));
+        g->plan = best;
+        g->plan.fgp_waves = g->plan.fgp_rows = 0;
+        int auto_w, auto_r;
+        fgp_tile_of(g, &auto_w, &auto_r);
+        std::vector<std::pair<int, int>> tiles{{auto_w, auto_r}};
+        for (int w8 : {4, 8, 16})
+            for (int r8 : {2, 4, 8})
+                if (fgp_tile_ok(w8, r8) && !(w8 == auto_w && r8 == auto_r)) tiles.emplace_back(w8, r8);
         float best_ms = 0.f;
-        int pick = 0;
-        const int tmax = fgp_max_iters_of(g);
-        for (int T = tmax; T >= 2; --T) {
-            ps_plan trial = best;
-            trial.fgp_iters = T;
-            g->plan = trial;
-            FgpOut o{};
-            o.z = w + L.img;
-            float ms = 0.f;
-            PS_TRY(restore_on_error(time_calls([&] {
-                return launch_fgp(g, w + L.x, w + L.dual, 1e-3, 50, 1, o, w + L.fws, L.fws_bytes, st);
-            }, reps, st, tm, &ms)));
-            if (pick == 0 || ms < best_ms * (pick == tmax ? kMinGain : 1.0f)) {
-                best_ms = ms;
-                pick = T;
+        int pick_t = 0, pick_w = 0, pick_r = 0;
+        bool first = true, auto_best = true;
+        for (const auto &tile : tiles) {
+            const int cap = std::min(fgp_max_iters_of(g), tile.first * tile.second / 2 - 2);
+            for (int T = cap; T >= 2; --T) {
+                ps_plan trial = best;
+                trial.fgp_waves = tile.first;
+                trial.fgp_rows = tile.second;
+                trial.fgp_iters = T;
+                g->plan = trial;
+                FgpOut o{};
+                o.z = w + L.img;
+                float ms = 0.f;
+                PS_TRY(restore_on_error(time_calls([&] {
+                    return launch_fgp(g, w + L.x, w + L.dual, 1e-3, 50, 1, o, w + L.fws, L.fws_bytes, st);
+                }, reps, st, tm, &ms)));
+                if (first || ms < best_ms * (auto_best ? kMinGain : 1.0f)) {
+                    best_ms = ms;
+                    pick_t = T;
+                    pick_w = tile.first;
+                    pick_r = tile.second;
+                    auto_best = first;
+                }
+                first = false;
             }
         }
-        best.fgp_iters = pick;
+        best.fgp_iters = pick_t;
+        best.fgp_waves = pick_w;
+        best.fgp_rows = pick_r;
     }
     // 3D FGP: slices per workgroup (10 inner iterations per timed call)
     if (g->tv_dims == 3) {

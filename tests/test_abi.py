@@ -142,7 +142,7 @@ def test_plan_get_set_and_validation(nat):
         assert lib.geometry_get_plan(h, C.byref(auto)) == nat.PS_OK
         assert auto.proj_split_full >= 1 and auto.proj_split_subset >= 1
         assert 1 <= auto.bp_groups_full <= 16 and auto.bp_strip_full in (1, 2, 4, 8)
-        assert auto.fgp_iters == 8
+        assert auto.fgp_iters == 8 and (auto.fgp_waves, auto.fgp_rows) == (8, 4)
         # the scatter backprojector unless a plan asks for the gather
         assert (auto.bp_method_full, auto.bp_method_subset) == (1, 1)
         forced = nat.Plan(proj_split_full=2, proj_split_subset=1, bp_groups_full=4,
@@ -154,10 +154,16 @@ def test_plan_get_set_and_validation(nat):
                 got.bp_groups_subset, got.bp_strip_full, got.bp_strip_subset, got.fgp_iters) == \
             (2, 1, 4, 2, 4, 2, 5)
         for bad in (dict(proj_split_full=-1), dict(bp_groups_subset=17), dict(bp_strip_full=3),
-                    dict(fgp_iters=9), dict(bp_method_subset=3)):
+                    dict(fgp_iters=9), dict(bp_method_subset=3), dict(fgp_waves=4, fgp_rows=2),
+                    dict(fgp_waves=8), dict(fgp_rows=4), dict(fgp_waves=32, fgp_rows=2)):
             assert lib.geometry_set_plan(h, C.byref(nat.Plan(**bad))) == nat.PS_EINVAL
         # a rejected plan leaves the previous one in place
         assert lib.geometry_get_plan(h, C.byref(got)) == nat.PS_OK and got.fgp_iters == 5
+        # a 2D FGP tile caps the inner iterations per launch at its height / 2 - 2
+        for w, r, t, want in ((4, 4, 8, 6), (8, 2, 3, 3), (16, 4, 0, 8), (4, 8, 7, 7)):
+            assert lib.geometry_set_plan(h, C.byref(nat.Plan(fgp_waves=w, fgp_rows=r, fgp_iters=t))) == nat.PS_OK
+            assert lib.geometry_get_plan(h, C.byref(got)) == nat.PS_OK
+            assert (got.fgp_waves, got.fgp_rows, got.fgp_iters) == (w, r, want)
         # workspace sizes follow the plan
         zero = nat.Plan()
         assert lib.geometry_set_plan(h, C.byref(zero)) == nat.PS_OK
@@ -209,3 +215,16 @@ def test_pdhg_arguments_rejected(nat, bad):
             or b"n_iters" in lib.last_error_message()
     finally:
         lib.free_geometry(h)
+
+
+def test_plan_fgp_tile_defaults_per_dtype(nat):
+    lib = nat.load()
+    for dt, tile in ((nat.PS_F32, (8, 4)), (nat.PS_F64, (16, 2))):
+        h = C.c_void_p()
+        assert lib.make_geometry(C.byref(_desc(nat, dtype=dt)), C.byref(h)) == nat.PS_OK
+        try:
+            got = nat.Plan()
+            assert lib.geometry_get_plan(h, C.byref(got)) == nat.PS_OK
+            assert (got.fgp_waves, got.fgp_rows, got.fgp_iters) == (*tile, 8)
+        finally:
+            lib.free_geometry(h)

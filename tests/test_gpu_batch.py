@@ -94,3 +94,31 @@ def test_batch_member_matches_oracle(orc):
     assert st["prox_calls"] == so["prox_calls"]
     x = s.x.cpu().numpy().astype(np.float64)
     assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 1e-4
+
+
+def test_batch_with_different_fgp_tiles_bitwise_equals_alone():
+    # solves whose 2D TV prox runs on different tile shapes share rounds but not launches
+    from paper_2602_09527_amd import api
+    tiles = [(4, 8, 8), (16, 2, 5), (8, 8, 0), (16, 4, 3)]
+    mix = [(128, 128, 180, 128, 10, 21, torch.float32, {}),
+           (96, 80, 90, 144, 5, 22, torch.float32, dict(fgp_inner=13)),
+           (150, 97, 72, 160, 8, 23, torch.float32, dict(p=0.5)),
+           (64, 64, 60, 96, 6, 24, torch.float64, dict(fgp_inner=7))]
+    probs = []
+    for m, (w, r, t) in zip(mix, tiles):
+        g, b, prm = _problem(*m[:7], **m[7])
+        g.set_plan(dict(g.get_plan(), fgp_waves=w, fgp_rows=r, fgp_iters=t))
+        assert (g.get_plan()["fgp_waves"], g.get_plan()["fgp_rows"]) == (w, r)
+        probs.append((g, b, prm))
+    alone = []
+    for g, b, prm in probs:
+        s = api.Solver(g, b, prm)
+        s.epochs(prm.n_epochs)
+        alone.append(_state(s))
+    solvers = [api.Solver(g, b, prm) for g, b, prm in probs]
+    api.run_epochs(solvers, max(p.n_epochs for _, _, p in probs))
+    for k, s in enumerate(solvers):
+        x, h, d, st = _state(s)
+        xa, ha, da, sa = alone[k]
+        assert st == sa, (k, st, sa)
+        assert torch.equal(x, xa) and torch.equal(h, ha) and torch.equal(d, da), k

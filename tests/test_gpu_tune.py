@@ -91,3 +91,33 @@ def test_tuned_solve_matches_oracle(orc):
     x, _, _, st = api.solve(g, torch.from_numpy(prob.b).float().cuda(), api.SolverParams(**kw))
     assert st["prox_calls"] == so["prox_calls"]
     assert _rel(x.cpu().numpy(), xo) <= 1e-4
+
+
+TILES = [(4, 4), (4, 8), (8, 2), (8, 4), (8, 8), (16, 2), (16, 4)]
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_fgp_tiles_bitwise_equal(orc, dtype):
+    # the tile shape and iterations per launch decide only which workgroup computes a pixel:
+    # every (tile, T) gives the same bits, and those match the FP64 oracle
+    from paper_2602_09527_amd import api
+    nx, ny = 150, 97   # several tiles of every shape, ragged in both directions
+    g = api.Geometry(nx, ny, 30, 40, n_subsets=2, dtype=dtype)
+    rng = np.random.default_rng(5)
+    v = rng.random((1, ny, nx))
+    d0 = 0.3 * rng.standard_normal((2, 1, ny, nx))
+    vt = torch.from_numpy(v).to("cuda", dtype)
+    ref = None
+    for w, r in TILES:
+        for T in (1, 3, 8):
+            g.set_plan(dict(fgp_waves=w, fgp_rows=r, fgp_iters=T))
+            assert g.get_plan()["fgp_iters"] == min(T, w * r // 2 - 2)
+            dual = torch.from_numpy(d0).to("cuda", dtype)
+            z = api.tv_prox(g, vt, 0.05, 29, dual=dual)
+            torch.cuda.synchronize()
+            if ref is None:
+                ref = (z.clone(), dual.clone())
+                z_ref = orc.tv_prox_fgp(v, 0.05, 29, nonneg=True, dual=d0.copy())
+                assert _rel(z.cpu().numpy(), z_ref) <= (1e-5 if dtype == torch.float32 else 1e-12)
+            else:
+                assert torch.equal(z, ref[0]) and torch.equal(dual, ref[1]), (w, r, T)
