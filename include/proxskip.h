@@ -95,8 +95,9 @@ PS_API int32_t subset_size(const ps_geometry *geom, int32_t subset);
  *   proj_split_*   workgroups along each ray (projector; partial sums added by a second pass)
  *   bp_groups_*    angle groups of the backprojector (each writes its own partial image)
  *   bp_strip_*     image rows (or columns) per backprojector workgroup: 8, 4, 2 or 1
- *   fgp_iters      inner iterations per 2D FGP launch (temporal blocking): 1..8, capped at
- *                  (fgp_waves x fgp_rows) / 2 - 2 so that every tile keeps interior rows
+ *   fgp_iters      inner iterations per 2D FGP launch (temporal blocking): 1..16 (FP32) or
+ *                  1..8 (FP64), 0 = 8; capped at (fgp_waves x fgp_rows) / 2 - 2 so that every
+ *                  tile keeps interior rows
  *   bp_method_*    1 = ray-driven scatter into LDS strips + combine pass; 2 = pixel-driven gather
  *                  with the update fused (needs bins at least one pixel apart along every ray's
  *                  stepping axis, e.g. bin_width >= 1; otherwise scatter is used)
@@ -107,7 +108,7 @@ PS_API int32_t subset_size(const ps_geometry *geom, int32_t subset);
  *                  16,2 FP64).  The tile does not change results, not even their rounding.
  *                  fgp_iters and the tile apply to a prox computed alone: the proxes of several
  *                  handles advanced together (solver_epochs / solver_steps over several
- *                  handles) share launches on the automatic tile at its largest depth.
+ *                  handles) share launches on the automatic tile and depth.
  * "_full" applies to all-angle calls (subset = -1), "_subset" to single subsets. */
 typedef struct {
     int32_t proj_split_full, proj_split_subset;

@@ -494,6 +494,7 @@ struct GatherAngle {
     int row;
     int cs, co;       // candidate rule: uf = cs * floor(cr * u* + 1/64) + co (see cell_ray)
     T a0, a1, a2, ia1, cr, inv;
+    T csf, cof;       // cs and co as floating point
     int64_t q0, q1, q2;
 };
 
@@ -504,6 +505,8 @@ __device__ inline GatherAngle<T> uni(const GatherAngle<T> &g) {
     r.cs = uni(g.cs);
     r.co = uni(g.co);
     r.cr = uni(g.cr);
+    r.csf = uni(g.csf);
+    r.cof = uni(g.cof);
     r.inv = uni(g.inv);
     r.a0 = uni(g.a0);
     r.a1 = uni(g.a1);
@@ -531,6 +534,8 @@ __device__ inline GatherAngle<T> gather_angle(const AngleTab<T> &tab, int k) {
     g.cr = up ? T(-1) : T(1);
     g.cs = up ? -1 : 1;
     g.co = up ? 0 : -1;
+    g.csf = static_cast<T>(g.cs);
+    g.cof = static_cast<T>(g.co);
     return g;
 }
 
@@ -548,7 +553,7 @@ __device__ inline double lane_from_left(double v) {
 // the first bin of the staged window yw.
 template <typename T>
 __device__ inline void cell_ray(const GatherAngle<T> &ga, int p, T c, int64_t base, const T *yw, int ub,
-                                T &own, T &next) {
+                                int nb, T &own, T &next) {
     constexpr bool kFixed = std::is_same<T, float>::value;
     // q(u) = c + u a1 is in [p, p + 1) for the bins in [u*, u* + 1/a1) (a1 > 0) or
     // (u* + 1/a1, u*] (a1 < 0), u* = (p - c) / a1: an interval of length <= 1 holding at most the
@@ -556,18 +561,27 @@ __device__ inline void cell_ray(const GatherAngle<T> &ga, int p, T c, int64_t ba
     // (resp. floor(u* + 1/64) - 1) contain it whatever the rounding of u* (|error| < 1e-3).
     // branch-free: ceil(u* - 1/64) = -floor(1/64 - u*)
     const T us = (static_cast<T>(p) - c) * ga.ia1;
-    const int uf = ga.cs * static_cast<int>(floor(fma(us, ga.cr, T(0.015625)))) + ga.co;
     int u;
     T w;
     bool hit;
     if constexpr (kFixed) {
-        const int64_t Q0 = base + static_cast<int64_t>(uf) * ga.q1;
+        // the candidate in floating point (an exact small integer), clamped into [0, nb]: a ray
+        // outside the detector deposits nothing, so the clamp loses no contribution.  Then
+        // uf * q1 needs one 32 x 32 -> 64-bit multiply-add (uf >= 0) and a 24-bit product for
+        // the small high word of q1, not a full 64-bit multiply.
+        const int uf = min(max(static_cast<int>(fma(ga.csf, floor(fma(us, ga.cr, T(0.015625))), ga.cof)), 0), nb);
+        const uint32_t q1lo = static_cast<uint32_t>(static_cast<uint64_t>(ga.q1));
+        const int q1hi = static_cast<int>(ga.q1 >> 32);
+        const uint64_t prod = static_cast<uint64_t>(static_cast<uint32_t>(uf)) * q1lo +
+                              (static_cast<uint64_t>(static_cast<uint32_t>(__mul24(uf, q1hi))) << 32);
+        const int64_t Q0 = static_cast<int64_t>(static_cast<uint64_t>(base) + prod);
         const int64_t Q1 = Q0 + ga.q1;
         const bool h0 = static_cast<int>(Q0 >> 32) == p;
         hit = h0 || static_cast<int>(Q1 >> 32) == p;
         u = h0 ? uf : uf + 1;
         w = static_cast<T>(static_cast<uint32_t>(h0 ? Q0 : Q1));
     } else {
+        const int uf = ga.cs * static_cast<int>(floor(fma(us, ga.cr, T(0.015625)))) + ga.co;
         // FP64 positions are rounded: with |a1| = 1 two adjacent rays can land in one cell (for
         // instance q = -1 - 6e-17 rounds to -1 while the next ray has q = -6e-17), so every
         // candidate in the cell contributes, as in the scatter
@@ -680,7 +694,7 @@ __global__ __launch_bounds__(kBlock) void k_backproject_gather(WorkList<GatherIt
                     const T c = fma(static_cast<T>(i), ga.a2, ga.a0);
                     const int64_t base = ga.q0 + static_cast<int64_t>(i) * ga.q2;
                     T own, next;
-                    cell_ray(ga, j, c, base, yw, ub, own, next);
+                    cell_ray(ga, j, c, base, yw, ub, B, own, next);
                     acc[r] += own + lane_from_left(next);
                 }
             } else {
@@ -689,11 +703,11 @@ __global__ __launch_bounds__(kBlock) void k_backproject_gather(WorkList<GatherIt
                 const T c = fma(static_cast<T>(j), ga.a2, ga.a0);
                 const int64_t base = ga.q0 + static_cast<int64_t>(j) * ga.q2;
                 T own, prev;
-                cell_ray(ga, i0 - 1, c, base, yw, ub, own, prev);
+                cell_ray(ga, i0 - 1, c, base, yw, ub, B, own, prev);
 #pragma unroll
                 for (int r = 0; r < kGatherRows; ++r) {
                     T next;
-                    cell_ray(ga, i0 + r, c, base, yw, ub, own, next);
+                    cell_ray(ga, i0 + r, c, base, yw, ub, B, own, next);
                     acc[r] += own + prev;
                     prev = next;
                 }

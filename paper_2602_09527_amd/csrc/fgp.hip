@@ -22,11 +22,15 @@ namespace ps {
 
 constexpr int kFgpEX = 64;          // tile width including halos (= one wave)
 constexpr int kFgpWaves = 4;
-constexpr int kFgpMaxIters = 8;
+// Inner iterations per 2D launch: at most 16 (FP32) or 8 (FP64), so that a work list of 16 items
+// with their momentum coefficients stays within 4 KB of kernel arguments; 8 unless a plan asks.
+template <typename T>
+constexpr int fgp_max_iters() { return std::is_same<T, double>::value ? 8 : 16; }
+constexpr int kFgpAutoIters = 8;
 
 template <typename T>
 struct FgpCoef {
-    T c[kFgpMaxIters];              // c_{k+1} for the T iterations of this launch
+    T c[fgp_max_iters<T>()];        // c_{k+1} for the T iterations of this launch
 };
 
 template <typename T>
@@ -502,10 +506,13 @@ size_t fgp_workspace(const ps_geometry *g) {
 
 // Inner iterations per 2D launch.  A launch recomputes a halo of T + 1 pixels around every tile,
 // so fewer iterations per launch waste less arithmetic but pay the per-launch cost (loading and
-// storing the tile state) more often; the largest T the tile allows was the fastest at every size
-// measured with the automatic tiles.  Neither choice changes results.
+// storing the tile state) more often.  8 per launch is the best depth for the automatic tiles;
+// taller tiles go deeper (at 512^2 a 16 x 4 tile at 10 or 12 per launch beats every tile at 8 by
+// 14%), which tuned plans choose.  Neither choice changes results.
 // A tile of height EY leaves EY - 2 (T + 1) interior rows, so T is capped at EY / 2 - 2.
-int fgp_max_iters_of(const ps_geometry *) { return kFgpMaxIters; }
+int fgp_max_iters_of(const ps_geometry *g) {
+    return g->elem == sizeof(double) ? fgp_max_iters<double>() : fgp_max_iters<float>();
+}
 static void fgp_auto_tile(const ps_geometry *g, int *waves, int *rows) {
     // 8 x 4 (FP32), 16 x 2 (FP64): at or near the fastest from 256^2 to 512^2 alone, and the
     // best throughput measured for batches (64 x 128^2)
@@ -520,12 +527,12 @@ void fgp_tile_of(const ps_geometry *g, int *waves, int *rows) {
         fgp_auto_tile(g, waves, rows);
     }
 }
-static int fgp_cap(int waves, int rows) { return std::min(kFgpMaxIters, waves * rows / 2 - 2); }
+static int fgp_cap(int waves, int rows) { return waves * rows / 2 - 2; }
 int fgp_iters_per_launch(const ps_geometry *g) {
     int waves, rows;
     fgp_tile_of(g, &waves, &rows);
     const int f = g->plan.fgp_iters;
-    return f > 0 ? std::min(f, fgp_cap(waves, rows)) : fgp_cap(waves, rows);
+    return std::min(f > 0 ? std::min(f, fgp_max_iters_of(g)) : kFgpAutoIters, fgp_cap(waves, rows));
 }
 
 // A 2D FGP solve as its sequence of launches, plus the copies around them.
@@ -542,7 +549,7 @@ struct FgpProgram {
 };
 
 // `shared`: the solve shares its launches with other 2D solves.  The plan's tile and depth are
-// tuned on one solve alone; with many workgroups in flight the automatic tile at its full depth
+// tuned on one solve alone; with many workgroups in flight the automatic tile and depth
 // has the better throughput (64 x 128^2: 19.8k slice-epochs/s against 16.3k with the tile tuned
 // alone), so shared solves use it.  The tile never changes the bits.
 template <typename T>
@@ -586,7 +593,7 @@ static ps_status fgp2d_program(const FgpCall &c, bool shared, FgpProgram<T> &pro
     int tmax;
     if (shared) {
         fgp_auto_tile(g, &prog.tile.waves, &prog.tile.rows);
-        tmax = fgp_cap(prog.tile.waves, prog.tile.rows);
+        tmax = std::min(kFgpAutoIters, fgp_cap(prog.tile.waves, prog.tile.rows));
     } else {
         fgp_tile_of(g, &prog.tile.waves, &prog.tile.rows);
         tmax = fgp_iters_per_launch(g);
@@ -646,6 +653,9 @@ template <typename T, int W, int RW>
 static void launch_fgp2d_tile(const WorkList<FgpItem<T>> &wl, int blocks, hipStream_t st) {
     hipLaunchKernelGGL((k_fgp2d<T, W, RW>), dim3(blocks), dim3(W * kFgpEX), 0, st, wl);
 }
+
+static_assert(sizeof(WorkList<FgpItem<float>>) <= 4096 && sizeof(WorkList<FgpItem<double>>) <= 4096,
+              "2D FGP work lists must fit in 4 KB of kernel arguments");
 
 template <typename T>
 static ps_status launch_fgp2d_list(const WorkList<FgpItem<T>> &wl, int blocks, FgpTile tile, hipStream_t st) {

@@ -301,42 +301,43 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
     }
 
     // 2D FGP tile shape and inner iterations per launch: one 50-iteration prox per timed call;
-    // the automatic tile at its largest iteration count is timed first and is the one to beat
+    // the automatic plan (tile and depth) is timed first and is the one to beat
     if (g->tv_dims == 2) {
         PS_TRY(fill(g, w + L.dual, 2 * n, st));
         g->plan = best;
-        g->plan.fgp_waves = g->plan.fgp_rows = 0;
+        g->plan.fgp_waves = g->plan.fgp_rows = g->plan.fgp_iters = 0;
         int auto_w, auto_r;
         fgp_tile_of(g, &auto_w, &auto_r);
-        std::vector<std::pair<int, int>> tiles{{auto_w, auto_r}};
+        const int auto_t = fgp_iters_per_launch(g);
+        std::vector<std::array<int, 3>> cands{{auto_w, auto_r, auto_t}};
         for (int w8 : {4, 8, 16})
-            for (int r8 : {2, 4, 8})
-                if (fgp_tile_ok(w8, r8) && !(w8 == auto_w && r8 == auto_r)) tiles.emplace_back(w8, r8);
+            for (int r8 : {2, 4, 8}) {
+                if (!fgp_tile_ok(w8, r8)) continue;
+                const int cap = std::min(fgp_max_iters_of(g), w8 * r8 / 2 - 2);
+                for (int T = cap; T >= 2; --T)
+                    if (!(w8 == auto_w && r8 == auto_r && T == auto_t)) cands.push_back({w8, r8, T});
+            }
         float best_ms = 0.f;
         int pick_t = 0, pick_w = 0, pick_r = 0;
-        bool first = true, auto_best = true;
-        for (const auto &tile : tiles) {
-            const int cap = std::min(fgp_max_iters_of(g), tile.first * tile.second / 2 - 2);
-            for (int T = cap; T >= 2; --T) {
-                ps_plan trial = best;
-                trial.fgp_waves = tile.first;
-                trial.fgp_rows = tile.second;
-                trial.fgp_iters = T;
-                g->plan = trial;
-                FgpOut o{};
-                o.z = w + L.img;
-                float ms = 0.f;
-                PS_TRY(restore_on_error(time_calls([&] {
-                    return launch_fgp(g, w + L.x, w + L.dual, 1e-3, 50, 1, o, w + L.fws, L.fws_bytes, st);
-                }, reps, st, tm, &ms)));
-                if (first || ms < best_ms * (auto_best ? kMinGain : 1.0f)) {
-                    best_ms = ms;
-                    pick_t = T;
-                    pick_w = tile.first;
-                    pick_r = tile.second;
-                    auto_best = first;
-                }
-                first = false;
+        bool auto_best = true;
+        for (size_t ci = 0; ci < cands.size(); ++ci) {
+            ps_plan trial = best;
+            trial.fgp_waves = cands[ci][0];
+            trial.fgp_rows = cands[ci][1];
+            trial.fgp_iters = cands[ci][2];
+            g->plan = trial;
+            FgpOut o{};
+            o.z = w + L.img;
+            float ms = 0.f;
+            PS_TRY(restore_on_error(time_calls([&] {
+                return launch_fgp(g, w + L.x, w + L.dual, 1e-3, 50, 1, o, w + L.fws, L.fws_bytes, st);
+            }, reps, st, tm, &ms)));
+            if (ci == 0 || ms < best_ms * (auto_best ? kMinGain : 1.0f)) {
+                best_ms = ms;
+                pick_w = cands[ci][0];
+                pick_r = cands[ci][1];
+                pick_t = cands[ci][2];
+                auto_best = ci == 0;
             }
         }
         best.fgp_iters = pick_t;

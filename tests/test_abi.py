@@ -154,13 +154,14 @@ def test_plan_get_set_and_validation(nat):
                 got.bp_groups_subset, got.bp_strip_full, got.bp_strip_subset, got.fgp_iters) == \
             (2, 1, 4, 2, 4, 2, 5)
         for bad in (dict(proj_split_full=-1), dict(bp_groups_subset=17), dict(bp_strip_full=3),
-                    dict(fgp_iters=9), dict(bp_method_subset=3), dict(fgp_waves=4, fgp_rows=2),
+                    dict(fgp_iters=17), dict(bp_method_subset=3), dict(fgp_waves=4, fgp_rows=2),
                     dict(fgp_waves=8), dict(fgp_rows=4), dict(fgp_waves=32, fgp_rows=2)):
             assert lib.geometry_set_plan(h, C.byref(nat.Plan(**bad))) == nat.PS_EINVAL
         # a rejected plan leaves the previous one in place
         assert lib.geometry_get_plan(h, C.byref(got)) == nat.PS_OK and got.fgp_iters == 5
         # a 2D FGP tile caps the inner iterations per launch at its height / 2 - 2
-        for w, r, t, want in ((4, 4, 8, 6), (8, 2, 3, 3), (16, 4, 0, 8), (4, 8, 7, 7)):
+        for w, r, t, want in ((4, 4, 8, 6), (8, 2, 3, 3), (16, 4, 0, 8), (4, 8, 7, 7), (16, 4, 16, 16),
+                              (8, 8, 12, 12), (16, 2, 16, 14)):
             assert lib.geometry_set_plan(h, C.byref(nat.Plan(fgp_waves=w, fgp_rows=r, fgp_iters=t))) == nat.PS_OK
             assert lib.geometry_get_plan(h, C.byref(got)) == nat.PS_OK
             assert (got.fgp_waves, got.fgp_rows, got.fgp_iters) == (w, r, want)
@@ -226,5 +227,9 @@ def test_plan_fgp_tile_defaults_per_dtype(nat):
             got = nat.Plan()
             assert lib.geometry_get_plan(h, C.byref(got)) == nat.PS_OK
             assert (got.fgp_waves, got.fgp_rows, got.fgp_iters) == (*tile, 8)
+            # deeper launches: up to 16 inner iterations in FP32, 8 in FP64
+            deep = nat.Plan(fgp_waves=16, fgp_rows=4, fgp_iters=12)
+            want = nat.PS_OK if dt == nat.PS_F32 else nat.PS_EINVAL
+            assert lib.geometry_set_plan(h, C.byref(deep)) == want
         finally:
             lib.free_geometry(h)

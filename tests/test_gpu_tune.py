@@ -23,7 +23,7 @@ def test_autotune_plan_valid_and_cached(tmp_path):
     assert plan == g.get_plan()
     assert 1 <= plan["proj_split_full"] <= 64 and 1 <= plan["proj_split_subset"] <= 64
     assert 1 <= plan["bp_groups_full"] <= 16 and plan["bp_strip_subset"] in (1, 2, 4, 8)
-    assert 2 <= plan["fgp_iters"] <= 8
+    assert 2 <= plan["fgp_iters"] <= 16
     assert plan["bp_method_full"] in (1, 2) and plan["bp_method_subset"] in (1, 2)
     cache = json.load(open(tmp_path / "plans.json"))
     assert cache[g.key] == plan
@@ -98,8 +98,8 @@ TILES = [(4, 4), (4, 8), (8, 2), (8, 4), (8, 8), (16, 2), (16, 4)]
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_fgp_tiles_bitwise_equal(orc, dtype):
-    # the tile shape and iterations per launch decide only which workgroup computes a pixel:
-    # every (tile, T) gives the same bits, and those match the FP64 oracle
+    # the tile shape and iterations per launch (up to 16 in FP32) decide only which workgroup
+    # computes a pixel: every (tile, T) gives the same bits, and those match the FP64 oracle
     from paper_2602_09527_amd import api
     nx, ny = 150, 97   # several tiles of every shape, ragged in both directions
     g = api.Geometry(nx, ny, 30, 40, n_subsets=2, dtype=dtype)
@@ -109,7 +109,7 @@ def test_fgp_tiles_bitwise_equal(orc, dtype):
     vt = torch.from_numpy(v).to("cuda", dtype)
     ref = None
     for w, r in TILES:
-        for T in (1, 3, 8):
+        for T in (1, 3, 8) + ((12, 16) if dtype == torch.float32 else ()):
             g.set_plan(dict(fgp_waves=w, fgp_rows=r, fgp_iters=T))
             assert g.get_plan()["fgp_iters"] == min(T, w * r // 2 - 2)
             dual = torch.from_numpy(d0).to("cuda", dtype)
