@@ -23,7 +23,8 @@ Prints one JSON line.  Besides the timed epochs it reports:
   cpu_baseline  the FP64 oracle timed on the host cores over a bounded sample of the same solve;
   parity        the GPU iterate against the oracle's after that sample.
 
---volume times the 256 x 1024^2 volume instead; --calibrate-copy runs only a plain device copy
+--volume times the 256 x 1024^2 volume instead (5 epochs after 1 warm-up unless --steps and
+--warmup say otherwise); --calibrate-copy runs only a plain device copy
 of known size (for scaling the HBM byte counters).
 """
 from __future__ import annotations
@@ -77,8 +78,8 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=None, help="timed epochs (200; 5 with --volume)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed epochs (5; 1 with --volume)")
     ap.add_argument("--p", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
@@ -105,7 +106,12 @@ def parse():
     ap.add_argument("--volume-ops", action="store_true",
                     help="only run one subset projection, one subset backprojection and a 10-iteration "
                          "3D prox on the volume geometry with random inputs (for counter collection)")
-    return ap.parse_args()
+    args = ap.parse_args()
+    if args.steps is None:
+        args.steps = 5 if args.volume else 200
+    if args.warmup is None:
+        args.warmup = 1 if args.volume else 5
+    return args
 
 
 def stored_L(w):
@@ -245,9 +251,12 @@ def bench_volume(args):
     s.epochs(W)
     s.query()
     torch.cuda.synchronize()
+    log(f"bench: volume {W} warm-up epochs done")
     t1 = time.perf_counter()
-    s.epochs(K)
-    torch.cuda.synchronize()
+    for e in range(K):   # one epoch (about 1.6 s) per call, with a progress line
+        s.epochs(1)
+        torch.cuda.synchronize()
+        log(f"bench: volume epoch {e + 1}/{K} at {time.perf_counter() - t1:.2f} s")
     el = time.perf_counter() - t1
     st = s.query()
     log(f"bench: volume {K} epochs in {el:.3f} s; prox calls {st['prox_calls']}")
