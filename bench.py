@@ -127,7 +127,9 @@ def time_to_eps(api, torch, g, b, w, gamma, ref_iters, passes, alpha):
     """The paper's protocol (Sec. 2.1): wall time and data passes until the squared relative
     error ||x - x*||^2 / ||x*||^2 falls below 1e-3 and 1e-5 (at most `passes` data passes; one
     pass = N subset gradients, or one iteration of a deterministic method), with x* from
-    preconditioned PDHG (the reference method of the data-splitting figure)."""
+    preconditioned PDHG (the reference method of the data-splitting figure).  Step sizes as in the
+    paper's comparison of all methods (Sec. 3): 1.99/L for ISTA and deterministic ProxSkip, 1/L
+    for FISTA and the SVRG family, 1/(3L) for SAGA; `gamma` is 1/L."""
     t0 = time.perf_counter()
     half = ref_iters // 2
     xs, y1, y2 = api.pdhg(g, b, alpha=alpha, n_iters=half, nonneg=w.nonneg)
@@ -152,8 +154,8 @@ def time_to_eps(api, torch, g, b, w, gamma, ref_iters, passes, alpha):
              ("ProxSVRG", g, dict(p=1.0, plain_prox_svrg=True)),
              ("ProxLSVRGSkip p=0.1", g, dict(p=0.1, estimator="lsvrg")),
              ("ProxSAGASkip p=0.1", g, dict(p=0.1, estimator="saga", gamma=gamma / 3.0)),
-             ("ISTA", g1, dict(p=1.0, plain_prox_svrg=True)),
-             ("ProxSkip p=0.1", g1, dict(p=0.1)),
+             ("ISTA", g1, dict(p=1.0, plain_prox_svrg=True, gamma=1.99 * gamma)),
+             ("ProxSkip p=0.1", g1, dict(p=0.1, gamma=1.99 * gamma)),
              ("FISTA", g1, None)]
     runs = []
     for label, geom, kw in specs:
