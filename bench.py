@@ -153,7 +153,9 @@ def time_to_eps(api, torch, g, b, w, gamma, ref_iters, passes, alpha):
              ("ProxSVRGSkip p=0.02", g, dict(p=0.02)),
              ("ProxSVRG", g, dict(p=1.0, plain_prox_svrg=True)),
              ("ProxLSVRGSkip p=0.1", g, dict(p=0.1, estimator="lsvrg")),
+             ("ProxLSVRG", g, dict(p=1.0, estimator="lsvrg", plain_prox_svrg=True)),
              ("ProxSAGASkip p=0.1", g, dict(p=0.1, estimator="saga", gamma=gamma / 3.0)),
+             ("ProxSAGA", g, dict(p=1.0, estimator="saga", plain_prox_svrg=True, gamma=gamma / 3.0)),
              ("ISTA", g1, dict(p=1.0, plain_prox_svrg=True, gamma=1.99 * gamma)),
              ("ProxSkip p=0.1", g1, dict(p=0.1, gamma=1.99 * gamma)),
              ("FISTA", g1, None)]

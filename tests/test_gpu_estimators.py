@@ -60,6 +60,27 @@ def test_small_2d_against_oracle(orc, estimator, dtype, tol, epochs):
     assert abs(st["last_rel_change"] - relo[-1]) <= 10 * tol * relo[-1] + 1e-12
 
 
+@pytest.mark.parametrize("estimator", ["lsvrg", "saga"])
+@pytest.mark.parametrize("dtype,tol,epochs", [(torch.float32, 1e-4, 10), (torch.float64, 1e-9, 3)])
+def test_non_skipped_against_oracle(orc, estimator, dtype, tol, epochs):
+    # ProxLSVRG and ProxSAGA: the prox after every step (h unused), tau = gamma alpha
+    from paper_2602_09527_amd import api, workloads
+    w = workloads.SMALL_2D
+    g, b, b_dev = _setup(w, dtype)
+    o = orc.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=w.n_subsets)
+    L = _L(w)
+    gamma = 1.0 / L if estimator == "lsvrg" else 1.0 / (3.0 * L)
+    kw = dict(gamma=gamma, p=1.0, alpha=w.alpha, fgp_inner=w.fgp_inner, nonneg=w.nonneg,
+              seed=w.seed + 2)
+    xo, _, _, so, _ = orc.proxskip(o, b, estimator=estimator, n_epochs=epochs, plain=True, **kw)
+    x, h, _, st = api.solve(g, b_dev, api.SolverParams(n_epochs=epochs, estimator=estimator,
+                                                       plain_prox_svrg=True, **kw))
+    torch.cuda.synchronize()
+    assert st["prox_calls"] == so["prox_calls"] == epochs * w.n_subsets
+    assert _rel(x.cpu().numpy(), xo) <= tol, _rel(x.cpu().numpy(), xo)
+    assert float(h.abs().max()) == 0.0
+
+
 def test_lsvrg_single_subset_is_svrg_bitwise():
     # N = 1: the loopless refresh fires every iteration, as the SVRG epoch start does
     from paper_2602_09527_amd import api, synth
