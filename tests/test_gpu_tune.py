@@ -121,3 +121,21 @@ def test_fgp_tiles_bitwise_equal(orc, dtype):
                 assert _rel(z.cpu().numpy(), z_ref) <= (1e-5 if dtype == torch.float32 else 1e-12)
             else:
                 assert torch.equal(z, ref[0]) and torch.equal(dual, ref[1]), (w, r, T)
+
+
+@pytest.mark.parametrize("shape", [(1, 40), (37, 1), (5, 3), (70, 2), (2, 65)])
+def test_fgp_tiles_on_degenerate_images(orc, shape):
+    # images narrower or shorter than one tile's halo: every tile and depth stays within the
+    # image and matches the oracle
+    from paper_2602_09527_amd import api
+    nx, ny = shape
+    g = api.Geometry(nx, ny, 8, 12, n_subsets=1)
+    rng = np.random.default_rng(nx * 100 + ny)
+    v = rng.random((1, ny, nx))
+    z_ref = orc.tv_prox_fgp(v, 0.1, 23, nonneg=True, dual=np.zeros((2, 1, ny, nx)))
+    vt = torch.from_numpy(v).to("cuda", torch.float32)
+    for w, r in TILES:
+        for T in (1, 8, 16):
+            g.set_plan(dict(fgp_waves=w, fgp_rows=r, fgp_iters=T))
+            z = api.tv_prox(g, vt, 0.1, 23, dual=torch.zeros(g.dual_shape(), device="cuda"))
+            assert _rel(z.cpu().numpy(), z_ref) <= 1e-5, (w, r, T)
