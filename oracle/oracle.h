@@ -12,7 +12,7 @@
  * fast-math.  OpenMP is used only over output elements: every output element is accumulated by
  * one thread in a fixed serial order, so results do not depend on the thread count.
  *
- * Conventions (the readings of points the paper leaves open are listed in the design doc):
+ * Conventions (where the paper leaves a point open, the reading taken is stated here):
  *   image x:     [nz][ny][nx] row-major, pixel (i, j) centre at (j - (nx-1)/2, i - (ny-1)/2),
  *                unit pixels; slices are independent for the projector (rotation axis = z).
  *   angles:      theta_k = k*pi/A unless an explicit table is given.
