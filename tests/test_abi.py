@@ -233,3 +233,31 @@ def test_plan_fgp_tile_defaults_per_dtype(nat):
             assert lib.geometry_set_plan(h, C.byref(deep)) == want
         finally:
             lib.free_geometry(h)
+
+
+def test_binding_structs_match_the_c_layout(nat, tmp_path):
+    # the ctypes structures of the binding against the header as a C compiler lays it out
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    structs = {"ps_geometry_desc": nat.GeometryDesc, "ps_plan": nat.Plan,
+               "ps_solver_params": nat.SolverParams, "ps_solver_stats": nat.SolverStats}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "proxskip.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
