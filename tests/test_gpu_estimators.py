@@ -197,3 +197,29 @@ def test_fista_continuation_bitwise():
     two = api.Fista(g, b, **kw).run(10).run(15)
     torch.cuda.synchronize()
     assert torch.equal(one.x, two.x) and torch.equal(one.y, two.y) and one.t.value == two.t.value
+
+
+@pytest.mark.parametrize("method", ["lsvrg", "saga", "fista"])
+@pytest.mark.parametrize("dtype,tol", [(torch.float32, 1e-4), (torch.float64, 1e-9)])
+def test_volume_with_3d_tv_against_oracle(orc, method, dtype, tol):
+    # 4 slices of 48^2 coupled by 3D TV: the volume paths of the other estimators and of FISTA
+    from paper_2602_09527_amd import api, synth
+    nx, nz, A, B, N = 48, 4, 60, 72, 6
+    prob = synth.make_problem(nx, nx, A, B, seed=61, nz=nz, with_phantom=False)
+    o = orc.Geometry(nx, nx, A, B, n_subsets=1 if method == "fista" else N, nz=nz)
+    g = api.Geometry(nx, nx, A, B, n_subsets=1 if method == "fista" else N, nz=nz, dtype=dtype)
+    b = torch.from_numpy(prob.b).to(device="cuda", dtype=dtype)
+    L = orc.lipschitz(o, 200)
+    if method == "fista":
+        kw = dict(gamma=1.0 / L, alpha=0.02, fgp_inner=15, nonneg=True)
+        xo, do, _ = orc.fista(o, prob.b, n_iters=12, **kw)
+        x, d = api.fista(g, b, n_iters=12, **kw)
+    else:
+        gamma = 1.0 / L if method == "lsvrg" else 1.0 / (3.0 * L)
+        kw = dict(gamma=gamma, p=0.3, alpha=0.02, fgp_inner=15, nonneg=True, seed=62)
+        xo, _, do, so, _ = orc.proxskip(o, prob.b, estimator=method, n_epochs=5, **kw)
+        x, _, d, st = api.solve(g, b, api.SolverParams(n_epochs=5, estimator=method, **kw))
+        assert st["prox_calls"] == so["prox_calls"]
+    torch.cuda.synchronize()
+    assert d.shape[0] == 3   # three dual components: the slices are coupled
+    assert _rel(x.cpu().numpy(), xo) <= tol, _rel(x.cpu().numpy(), xo)
