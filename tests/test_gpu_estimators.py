@@ -223,3 +223,24 @@ def test_volume_with_3d_tv_against_oracle(orc, method, dtype, tol):
     torch.cuda.synchronize()
     assert d.shape[0] == 3   # three dual components: the slices are coupled
     assert _rel(x.cpu().numpy(), xo) <= tol, _rel(x.cpu().numpy(), xo)
+
+
+@pytest.mark.parametrize("estimator", ["lsvrg", "saga"])
+def test_single_2d_512_two_epochs(orc, estimator):
+    # the benchmarked shape (512^2, 720 angles x 768 bins, 20 subsets, p = 0.1, 50 FGP
+    # iterations) with the stored launch plan, 2 epochs
+    from paper_2602_09527_amd import api, workloads
+    import bench
+    w = workloads.SINGLE_2D
+    g, b, b_dev = _setup(w, torch.float32)
+    api.autotune(g, reps=1, cache_path=bench.PLANS_FILE, store=False, tune_missing=False)
+    o = orc.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=w.n_subsets)
+    L = _L(w)
+    gamma = 1.0 / L if estimator == "lsvrg" else 1.0 / (3.0 * L)
+    kw = dict(gamma=gamma, p=w.p, alpha=w.alpha, fgp_inner=w.fgp_inner, nonneg=w.nonneg,
+              seed=w.seed + 2)
+    xo, _, _, so, _ = orc.proxskip(o, b, estimator=estimator, n_epochs=2, **kw)
+    x, _, _, st = api.solve(g, b_dev, api.SolverParams(n_epochs=2, estimator=estimator, **kw))
+    torch.cuda.synchronize()
+    assert st["prox_calls"] == so["prox_calls"]
+    assert _rel(x.cpu().numpy(), xo) <= 1e-4, _rel(x.cpu().numpy(), xo)
