@@ -119,6 +119,27 @@ def test_brute_force_8x8_vs_independent_solver(orc, nonneg):
         assert np.all(z >= 0.0) and np.any(z == 0.0)
 
 
+def test_brute_force_3d_duality_gap(orc):
+    # A volume that varies along z: the unconstrained 3D prox closes the primal-dual gap,
+    # primal 1/2||z - v||^2 + tau TV3(z) (TV3 from the differences written in this file) against
+    # dual 1/2||v||^2 - 1/2||v - tau D^T p|| ^2, with z = v - tau D^T p and |p_ijk| <= 1.
+    rng = np.random.default_rng(8)
+    v = rng.uniform(0.0, 1.0, (3, 5, 6))
+    tau = 0.1
+    dual = np.zeros((3, 3, 5, 6))
+    z = orc.tv_prox_fgp(v, tau, 40000, nonneg=False, dual=dual)
+    DTp = _DT_from_oracle(orc, dual).reshape(v.shape)
+    tv3 = float(np.sum(np.sqrt(np.sum(_D(z) ** 2, axis=0))))
+    assert np.max(np.sqrt(np.sum(dual ** 2, axis=0))) <= 1.0 + 1e-15
+    primal = 0.5 * np.sum((z - v) ** 2) + tau * tv3
+    dualv = 0.5 * np.sum(v ** 2) - 0.5 * np.sum((v - tau * DTp) ** 2)
+    assert abs(primal - dualv) <= 1e-10, primal - dualv
+    assert np.max(np.abs(z - (v - tau * DTp))) <= 1e-15
+    # the z coupling matters: the slice-wise 2D prox is not the answer
+    z2 = np.stack([orc.tv_prox_fgp(v[k], tau, 20000, nonneg=False) for k in range(3)])
+    assert np.max(np.abs(z - z2)) >= 1e-3
+
+
 def test_3d_constant_along_z_matches_2d(orc):
     # The z differences of a z-constant volume are zero, so the 3D prox is the 2D prox of each
     # slice (at convergence; the 3D step size 1/(12 tau) differs from the 2D 1/(8 tau)).
