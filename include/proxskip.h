@@ -170,14 +170,14 @@ PS_API ps_status tv_prox_fgp(const ps_geometry *geom, const void *v, void *z, do
                       int32_t n_inner, int32_t nonneg, void *dual, void *workspace,
                       size_t ws_bytes, void *stream);
 
-/* Gradient estimators G_k of the table beside Algorithm 1 (Sec. 1.3). */
+/* Gradient estimators G_k of the table beside Algorithm 1 (Sec. 1.2). */
 typedef enum {
     PS_EST_SVRG = 0,   /* N (grad f_i(x) - grad f_i(xs)) + grad f(xs), xs refreshed every N iterations */
     PS_EST_LSVRG = 1,  /* the same G, xs refreshed with probability 1/N per iteration (loopless)     */
     PS_EST_SAGA = 2    /* N (grad f_i(x) - v_i) + sum_j v_j with the table v of Eq. 4              */
 } ps_estimator;
 
-/* Parameters of Algorithm 1 (Sec. 1.3). */
+/* Parameters of Algorithm 1 (Sec. 1.2). */
 typedef struct {
     double gamma;             /* step size > 0 (the paper uses 1/L, L = ||A||^2)                */
     double p;                 /* prox probability, 0 < p <= 1                                   */
@@ -281,7 +281,7 @@ PS_API void solver_free(ps_solver *handle);
 PS_API ps_status sample_sequences(uint64_t seed, int64_t k0, int64_t count, int32_t n_subsets,
                            double p, int32_t *subset_out, uint8_t *coin_out);
 
-/* Refresh coins of the loopless SVRG estimator (Sec. 1.3: the full gradient is refreshed with
+/* Refresh coins of the loopless SVRG estimator (Sec. 1.2: the full gradient is refreshed with
  * probability 1/N in every iteration), from the same generator at counters 2^62 + k:
  *   rho_k = (u(seed, 2^62 + k) >> 11) < floor(2^53 / N),   k = k0 .. k0+count-1.
  * Errors: PS_EINVAL. */

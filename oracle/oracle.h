@@ -21,9 +21,11 @@
  *                the data-splitting figure), stored as [nz][a_i][B] with its angles in order.
  *   dual field:  [d][nz][ny][nx], d = 2 for nz == 1 and d = 3 otherwise (3D TV couples slices).
  *
- * Parity pins: see tests/test_oracle_*.py.  The end-to-end ProxSkip iterate has no printed
- * value in the paper; it is pinned only through the component pins and the algorithm's
- * reductions (p = 1 is proximal gradient; prox = identity gives plain SVRG descent).
+ * Parity pins: see tests/test_oracle_*.py.  The paper prints no iterate value.  The loop is
+ * pinned by the algorithm's reductions (p = 1 is proximal gradient; prox = identity gives plain
+ * SVRG descent) and, at p < 1 with a non-trivial prox, by its fixed point (x -> x* of the
+ * reference method, h -> grad f(x*)); FGP at a finite number of inner iterations is pinned by
+ * trajectories derived by hand on two- and four-pixel images.
  */
 #ifndef PROXSKIP_ORACLE_H
 #define PROXSKIP_ORACLE_H
@@ -122,14 +124,14 @@ int orc_proxskip_svrg(const orc_geom *g, const double *b, double *x, double *h, 
                       int n_epochs, int plain, uint64_t seed, int64_t k0, double tol,
                       orc_stats *stats, double *rel_change_out);
 
-/* Refresh coins of the loopless SVRG estimator (Sec. 1.3: the full gradient is refreshed with
+/* Refresh coins of the loopless SVRG estimator (Sec. 1.2: the full gradient is refreshed with
  * probability 1/N in every iteration):
  *   rho_k = (u(seed, 2^62 + k) >> 11) < floor(2^53 / N)      (integer division)
  * for k = k0 .. k0 + count - 1.  The counters 2^62 + k never meet the subset and coin counters
  * 2k and 2k + 1 while k < 2^61. */
 void orc_refresh_coins(uint64_t seed, int64_t k0, int64_t count, int n_subsets, uint8_t *out);
 
-/* Gradient estimators of the table beside Algorithm 1 (Sec. 1.3). */
+/* Gradient estimators of the table beside Algorithm 1 (Sec. 1.2). */
 enum { ORC_SVRG = 0, ORC_LSVRG = 1, ORC_SAGA = 2 };
 
 /* Algorithm 1 with estimator G_k:

@@ -186,3 +186,49 @@ def test_invalid_arguments(orc):
         orc.proxskip_svrg(g, b, gamma=-1.0, p=0.5, alpha=0.1, fgp_inner=5, n_epochs=1)
     with pytest.raises(ValueError):
         orc.proxskip_svrg(g, b, gamma=1e-3, p=0.5, alpha=0.1, fgp_inner=5, n_epochs=1, k0=1)
+
+
+# ---------------------------------------------------------------------------------------------
+# Fixed point of Algorithm 1 at p < 1 with a non-trivial prox.
+# ---------------------------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def fixed_point_problem(orc):
+    """12 x 12, 24 angles x 18 bins, alpha = 2, with the constraint; x* from the reference
+    PDHG method (pinned by its optimality conditions in test_oracle_reference.py)."""
+    g1 = orc.Geometry(12, 12, n_angles=24, n_bins=18, n_subsets=1)
+    rng = np.random.default_rng(0)
+    b = np.abs(rng.standard_normal((1, 24, 18))) * 5.0
+    L = orc.lipschitz(g1, 500)
+    xstar, _, _ = orc.pdhg(g1, b, alpha=2.0, n_iters=5000, nonneg=True)
+    x_more, _, _ = orc.pdhg(g1, b, alpha=2.0, n_iters=6000, nonneg=True)
+    assert np.linalg.norm(x_more - xstar) <= 1e-13 * np.linalg.norm(xstar)
+    return b, L, xstar
+
+
+@pytest.mark.parametrize("estimator,N,p,epochs,gscale", [
+    ("svrg", 1, 0.3, 1000, 1.0),      # deterministic ProxSkip: N = 1 gives G = grad f
+    ("svrg", 4, 0.3, 300, 1.0),       # ProxSVRGSkip
+    ("svrg", 4, 0.1, 400, 1.0),
+    ("lsvrg", 4, 0.3, 300, 1.0),      # ProxLSVRGSkip
+    ("saga", 4, 0.3, 600, 1.0 / 3.0),  # ProxSAGASkip at the paper's 1/(3L)
+])
+def test_proxskip_reaches_the_fixed_point(orc, fixed_point_problem, estimator, N, p, epochs,
+                                          gscale):
+    # ProxSkip's fixed point (Mishchenko et al. 2022, the method Algorithm 1 builds on): x_k ->
+    # x* = argmin f + g and h_k -> grad f(x*), since x* = prox_{(gamma/p) g}(x* - (gamma/p)
+    # grad f(x*)) makes both the skipped and the prox branch leave (x*, grad f(x*)) in place.
+    # A wrong sign or weight in the h line, or in the prox argument x^ - (gamma/p) h, moves or
+    # breaks this fixed point.
+    b, L, xstar = fixed_point_problem
+    g = orc.Geometry(12, 12, n_angles=24, n_bins=18, n_subsets=N)
+    x, h, _, st, _ = orc.proxskip(g, b, estimator=estimator, gamma=gscale / L, p=p, alpha=2.0,
+                                  fgp_inner=50, n_epochs=epochs, nonneg=True, seed=5)
+    assert 0 < st["prox_calls"] < st["iters_done"]
+    gf = orc.grad_full(g, xstar, b)
+    assert np.linalg.norm(x - xstar) <= 1e-8 * np.linalg.norm(xstar)
+    assert np.linalg.norm(h - gf) <= 1e-8 * np.linalg.norm(gf)
+    if estimator == "svrg":
+        x2, h2, _, _, _ = orc.proxskip_svrg(g, b, gamma=gscale / L, p=p, alpha=2.0,
+                                            fgp_inner=50, n_epochs=epochs, nonneg=True, seed=5)
+        assert np.array_equal(x, x2) and np.array_equal(h, h2)
