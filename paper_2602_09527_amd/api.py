@@ -125,12 +125,14 @@ class Geometry:
             raise ValueError(f"{what} is on {t.device}, geometry is on {self.device}")
         if t.dtype != self.dtype:
             raise TypeError(f"{what} has dtype {t.dtype}, geometry uses {self.dtype}")
-        if tuple(t.shape) != tuple(shape):
-            t = t.reshape(shape) if t.numel() == math.prod(shape) else None
-            if t is None:
-                raise ValueError(f"{what} must have shape {tuple(shape)}")
+        # contiguity first: a reshape of a strided tensor would hand the kernels a copy, and an
+        # in/out buffer (x, h, dual, out) would then be updated in the copy, not in the caller's
         if not t.is_contiguous():
             raise ValueError(f"{what} must be contiguous")
+        if tuple(t.shape) != tuple(shape):
+            if t.numel() != math.prod(shape):
+                raise ValueError(f"{what} must have shape {tuple(shape)}")
+            t = t.view(shape)   # a view of the same memory, never a copy
         return t
 
     def workspace(self, key, nbytes: int) -> torch.Tensor | None:

@@ -189,3 +189,21 @@ def test_backproject_methods_parity(orc, shape, dtype, tol, method):
         y = rng.standard_normal(g.sino_shape(subset))
         x = api.backproject(g, _dev(y, dtype), subset).cpu().numpy()
         assert _rel(x, orc.backproject(o, y, subset)) <= tol, (subset, method)
+
+
+def test_strided_buffers_are_refused_not_copied():
+    # an in/out buffer given as a strided view must raise: a reshaped copy would receive the
+    # result (or the warm-start dual) instead of the caller's tensor
+    from paper_2602_09527_amd import api
+    g = api.Geometry(16, 16, 12, 16, n_subsets=2)
+    v = torch.rand(g.image_shape, device="cuda")
+    dual_big = torch.zeros((2, 1, 16, 32), device="cuda")
+    with pytest.raises(ValueError):
+        api.tv_prox(g, v, 0.1, 5, dual=dual_big[..., ::2])
+    with pytest.raises(ValueError):
+        api.project(g, torch.rand(1, 16, 32, device="cuda")[..., ::2])
+    # a contiguous tensor of another shape with the right count is a view: results land in it
+    flat = torch.zeros(2 * 16 * 16, device="cuda")
+    api.tv_prox(g, v, 0.1, 5, dual=flat)
+    torch.cuda.synchronize()
+    assert float(flat.abs().sum()) > 0

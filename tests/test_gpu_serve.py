@@ -60,3 +60,28 @@ def test_requests_arriving_mid_run_are_admitted():
                 if a["rid"] < b["rid"] and b["admitted"] < a["finished"])
     assert overl > 0
     assert all(r["epochs"] >= 1 for r in res)
+
+
+def test_served_request_matches_the_oracle(orc):
+    # a sampled request of a served mix, solved to the relative-change rule, against the FP64
+    # oracle on the same data (its FP32 sinogram), step size and streams after the same epochs
+    import numpy as np
+    from paper_2602_09527_amd import serve
+    trace, geoms, bank = _setup(n=6, rate=400.0)
+    cfg = serve.ServeConfig(fgp_inner=20, tol=5e-3, max_epochs=40, max_slots=6, steps_per_round=7)
+    pick = max(trace, key=lambda r: (r.side, r.n_angles))
+    res, _ = serve.serve(trace, cfg, bank, geoms, keep={pick.rid})
+    got = {r["rid"]: r for r in res}[pick.rid]
+    assert got["converged"] and got["epochs"] < cfg.max_epochs
+    g, L = geoms.get(pick)
+    o = orc.Geometry(pick.side, pick.side, pick.n_angles, pick.n_bins, n_subsets=pick.n_subsets)
+    b = bank[pick.rid].numpy().astype(np.float64)
+    xo, _, _, so, relo = orc.proxskip_svrg(o, b, gamma=1.0 / L, p=cfg.p, alpha=cfg.alpha,
+                                           fgp_inner=cfg.fgp_inner, n_epochs=got["epochs"],
+                                           nonneg=True, seed=pick.seed + 2)
+    assert so["prox_calls"] == got["prox_calls"]
+    # the oracle crosses the tolerance at the same epoch end
+    assert relo[-1] < cfg.tol * 1.01 and np.all(relo[:-1] >= cfg.tol * 0.99)
+    x = got["x"].cpu().numpy().astype(np.float64)
+    rel = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    assert rel <= 1e-4, rel

@@ -81,6 +81,25 @@ def test_p1_equals_proximal_svrg(orc):
     assert np.max(np.abs(xs1 - x)) <= 1e-12 * np.max(np.abs(x))
 
 
+@pytest.mark.slow
+def test_p1_equals_proximal_svrg_at_512(orc):
+    # the same reduction on the benchmarked solve: 512^2, 720 angles x 768 bins, 20 subsets,
+    # alpha = 0.005, 50 FGP iterations, one epoch (20 prox calls), within 1e-12
+    from paper_2602_09527_amd import synth, workloads
+    w = workloads.SINGLE_2D
+    prob = synth.make_problem(w.nx, w.ny, w.n_angles, w.n_bins, seed=w.seed, noise=w.noise,
+                              with_phantom=False)
+    g = orc.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=w.n_subsets)
+    L = json.load(open(os.path.join(GOLDEN, "lipschitz.json")))[w.key]["L"]
+    kw = dict(gamma=1.0 / L, p=1.0, alpha=w.alpha, fgp_inner=w.fgp_inner, n_epochs=1,
+              nonneg=w.nonneg, seed=w.seed + 2)
+    x1, h1, _, s1, _ = orc.proxskip_svrg(g, prob.b, **kw)
+    x2, h2, _, s2, _ = orc.proxskip_svrg(g, prob.b, plain=True, **kw)
+    assert s1["prox_calls"] == s2["prox_calls"] == w.n_subsets
+    assert not np.any(h2)
+    assert np.linalg.norm(x1 - x2) <= 1e-12 * np.linalg.norm(x2)
+
+
 @pytest.mark.parametrize("p", [0.3, 1.0])
 def test_trivial_prox_is_plain_svrg_descent(orc, p):
     # alpha = 0 and no constraint: the prox is the identity, h stays exactly zero and the
