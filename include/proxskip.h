@@ -229,6 +229,25 @@ PS_API ps_status proxskip_svrg_run(const ps_geometry *geom, const void *b, void 
                             ps_solver_stats *stats_out, void *workspace, size_t ws_bytes,
                             void *stream);
 
+/* proxskip_svrg_run for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same iteration and
+ * arguments, and bit for bit the same results, without a workspace.  The solver's scratch lives
+ * in a fixed device array of the library, proxskip_noalloc_max_bytes() bytes (64 MiB), one per
+ * GPU, held from the first call on that GPU until the process ends; its device address is taken
+ * once per device on the first call there (the caller's current device is used).  The call makes
+ * no device allocation.
+ * Limits: proxskip_workspace_bytes(geom, params) must not exceed proxskip_noalloc_max_bytes()
+ * (a 512^2 FP32 solve with 720 x 768 data fits), else PS_EINVAL; tol_rel_change must be 0 (a
+ * fixed number of epochs), else PS_EINVAL.
+ * Every call on one GPU uses the same array, which keeps the last call's contents (nothing in it
+ * has to start at zero): calls that overlap on one GPU (other streams, other host threads) race
+ * and must be serialised by the caller.  Synchronises `stream` once at the end.
+ * Errors: PS_EINVAL, PS_EHIP, PS_ENONFINITE. */
+PS_API size_t proxskip_noalloc_max_bytes(void);
+PS_API ps_status proxskip_svrg_run_noalloc(const ps_geometry *geom, const void *b, void *x, void *h,
+                                    void *dual, const ps_solver_params *params,
+                                    ps_solver_stats *stats_out, void *stream);
+
 /* Resumable solver handles (the same iteration as proxskip_svrg_run, split into calls), and
  * batching of independent problems.
  * solver_init binds caller-owned buffers (they must outlive the handle; the workspace must be

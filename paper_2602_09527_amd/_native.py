@@ -29,6 +29,7 @@ EXPORTS = (
     "solver_cancel",
     "solver_free", "sample_sequences", "sample_refresh_coins", "fista_workspace_bytes",
     "fista_run", "pdhg_workspace_bytes", "pdhg_run", "last_error_message",
+    "proxskip_noalloc_max_bytes", "proxskip_svrg_run_noalloc",
 )
 PS_EST_SVRG, PS_EST_LSVRG, PS_EST_SAGA = 0, 1, 2
 
@@ -121,6 +122,9 @@ def load():
         "pdhg_workspace_bytes": (sz, [vp]),
         "pdhg_run": (st, [vp, vp, vp, vp, vp, d, i32, i32, vp, sz, vp]),
         "last_error_message": (C.c_char_p, []),
+        "proxskip_noalloc_max_bytes": (sz, []),
+        "proxskip_svrg_run_noalloc": (st, [vp, vp, vp, vp, vp, C.POINTER(SolverParams),
+                                           C.POINTER(SolverStats), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -243,6 +243,27 @@ def solve(g: Geometry, b: torch.Tensor, params: SolverParams, x=None, h=None, du
     return x, h, dual, _stats(st)
 
 
+def solve_noalloc(g: Geometry, b: torch.Tensor, params: SolverParams, x=None, h=None, dual=None):
+    """``solve`` without a workspace: the library's fixed per-GPU scratch array holds the solver's
+    work buffers (proxskip_svrg_run_noalloc; at most proxskip_noalloc_max_bytes() of them, a fixed
+    number of epochs, and calls on one GPU must not overlap).  Allocates nothing on the device
+    beyond x, h, dual when they are omitted.
+
+    Returns (x, h, dual, stats)."""
+    b = g.check(b, (g.nz, g.n_angles, g.n_bins), "b")
+    x = g.zeros_image() if x is None else g.check(x, g.image_shape, "x")
+    h = g.zeros_image() if h is None else g.check(h, g.image_shape, "h")
+    dual = (torch.zeros(g.dual_shape(), dtype=g.dtype, device=g.device) if dual is None
+            else g.check(dual, g.dual_shape(), "dual"))
+    prm = params.c()
+    st = nat.SolverStats()
+    with torch.cuda.device(g.device):
+        nat.check(g.lib.proxskip_svrg_run_noalloc(g.handle, _ptr(b), _ptr(x), _ptr(h), _ptr(dual),
+                                                  C.byref(prm), C.byref(st), _stream(g.device)),
+                  "proxskip_svrg_run_noalloc")
+    return x, h, dual, _stats(st)
+
+
 class Solver:
     """Resumable ProxSkip-SVRG handle: owns its state tensors and workspace."""
 

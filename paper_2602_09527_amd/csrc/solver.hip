@@ -18,6 +18,7 @@
 #include <climits>
 #include <cmath>
 #include <atomic>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -855,6 +856,66 @@ extern "C" ps_status proxskip_svrg_run(const ps_geometry *g, const void *b, void
     }
     solver_free(s);
     return st;
+}
+
+// ---------------------------------------------------------------------------------------------
+// proxskip_svrg_run without a caller workspace: the solver's scratch (snapshot, its gradient, the
+// prox argument, one sinogram, projector partial sums, backprojector partial images, FGP
+// buffers, epoch norms) lives in a fixed device array of this file, one per GPU, for callers
+// that cannot allocate device memory.  Host code never names the array in a launch or copy: its
+// device address is looked up once per device (hipGetSymbolAddress, with that device current)
+// and that address is what the kernels receive.  Every region of the solver workspace is written
+// before it is read (the workspace entry point takes uninitialised memory too), so nothing has
+// to be cleared between calls.
+// ---------------------------------------------------------------------------------------------
+namespace ps {
+
+constexpr size_t kStaticScratchBytes = static_cast<size_t>(64) << 20;
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+static std::mutex g_scratch_mutex;
+static unsigned char *g_scratch_ptr[kMaxDevices];
+
+// Device address of this GPU's scratch array (the current device's), looked up on first use.
+static ps_status static_scratch(unsigned char **out) {
+    int dev = -1;
+    PS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(PS_EINVAL, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(PS_EHIP, "hipGetSymbolAddress(scratch) on device %d failed: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<unsigned char *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return PS_OK;
+}
+
+}  // namespace ps
+
+extern "C" size_t proxskip_noalloc_max_bytes(void) { return ps::kStaticScratchBytes; }
+
+extern "C" ps_status proxskip_svrg_run_noalloc(const ps_geometry *g, const void *b, void *x, void *h,
+                                               void *dual, const ps_solver_params *prm,
+                                               ps_solver_stats *stats_out, void *stream) {
+    clear_error();
+    if (!g) return fail(PS_EINVAL, "geometry is null");
+    PS_TRY(check_params(g, prm));
+    if (prm->tol_rel_change > 0.0)
+        return fail(PS_EINVAL, "proxskip_svrg_run_noalloc runs a fixed number of epochs: "
+                               "tol_rel_change must be 0 (the tolerance check needs pinned host memory)");
+    const size_t need = layout(g, prm->n_epochs, prm->estimator).total;
+    if (need > kStaticScratchBytes)
+        return fail(PS_EINVAL, "proxskip_svrg_run_noalloc: this problem needs %zu bytes of scratch, "
+                               "the static scratch holds %zu", need, kStaticScratchBytes);
+    unsigned char *ws = nullptr;
+    PS_TRY(static_scratch(&ws));
+    return proxskip_svrg_run(g, b, x, h, dual, prm, stats_out, ws, kStaticScratchBytes, stream);
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -261,3 +261,35 @@ def test_binding_structs_match_the_c_layout(nat, tmp_path):
         assert got[(cname, "size")] == C.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_noalloc_entry_rejects_on_the_host(nat):
+    # proxskip_svrg_run_noalloc: parameter checks, a tolerance run, and a problem whose solver
+    # scratch exceeds the static array are refused before any device call
+    lib = nat.load()
+    assert lib.proxskip_noalloc_max_bytes() == 64 << 20
+    fake = C.c_void_p(256)
+    good = dict(gamma=1e-3, p=0.5, alpha=0.1, fgp_inner=5, nonneg=1, n_epochs=2,
+                plain_prox_svrg=0, seed=1, k0=0, tol_rel_change=0.0)
+    h = C.c_void_p()
+    assert lib.make_geometry(C.byref(_desc(nat)), C.byref(h)) == nat.PS_OK
+    try:
+        for bad in (dict(gamma=0.0), dict(p=1.5), dict(n_epochs=-1), dict(tol_rel_change=1e-4)):
+            P = nat.SolverParams(**{**good, **bad})
+            assert lib.proxskip_svrg_run_noalloc(h, fake, fake, fake, fake, C.byref(P), None,
+                                                 None) == nat.PS_EINVAL
+        assert lib.proxskip_svrg_run_noalloc(None, fake, fake, fake, fake,
+                                             C.byref(nat.SolverParams(**good)), None, None) == nat.PS_EINVAL
+    finally:
+        lib.free_geometry(h)
+    big = C.c_void_p()
+    assert lib.make_geometry(C.byref(_desc(nat, nx=1024, ny=1024, n_angles=1800, n_bins=1448,
+                                           n_subsets=30)), C.byref(big)) == nat.PS_OK
+    try:
+        P = nat.SolverParams(**good)
+        assert lib.proxskip_workspace_bytes(big, C.byref(P)) > lib.proxskip_noalloc_max_bytes()
+        assert lib.proxskip_svrg_run_noalloc(big, fake, fake, fake, fake, C.byref(P), None,
+                                             None) == nat.PS_EINVAL
+        assert b"static scratch" in lib.last_error_message()
+    finally:
+        lib.free_geometry(big)
