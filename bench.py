@@ -94,10 +94,18 @@ def parse():
                     help="TV weight of the time-to-epsilon problem: 50 makes 1e-5 reachable in 200 "
                          "data passes; at the workload's 0.005 the problem is nearly unregularised "
                          "least squares and no method gets below 1e-3 in 200 passes")
+    ap.add_argument("--no-oracle-extra", action="store_true",
+                    help="skip the oracle's 1-thread run and its timings on the other workloads")
+    ap.add_argument("--no-volume", action="store_true",
+                    help="skip the bounded leg on the 256 x 1024^2 volume")
+    ap.add_argument("--volume-epochs", type=int, default=2,
+                    help="timed epochs of the volume leg (after one warm-up)")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=60)
-    ap.add_argument("--serve-cap", type=int, default=30, help="epoch cap per served request")
+    ap.add_argument("--serve-requests", type=int, default=40,
+                    help="requests of the bounded serving trace")
+    ap.add_argument("--serve-cap", type=int, default=200,
+                    help="epoch cap per served request (each stops earlier at 1e-4 relative change)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrivals per second")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (for HBM counter scaling)")
@@ -106,6 +114,9 @@ def parse():
     ap.add_argument("--volume-ops", action="store_true",
                     help="only run one subset projection, one subset backprojection and a 10-iteration "
                          "3D prox on the volume geometry with random inputs (for counter collection)")
+    ap.add_argument("--solve", default=None, metavar="WORKLOAD",
+                    help="only time --steps epochs of one 2D workload's solve after --warmup "
+                         "(2d-128-a180 or 2d-512-a720; a short program for kernel traces)")
     args = ap.parse_args()
     if args.steps is None:
         args.steps = 5 if args.volume else 200
@@ -230,8 +241,13 @@ def volume_ops():
     log("bench: volume ops: 10-iteration prox done")
 
 
-def bench_volume(args):
-    """256 slices of 1024^2 coupled by 3D TV: one ProxSkip-SVRG epoch per step."""
+def volume_leg(epochs, warmup, log_fn, graph_check=True, plan_check=True, oracle_ops=True):
+    """The 256 x 1024^2 volume (1800 angles x 1448 bins, 30 subsets, 3D TV, p = 0.05): `epochs`
+    timed ProxSkip-SVRG epochs after `warmup`, per-operator times with the stored plan and with
+    the automatic one, one epoch eager against the same epoch issued as a captured HIP graph, and
+    the FP64 oracle's per-operator times on a few slices of the same geometry, extrapolated to the
+    volume (labelled as such)."""
+    import numpy as np
     import torch
     from paper_2602_09527_amd import api, synth, workloads
     w = workloads.VOLUME_3D
@@ -243,27 +259,41 @@ def bench_volume(args):
     b = synth.poisson_log_noise_torch(clean, w.seed + 1)
     del clean
     torch.cuda.synchronize()
-    log(f"bench: volume data {tuple(b.shape)} in {time.time() - t0:.1f} s")
+    t_data = time.time() - t0
+    log_fn(f"bench: volume data {tuple(b.shape)} in {t_data:.1f} s")
     g = api.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=w.n_subsets, nz=w.nz, device=dev)
     plan = api.autotune(g, reps=2, cache_path=PLANS_FILE, store=False, tune_missing=False)
-    log(f"bench: launch plan {plan}")
     L = stored_L(w) or api.lipschitz(g, 20)
-    K, W = args.steps, args.warmup
-    prm = api.SolverParams(gamma=1.0 / L, p=w.p, alpha=w.alpha, fgp_inner=w.fgp_inner,
-                           n_epochs=W + K, nonneg=w.nonneg, seed=w.seed + 2)
-    s = api.Solver(g, b, prm)
+    K, W = epochs, warmup
+    N = w.n_subsets
+    prm = dict(gamma=1.0 / L, p=w.p, alpha=w.alpha, fgp_inner=w.fgp_inner, nonneg=w.nonneg,
+               seed=w.seed + 2)
+    s = api.Solver(g, b, api.SolverParams(n_epochs=W + K, **prm))
     s.epochs(W)
     s.query()
     torch.cuda.synchronize()
-    log(f"bench: volume {W} warm-up epochs done")
+    log_fn(f"bench: volume {W} warm-up epochs done")
+    # the same state continued by a second handle, for the graph comparison below
+    state = (s.x.clone(), s.h.clone(), s.dual.clone()) if graph_check else None
+    per_epoch = []
+    calls0 = s.query()["prox_calls"]
     t1 = time.perf_counter()
-    for e in range(K):   # one epoch (about 1.6 s) per call, with a progress line
+    for e in range(K):
+        te = time.perf_counter()
+        c0 = s.query()["prox_calls"]
         s.epochs(1)
         torch.cuda.synchronize()
-        log(f"bench: volume epoch {e + 1}/{K} at {time.perf_counter() - t1:.2f} s")
+        per_epoch.append((time.perf_counter() - te, s.query()["prox_calls"] - c0))
+        log_fn(f"bench: volume epoch {e + 1}/{K}: {per_epoch[-1][0]:.3f} s, "
+               f"{per_epoch[-1][1]} prox calls")
     el = time.perf_counter() - t1
     st = s.query()
-    log(f"bench: volume {K} epochs in {el:.3f} s; prox calls {st['prox_calls']}")
+    rec = {"workload": w.name, "volume": f"{w.nz}x{w.ny}x{w.nx}", "angles": w.n_angles,
+           "bins": w.n_bins, "subsets": N, "p": w.p, "alpha": w.alpha, "fgp_inner": w.fgp_inner,
+           "tv": "3D isotropic", "noise": w.noise, "data_s": round(t_data, 2),
+           "epochs": K, "warmup": W, "s_per_epoch": round(el / K, 4),
+           "epochs_per_s": round(K / el, 4), "prox_calls": st["prox_calls"] - calls0,
+           "epoch_s_and_prox_calls": [[round(a, 4), c] for a, c in per_epoch], "plan": plan}
 
     def event_time(fn, reps=3):
         fn()
@@ -276,41 +306,128 @@ def bench_volume(args):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps * 1e-3
 
-    ysub = torch.empty(g.sino_shape(0), device=dev)
-    img = torch.empty_like(s.x)
-    dual = torch.zeros(g.dual_shape(), device=dev)
-    # achievable HBM rate for reference: a 1 GiB device-to-device copy (read + write bytes)
-    src_ = torch.ones(256 * 1024 * 1024, device=dev)
-    dst_ = torch.empty_like(src_)
-    t_copy = event_time(lambda: dst_.copy_(src_), reps=5)
-    copy_gbs = 2.0 * src_.numel() * 4 / t_copy / 1e9
-    del src_, dst_
-    t_fp = event_time(lambda: api.project(g, s.x, 0, out=ysub))
-    t_bp = event_time(lambda: api.backproject(g, ysub, 0, out=img))
-    t_tv = event_time(lambda: api.tv_prox(g, s.x, 1e-4, w.fgp_inner, dual=dual, out=img), reps=1)
+    if graph_check:
+        # epoch W + 1 eager (a fresh handle from the saved state) against the same epoch as a HIP
+        # graph (another handle from the same state): identical work, bit for bit the same x
+        xs_, hs_, ds_ = state
+        del s
+        times = {}
+        xs_out = {}
+        for mode in ("eager", "graph"):
+            h2 = api.Solver(g, b, api.SolverParams(n_epochs=1, k0=W * N, **prm),
+                            x=xs_.clone(), h=hs_.clone(), dual=ds_.clone())
+            torch.cuda.synchronize()
+            tg = time.perf_counter()
+            h2.epochs(1, graph=(mode == "graph"))
+            torch.cuda.synchronize()
+            times[mode] = time.perf_counter() - tg
+            xs_out[mode] = h2.x.clone()
+            del h2
+            log_fn(f"bench: volume epoch {W + 1} {mode}: {times[mode]:.3f} s")
+        rec["graph_vs_eager"] = {"epoch": W + 1, "eager_s": round(times["eager"], 4),
+                                 "graph_s": round(times["graph"], 4),
+                                 "graph_over_eager": round(times["graph"] / times["eager"], 4),
+                                 "bitwise_equal": bool(torch.equal(xs_out["eager"], xs_out["graph"]))}
+        del xs_out, state, xs_, hs_, ds_
+    else:
+        del s
+    torch.cuda.empty_cache()
+
+    # per-operator times: stored (tuned) plan against the automatic plan
     n = w.nx * w.ny * w.nz
     a = g.subset_size(0)
+    x = torch.rand(g.image_shape, device=dev)
+    ysub = torch.empty(g.sino_shape(0), device=dev)
+    img = torch.empty_like(x)
+    dual = torch.zeros(g.dual_shape(), device=dev)
+    copy_src = torch.ones(256 * 1024 * 1024, device=dev)
+    copy_dst = torch.empty_like(copy_src)
+    t_copy = event_time(lambda: copy_dst.copy_(copy_src), reps=5)
+    copy_gbs = 2.0 * copy_src.numel() * 4 / t_copy / 1e9
+    del copy_src, copy_dst
+    fgp_iters = 10
+
+    def ops(geom):
+        tp = event_time(lambda: api.project(geom, x, 0, out=ysub))
+        tb = event_time(lambda: api.backproject(geom, ysub, 0, out=img))
+        tf = event_time(lambda: api.tv_prox(geom, x, 1e-4, fgp_iters, dual=dual, out=img), reps=2)
+        return tp, tb, tf
+    t_fp, t_bp, t_tv = ops(g)
     steps_fp = a * w.n_bins * w.nz * max(w.nx, w.ny)
-    fgp_bytes = 40.0 * n * w.fgp_inner   # read v, p(3), p_prev(3); write p(3) per iteration
-    out = {
-        "metric": METRIC, "value": round(K / el, 4), "unit": "epochs/s", "n_gpus": 1, "steps": K,
-        "warmup": W, "ms_per_step": round(1e3 * el / K, 2), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "plan": plan,
-        "config": {"workload": w.name, "volume": f"{w.nz}x{w.ny}x{w.nx}", "angles": w.n_angles,
-                   "bins": w.n_bins, "subsets": w.n_subsets, "p": w.p, "alpha": w.alpha,
-                   "fgp_inner": w.fgp_inner, "tv": "3D isotropic", "noise": w.noise},
-        "kernels": {
-            "project_subset_ms": round(t_fp * 1e3, 3),
-            "project_subset_gsteps_per_s": round(steps_fp / t_fp / 1e9, 1),
-            "backproject_subset_ms": round(t_bp * 1e3, 3),
-            "tv_prox_50_ms": round(t_tv * 1e3, 3),
-            "tv_prox_algorithmic_gbs": round(fgp_bytes / t_tv / 1e9, 1),
-            "tv_prox_hbm_frac": round(fgp_bytes / t_tv / 1e9 / HBM_PEAK_GBS, 4),
-            "device_copy_gbs": round(copy_gbs, 1),
-            "tv_prox_frac_of_copy": round(fgp_bytes / t_tv / 1e9 / copy_gbs, 4),
-        },
-    }
+    fgp_bytes = 40.0 * n * fgp_iters   # per iteration: read v, p (3), p_prev (3); write p (3)
+    rec["kernels"] = {
+        "project_subset_ms": round(t_fp * 1e3, 3),
+        "project_subset_gsamples_per_s": round(steps_fp / t_fp / 1e9, 1),
+        "backproject_subset_ms": round(t_bp * 1e3, 3),
+        "fgp3d_iteration_ms": round(t_tv * 1e3 / fgp_iters, 3),
+        "fgp3d_algorithmic_gbs": round(fgp_bytes / t_tv / 1e9, 1),
+        "fgp3d_hbm_frac": round(fgp_bytes / t_tv / 1e9 / HBM_PEAK_GBS, 4),
+        "device_copy_gbs": round(copy_gbs, 1),
+        "fgp3d_frac_of_copy": round(fgp_bytes / t_tv / 1e9 / copy_gbs, 4)}
+    log_fn(f"bench: volume kernels {rec['kernels']}")
+    if plan_check:
+        gd = api.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=N, nz=w.nz, device=dev)
+        d_fp, d_bp, d_tv = ops(gd)
+        rec["tuned_vs_automatic_plan"] = {
+            "automatic_plan": gd.get_plan(),
+            "project_subset_ms": [round(t_fp * 1e3, 3), round(d_fp * 1e3, 3)],
+            "backproject_subset_ms": [round(t_bp * 1e3, 3), round(d_bp * 1e3, 3)],
+            "fgp3d_iteration_ms": [round(t_tv * 1e3 / fgp_iters, 3), round(d_tv * 1e3 / fgp_iters, 3)]}
+        log_fn(f"bench: volume tuned vs automatic {rec['tuned_vs_automatic_plan']}")
+        del gd
+    del x, ysub, img, dual
+    torch.cuda.empty_cache()
+    if oracle_ops:
+        rec["oracle_ops"] = oracle_volume_ops(w, log_fn)
+    return rec
+
+
+def oracle_volume_ops(w, log_fn, nz_proj=2, nz_tv=4):
+    """The FP64 oracle's time for one subset projection, one subset backprojection (2 slices of
+    the volume's geometry) and one 3D FGP iteration (4 slices), each extrapolated to the 256
+    slices, and an epoch estimated from them (labelled extrapolated)."""
+    import numpy as np
+    import oracle
+    rng = np.random.default_rng(0)
+    og = oracle.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=w.n_subsets, nz=nz_proj)
+    x = rng.random((nz_proj, w.ny, w.nx))
+    t = time.perf_counter()
+    y = oracle.project(og, x, 0)
+    t_fp = time.perf_counter() - t
+    t = time.perf_counter()
+    oracle.backproject(og, y, 0)
+    t_bp = time.perf_counter() - t
+    v = rng.random((nz_tv, w.ny, w.nx))
+    dual = np.zeros((3, nz_tv, w.ny, w.nx))
+    t = time.perf_counter()
+    oracle.tv_prox_fgp(v, 1e-2, 1, nonneg=True, dual=dual)
+    t_tv = time.perf_counter() - t
+    sp, st_ = w.nz / nz_proj, w.nz / nz_tv
+    fp, bp, tv = t_fp * sp, t_bp * sp, t_tv * st_
+    N = w.n_subsets
+    # an SVRG epoch: the snapshot's all-angle pair (N subsets' worth) plus N subset pairs, and
+    # p N prox calls of fgp_inner iterations on average
+    epoch = 2 * N * (fp + bp) + w.p * N * w.fgp_inner * tv
+    rec = {"threads": oracle.num_threads(),
+           "sample": f"subset projection and backprojection on {nz_proj} slices, one 3D FGP "
+                     f"iteration on {nz_tv} slices of the 1024^2 geometry (random inputs), "
+                     f"scaled to {w.nz} slices",
+           "project_subset_s_extrapolated": round(fp, 3),
+           "backproject_subset_s_extrapolated": round(bp, 3),
+           "fgp3d_iteration_s_extrapolated": round(tv, 3),
+           "epoch_s_extrapolated": round(epoch, 1),
+           "epochs_per_s_extrapolated": round(1.0 / epoch, 6)}
+    log_fn(f"bench: volume oracle ops {rec}")
+    return rec
+
+
+def bench_volume(args):
+    """--volume: the 256 x 1024^2 volume alone, one JSON line with its epochs per second."""
+    rec = volume_leg(args.steps, args.warmup, log)
+    out = {"metric": METRIC, "value": rec["epochs_per_s"], "unit": "epochs/s", "n_gpus": 1,
+           "steps": rec["epochs"], "warmup": rec["warmup"], "ms_per_step": round(1e3 * rec["s_per_epoch"], 2),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic", "config": {"workload": rec["workload"]}, "volume": rec}
     print(json.dumps(out), flush=True)
 
 
@@ -360,8 +477,9 @@ def bench_batch(dev, log_fn, n_slices=64, epochs=10):
 
 
 def bench_serve(args, dev, log_fn):
-    """A Poisson trace of mixed-size reconstructions served with continuous batching, against the
-    same trace served one request at a time."""
+    """A Poisson trace of mixed-size reconstructions, each solved to 1e-4 relative change (or
+    the epoch cap), served with continuous batching, against the same trace served one request
+    at a time."""
     from paper_2602_09527_amd import serve
     trace = serve.make_trace(args.serve_requests, args.serve_rate, seed=505)
     geoms = serve.GeometryCache(dev, power_iters=30)
@@ -374,10 +492,22 @@ def bench_serve(args, dev, log_fn):
     res2, wall2 = serve.serve_sequential(trace, cfg, bank, geoms)
     seq = serve.summarize(res2, wall2)
     log_fn(f"bench: serving (one at a time) {seq}")
+    rel = [r["last_rel_change"] for r in res]
     return {"trace": f"{args.serve_requests} requests, Poisson {args.serve_rate}/s, sides "
                      f"{{128..1024}}, angles {{90..1800}}, bins 1.5 N, p = {cfg.p}, "
-                     f"tol {cfg.tol}, cap {cfg.max_epochs} epochs",
-            "continuous_batching": batched, "one_at_a_time": seq}
+                     f"alpha = {cfg.alpha}, {cfg.fgp_inner} FGP iterations, stop at relative "
+                     f"change < {cfg.tol} or {cfg.max_epochs} epochs",
+            "continuous_batching": batched, "one_at_a_time": seq,
+            "converged": batched["converged"],
+            "relative_change_at_stop": {"min": min(rel), "median": float(sorted(rel)[len(rel) // 2]),
+                                        "max": max(rel)},
+            "arrival_span_s": round(trace[-1].arrival, 3),
+            # when the arrivals outpace the service (the last result comes well after the last
+            # arrival) the GPU is busy from the first arrival to the last result, and the
+            # measured throughput is the highest rate this mix can be sustained at
+            "sustainable_req_per_s": ({"continuous_batching": batched["throughput_req_s"],
+                                       "one_at_a_time": seq["throughput_req_s"]}
+                                      if min(wall, wall2) > 1.5 * trace[-1].arrival else None)}
 
 
 def calibrate_copy():
@@ -389,6 +519,94 @@ def calibrate_copy():
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"calibrate_copy_bytes_each_way": 4 * n, "launches": 3}), flush=True)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_one_thread(og, b, kw, threads, epochs=1):
+    """The same oracle solve on one thread (results do not depend on the thread count)."""
+    import oracle
+    oracle.set_num_threads(1)
+    try:
+        t = time.perf_counter()
+        oracle.proxskip_svrg(og, b, **{**kw, "n_epochs": epochs})
+        el = time.perf_counter() - t
+    finally:
+        oracle.set_num_threads(threads)
+    log(f"bench: oracle on 1 thread: {epochs} epoch(s) in {el:.1f} s")
+    return {"epochs": epochs, "epochs_per_s": round(epochs / el, 4), "seconds": round(el, 2)}
+
+
+def oracle_other_configs(threads):
+    """The oracle on the other fixed workloads: the full 30-epoch 128^2 solve, and the forward and
+    backward projection of two images of the 64-image autograd batch (extrapolated to 64)."""
+    import numpy as np
+    import oracle
+    from paper_2602_09527_amd import synth, workloads
+    out = {"threads": threads}
+    w = workloads.SMALL_2D
+    prob = synth.make_problem(w.nx, w.ny, w.n_angles, w.n_bins, seed=w.seed, noise=w.noise,
+                              with_phantom=False)
+    og = oracle.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=w.n_subsets)
+    t = time.perf_counter()
+    _, _, _, st, _ = oracle.proxskip_svrg(og, prob.b, gamma=1.0 / stored_L(w), p=w.p, alpha=w.alpha,
+                                          fgp_inner=w.fgp_inner, n_epochs=w.n_epochs,
+                                          nonneg=w.nonneg, seed=w.seed + 2)
+    el = time.perf_counter() - t
+    out[w.name] = {"epochs": w.n_epochs, "seconds": round(el, 2),
+                   "epochs_per_s": round(w.n_epochs / el, 3), "prox_calls": st["prox_calls"]}
+    wa = workloads.AUTOGRAD_BATCH
+    two = 2
+    oa = oracle.Geometry(wa.nx, wa.ny, wa.n_angles, wa.n_bins, nz=two)
+    xa = np.random.default_rng(0).random((two, wa.ny, wa.nx))
+    t = time.perf_counter()
+    ya = oracle.project(oa, xa, -1)
+    tf = time.perf_counter() - t
+    t = time.perf_counter()
+    oracle.backproject(oa, ya, -1)
+    tb = time.perf_counter() - t
+    out[wa.name] = {"sample": f"{two} images, extrapolated to {wa.nz}",
+                    "forward_images_per_s": round(two / tf, 2),
+                    "backward_images_per_s": round(two / tb, 2),
+                    "forward_s_per_batch_extrapolated": round(tf * wa.nz / two, 2),
+                    "backward_s_per_batch_extrapolated": round(tb * wa.nz / two, 2)}
+    log(f"bench: oracle on the other workloads {out}")
+    return out
+
+
+def solve_only(args):
+    """--solve WORKLOAD: the workload's ProxSkip-SVRG solve alone, --steps timed epochs after
+    --warmup, on its stored plan and stored step size (a short program for kernel traces)."""
+    import torch
+    from paper_2602_09527_amd import api, synth, workloads
+    w = workloads.ALL[args.solve]
+    prob = synth.make_problem(w.nx, w.ny, w.n_angles, w.n_bins, seed=w.seed, noise=w.noise,
+                              with_phantom=False)
+    g = api.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=w.n_subsets)
+    plan = api.autotune(g, reps=3, cache_path=PLANS_FILE, store=False)
+    b = torch.from_numpy(prob.b).to(device="cuda", dtype=torch.float32)
+    s = api.Solver(g, b, api.SolverParams(gamma=1.0 / stored_L(w), p=w.p, alpha=w.alpha,
+                                          fgp_inner=w.fgp_inner, n_epochs=args.warmup + args.steps,
+                                          nonneg=w.nonneg, seed=w.seed + 2))
+    s.epochs(args.warmup)
+    s.query()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    s.epochs(args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    st = s.query()
+    print(json.dumps({"workload": w.name, "epochs": args.steps, "epochs_per_s": round(args.steps / el, 2),
+                      "prox_calls": st["prox_calls"], "plan": plan}), flush=True)
 
 
 def main():
@@ -409,6 +627,9 @@ def main():
     if args.volume:
         bench_volume(args)
         return
+    if args.solve:
+        solve_only(args)
+        return
     from paper_2602_09527_amd import api, synth, workloads
 
     w = workloads.SINGLE_2D
@@ -423,9 +644,14 @@ def main():
     log(f"bench: synthetic data in {time.time() - t0:.1f} s")
     g = api.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=w.n_subsets, device=dev)
     b = torch.from_numpy(prob.b).to(device=dev, dtype=torch.float32)
-    L_gpu = api.lipschitz(g, 50)
-    gamma = 1.0 / L_gpu
-    log(f"bench: L (GPU power method) = {L_gpu:.6f}")
+    # gamma = 1/L with L from the oracle's FP64 power method, stored with the tests: the timed
+    # solve and its oracle parity check below use the identical double
+    L = stored_L(w)
+    if L is None:
+        L = api.lipschitz(g, 50)
+        log(f"bench: no stored L for {w.key}; GPU power method L = {L:.6f}")
+    gamma = 1.0 / L
+    log(f"bench: L = {L:.9f} (stored, oracle power method)")
     plan = api.autotune(g, reps=5, cache_path=PLANS_FILE, store=False)
     log(f"bench: launch plan {plan}")
 
@@ -590,6 +816,13 @@ def main():
     if not args.no_serve:
         out["serving"] = bench_serve(args, dev, log)
 
+    # ---- the 256 x 1024^2 volume: a bounded leg (1 warm-up + 2 timed epochs by default) ------
+    vol = None
+    if not args.no_volume:
+        torch.cuda.empty_cache()
+        vol = volume_leg(args.volume_epochs, 1, log, oracle_ops=not args.no_cpu_baseline)
+        torch.cuda.empty_cache()
+
     # ---- CPU oracle baseline on a bounded sample + parity of that sample -------------------
     if not args.no_cpu_baseline:
         import oracle
@@ -615,12 +848,19 @@ def main():
                                "cores": threads, "kind": "oracle",
                                "sample": f"{E} epochs of the same solve from x0 = 0 "
                                          f"(FP64, OpenMP over output elements); "
-                                         f"{cpu_wall:.1f} s wall, {cpu_proc:.1f} s CPU"}
+                                         f"{cpu_wall:.1f} s wall, {cpu_proc:.1f} s CPU",
+                               "cpu_model": cpu_model()}
         out["parity"] = {"epochs": E, "rel_l2_vs_oracle": rel, "bar": 1e-4,
-                         "prox_calls_gpu": sg["prox_calls"], "prox_calls_oracle": so["prox_calls"]}
+                         "prox_calls_gpu": sg["prox_calls"], "prox_calls_oracle": so["prox_calls"],
+                         "gamma_same_as_timed_solve": gamma_o == gamma}
         log(f"bench: oracle {E} epochs in {cpu_wall:.1f} s ({threads} threads); "
             f"GPU vs oracle rel L2 = {rel:.3e}")
-    print(json.dumps(out), flush=True)
+        if not args.no_oracle_extra:
+            out["cpu_baseline"]["one_thread"] = oracle_one_thread(og, prob.b, kw, threads)
+            out["oracle_timings"] = oracle_other_configs(threads)
+    if vol is not None:
+        out["volume"] = vol
+        print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

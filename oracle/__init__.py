@@ -79,6 +79,7 @@ def _load():
                                 C.c_int, _DN]),
         "orc_pdhg": (C.c_int, [G, _D, _D, _D, _D, C.c_double, C.c_int, C.c_int]),
         "orc_num_threads": (C.c_int, []),
+        "orc_set_num_threads": (None, [C.c_int]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -327,3 +328,8 @@ def pdhg(g: Geometry, b, *, alpha, n_iters, nonneg=True, x=None, y1=None, y2=Non
 
 def num_threads() -> int:
     return _load().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads for later oracle calls (results do not depend on it)."""
+    _load().orc_set_num_threads(int(n))

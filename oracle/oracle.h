@@ -179,8 +179,11 @@ int orc_fista(const orc_geom *g, const double *b, double *x, double *dual, doubl
 int orc_pdhg(const orc_geom *g, const double *b, double *x, double *y1, double *y2, double alpha,
              int nonneg, int n_iters);
 
-/* Threads the OpenMP runtime will use (for reporting). */
+/* Threads the OpenMP runtime will use (for reporting), and a new count for later calls (for
+ * timing; every result is independent of the thread count: each output element is summed by one
+ * thread in a fixed order). */
 int orc_num_threads(void);
+void orc_set_num_threads(int n);
 
 #ifdef __cplusplus
 }

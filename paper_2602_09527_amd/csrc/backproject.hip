@@ -111,6 +111,7 @@ struct BackItem {
     const int32_t *order;
     AngleTab<T> tab;
     int subset, nsub, na, nx, ny, nz, nbins, strip, stride, s_row, s_col, groups, passes, nrow;
+    int xcd;   // set on every item of a launch whose items all take all angles: XCD-ordered grid
 };
 
 template <typename T, int NP, int kStrip>
@@ -119,7 +120,10 @@ __global__ __launch_bounds__(kBlock) void k_backproject(WorkList<BackItem<T>> wl
     T *acc_all = reinterpret_cast<T *>(smem_raw);
     constexpr bool kFixed = std::is_same<T, float>::value;
     int local;
-    const BackItem<T> &it = wl.item[work_item(wl, local)];
+    // all-angle launches take their workgroups in XCD order (each XCD's L2 then fetches the rows
+    // of y of its own angle groups and slices only); subset launches keep the dispatch order,
+    // which measured faster for them
+    const BackItem<T> &it = wl.item[wl.item[0].xcd ? work_item_xcd(wl, local) : work_item(wl, local)];
     const T *__restrict__ y = it.y;
     T *__restrict__ part = it.part;
     const int32_t *__restrict__ order = it.order;
@@ -780,6 +784,14 @@ static int strip_key(int strip) { return strip == 8 || strip == 4 ? strip : 1; }
 static int np_key(int passes) { return passes >= 1 && passes <= 4 ? passes : 0; }
 
 // All calls of one dtype: scatter launches grouped by (passes, strip, waves), then the combines.
+// XCD order for a scatter launch whose items all take all angles (see k_backproject).
+template <typename T>
+static void mark_xcd_order(WorkList<BackItem<T>> &wl) {
+    bool all = true;
+    for (int k = 0; k < wl.count; ++k) all = all && wl.item[k].subset < 0;
+    for (int k = 0; k < wl.count; ++k) wl.item[k].xcd = all ? 1 : 0;
+}
+
 template <typename T>
 static ps_status backproject_many_t(const BackCall *calls, int n, hipStream_t st) {
     std::vector<BackItem<T>> items;
@@ -872,12 +884,16 @@ static ps_status backproject_many_t(const BackCall *calls, int n, hipStream_t st
             lb.add(items[i], static_cast<int>(blocks));
             lds = std::max(lds, plans[i].lds_bytes);
             if (lb.full()) {
+                mark_xcd_order(lb.wl);
                 PS_TRY(launch_bp_key<T>(np, sk, lb.wl, lb.blocks, waves, lds, st));
                 lb.clear();
                 lds = 0;
             }
         }
-        if (!lb.empty()) PS_TRY(launch_bp_key<T>(np, sk, lb.wl, lb.blocks, waves, lds, st));
+        if (!lb.empty()) {
+            mark_xcd_order(lb.wl);
+            PS_TRY(launch_bp_key<T>(np, sk, lb.wl, lb.blocks, waves, lds, st));
+        }
     }
     // combine + epilogue
     ListBuilder<CombineItem<T>> lb;

@@ -157,6 +157,31 @@ __device__ inline int work_item(const WorkList<Item> &wl, int &local) {
     return i;
 }
 
+// XCD-aware workgroup order.  The dispatcher hands workgroup b of a launch to XCD b mod 8 (round
+// robin over the chip's 8 XCDs, each with its own 4 MB L2).  xcd_order maps that dispatch index
+// to a logical index such that every XCD receives one contiguous range of logical workgroups, in
+// order: neighbouring tiles (halos), the strips of one angle group or one slab of slices then
+// share an L2 instead of each XCD fetching all of it.  A bijection of [0, nb): it moves work
+// between XCDs, it never changes what a workgroup computes.
+constexpr int kXcds = 8;
+__device__ inline int xcd_order(int b, int nb) {
+    const int x = b % kXcds, q = b / kXcds;
+    const int per = nb / kXcds, rem = nb % kXcds;
+    return x * per + min(x, rem) + q;
+}
+
+// work_item over the XCD-ordered grid (the items' ranges are logical workgroup ranges).
+template <typename Item>
+__device__ inline int work_item_xcd(const WorkList<Item> &wl, int &local) {
+    const int b = xcd_order(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
+    int i = 0;
+#pragma unroll
+    for (int q = 1; q < kMaxItems; ++q)
+        if (q < wl.count && b >= wl.first[q]) i = q;
+    local = b - wl.first[i];
+    return i;
+}
+
 // Host side: append items, launching a kernel whenever the list is full.
 template <typename Item>
 struct ListBuilder {
