@@ -48,27 +48,35 @@ ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 #   backprojector: position step, floor, weight, w y, y - w y, two accumulations        = 7
 OPS_PROJECT = 6
 OPS_BACKPROJECT = 7
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_backproject_2d-512-a720_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_2d-512-a720.txt")
 # launch plans tuned once on an MI355X (python -m paper_2602_09527_amd.tune_plans); a geometry
 # missing from the file is tuned on the spot
 PLANS_FILE = os.path.join(ROOT, "paper_2602_09527_amd", "plans_mi355x.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2602_09527_amd", "csrc", "backproject.hip")
 
 
-def measured_traffic():
-    """HBM bytes per launch of the backprojector (all angles) from the committed rocprofv3 counter
-    summary, or None once the kernel source differs from the one the counters were taken on."""
+def measured_traffic(kernel_class):
+    """HBM bytes per launch of a kernel class (e.g. backproject_subset) from the committed
+    rocprofv3 counter summary, or None when the summary has no line for it or the kernel's
+    source differs from the one the counters were taken on."""
     import hashlib
     try:
-        line = next(l for l in open(TRAFFIC_FILE) if l.startswith("traffic:"))
-    except (OSError, StopIteration):
+        lines = [l for l in open(TRAFFIC_FILE) if l.startswith("traffic:")]
+    except OSError:
         return None
-    kv = dict(tok.split("=", 1) for tok in line.split()[1:])
-    with open(KERNEL_SOURCE, "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != kv.get("source_sha256"):
+    for line in lines:
+        kv = dict(tok.split("=", 1) for tok in line.split()[1:])
+        if kv.get("class") != kernel_class:
+            continue
+        src = os.path.join(ROOT, "paper_2602_09527_amd", "csrc", kv.get("source", ""))
+        try:
+            with open(src, "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest() != kv.get("source_sha256"):
+                    return None
+        except OSError:
             return None
-    return (float(kv["fetch_kib"]) * float(kv["fetch_factor"]) +
-            float(kv["write_kib"]) * float(kv["write_factor"])) * 1024.0
+        return (float(kv["fetch_kib"]) * float(kv["fetch_factor"]) +
+                float(kv["write_kib"]) * float(kv["write_factor"])) * 1024.0
+    return None
 
 
 def log(*a):
@@ -218,9 +226,10 @@ def time_to_eps(api, torch, g, b, w, gamma, ref_iters, passes, alpha):
 
 
 def volume_ops():
-    """One subset projection, one subset backprojection and a 10-iteration 3D TV prox on the
-    256 x 1024^2 volume geometry with its stored plan and random inputs: a short program for
-    hardware counters (under counter collection the synthetic sinogram takes minutes)."""
+    """One subset projection, one subset backprojection, a 10-iteration 3D TV prox and one
+    all-angle projection and backprojection on the 256 x 1024^2 volume geometry with its stored
+    plan and random inputs: a short program for hardware counters (under counter collection the
+    synthetic sinogram takes minutes)."""
     import torch
     from paper_2602_09527_amd import api, workloads
     w = workloads.VOLUME_3D
@@ -239,6 +248,14 @@ def volume_ops():
     api.tv_prox(g, x, 1e-4, 10, dual=dual, out=torch.empty_like(x))
     torch.cuda.synchronize()
     log("bench: volume ops: 10-iteration prox done")
+    del dual, y
+    yf = torch.empty(g.sino_shape(-1), device="cuda")
+    api.project(g, x, -1, out=yf)
+    torch.cuda.synchronize()
+    log("bench: volume ops: all-angle projection done")
+    api.backproject(g, yf, -1, out=x)
+    torch.cuda.synchronize()
+    log("bench: volume ops: all-angle backprojection done")
 
 
 def volume_leg(epochs, warmup, log_fn, graph_check=True, plan_check=True, oracle_ops=True):
@@ -717,15 +734,74 @@ def main():
     }
     for k_, v in kern.items():
         log(f"bench: {k_}: " + " ".join(f"{kk}={vv}" for kk, vv in v.items()))
-    # k_backproject is the kernel with the most time per epoch (all-angle and subset launches);
-    # its all-angle launch is the one rated here.
-    dk = kern["backproject_full"]
-    traffic = measured_traffic()
-    roofline = {"kernel": "k_backproject (all 720 angles, 512^2)", "bound": "alu",
-                "achieved": dk["alu_tops"], "peak": round(ALU_PEAK_TOPS, 2), "unit": "Tops/s",
-                "frac": dk["alu_frac"], "traffic": round(traffic) if traffic else None,
-                "us_per_launch": dk["us"], "ops_per_sample": OPS_BACKPROJECT,
-                "samples_per_launch": samples_full}
+    # ---- per-kernel GPU time inside the solve: the library's HIP events around every launch of
+    # each class over E_t more epochs (a second pass: the events would perturb the timed one) ---
+    E_t = 20
+    s2 = api.Solver(g, b, params(W + E_t))
+    s2.epochs(W)
+    s2.query()
+    torch.cuda.synchronize()
+    classes = ("backproject_subset", "project_subset", "backproject_full", "project_full",
+               "backproject_combine", "project_reduce", "backproject_gather", "fgp2d")
+    with api.KernelTimer(classes) as kt:
+        t1 = time.perf_counter()
+        s2.epochs(E_t)
+        torch.cuda.synchronize()
+        el_t = time.perf_counter() - t1
+        per = {c: kt.result(c) for c in classes}
+    del s2
+    # algorithmic work per launch: lane operations of the ray steps for the projector and the
+    # backprojector (SURVEY's per-sample figures), none counted for the other classes
+    samples = {"backproject_subset": samples_sub, "project_subset": samples_sub,
+               "backproject_full": samples_full, "project_full": samples_full}
+    ops = {"backproject_subset": OPS_BACKPROJECT, "project_subset": OPS_PROJECT,
+           "backproject_full": OPS_BACKPROJECT, "project_full": OPS_PROJECT}
+    breakdown = {}
+    for c, (ms, nl) in per.items():
+        if nl == 0:
+            continue
+        r = {"launches_per_epoch": round(nl / E_t, 2), "us_per_launch": round(1e3 * ms / nl, 2),
+             "ms_per_epoch": round(ms / E_t, 4), "share_of_epoch": round(ms / (1e3 * el_t), 4)}
+        if c in samples:
+            r["alu_frac"] = round(ops[c] * samples[c] / (ms / nl * 1e-3) / 1e12 / ALU_PEAK_TOPS, 4)
+        breakdown[c] = r
+    log(f"bench: kernel time per epoch (library events, {E_t} epochs): {breakdown}")
+    # the dominant kernel: the class with the most GPU time per epoch, then its launch timed
+    # alone (library HIP events around back-to-back launches, dispatch overlapped as in the
+    # solve: the in-solve events above also count each launch's dispatch)
+    dom = max(breakdown, key=lambda c: breakdown[c]["ms_per_epoch"])
+    alone = {c: api.kernel_time(g, c, reps=200) for c in samples}
+    for c, us in alone.items():
+        if c in breakdown:
+            breakdown[c]["us_per_launch_alone"] = round(us, 2)
+            breakdown[c]["alu_frac_alone"] = round(ops[c] * samples[c] / (us * 1e-6) / 1e12 / ALU_PEAK_TOPS, 4)
+    log(f"bench: kernels alone (us per launch): {alone}")
+    t_dom = (alone[dom] if dom in alone else breakdown[dom]["us_per_launch"]) * 1e-6
+    names = {"backproject_subset": "k_backproject (scatter), one subset: 36 angles x 768 bins "
+                                   "over 512 rows",
+             "project_subset": "k_project, one subset: 36 angles x 768 bins over 512 rows",
+             "backproject_full": "k_backproject (scatter), all 720 angles x 768 bins over 512 rows",
+             "project_full": "k_project, all 720 angles x 768 bins over 512 rows"}
+    if dom in samples:
+        achieved = ops[dom] * samples[dom] / t_dom / 1e12
+        traffic = measured_traffic(dom)
+        roofline = {"kernel": names[dom], "bound": "alu", "achieved": round(achieved, 3),
+                    "peak": round(ALU_PEAK_TOPS, 2), "unit": "Tops/s",
+                    "frac": round(achieved / ALU_PEAK_TOPS, 4),
+                    "traffic": round(traffic) if traffic else None,
+                    "us_per_launch": round(t_dom * 1e6, 2), "ops_per_sample": ops[dom],
+                    "samples_per_launch": samples[dom], "launches_per_epoch":
+                    breakdown[dom]["launches_per_epoch"],
+                    "timing": "HIP events around 200 back-to-back launches of the kernel alone "
+                              "(kernel_time), median of three rounds; chosen as the kernel with "
+                              "the most GPU time per epoch inside the solve (HIP events around "
+                              "each launch over %d epochs)" % E_t}
+    else:
+        roofline = {"kernel": dom, "bound": None, "achieved": None, "peak": None, "unit": None,
+                    "frac": None, "traffic": None}
+    # the whole epoch: projector and backprojector lane operations over the epoch's wall time
+    n_sub_iters = w.n_subsets - 1
+    epoch_ops = (OPS_PROJECT + OPS_BACKPROJECT) * (n_sub_iters * samples_sub + samples_full)
 
     out = {
         "metric": METRIC, "value": round(eps, 3), "unit": "epochs/s", "n_gpus": 1, "steps": K,
@@ -735,6 +811,11 @@ def main():
                    "bins": w.n_bins, "subsets": w.n_subsets, "p": p, "alpha": w.alpha,
                    "fgp_inner": w.fgp_inner, "method": "ProxSkip-SVRG"},
         "roofline": roofline,
+        "epoch_alu_frac": {"value": round(epoch_ops / (el / K) / 1e12 / ALU_PEAK_TOPS, 4),
+                           "what": "lane operations of the projector and backprojector ray steps "
+                                   "in one epoch (19 subset pairs and the snapshot's all-angle "
+                                   "pair) over the epoch's wall time, against the VALU peak"},
+        "kernel_time_per_epoch": breakdown,
         "plan": plan,
         "projector_hbm_gbs": kern["project_full"]["algorithmic_gbs"],
         "kernels": kern,
@@ -860,7 +941,7 @@ def main():
             out["oracle_timings"] = oracle_other_configs(threads)
     if vol is not None:
         out["volume"] = vol
-        print(json.dumps(out), flush=True)
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -109,6 +109,11 @@ PS_API int32_t subset_size(const ps_geometry *geom, int32_t subset);
  *                  fgp_iters and the tile apply to a prox computed alone: the proxes of several
  *                  handles advanced together (solver_epochs / solver_steps over several
  *                  handles) share launches on the automatic tile and depth.
+ *   fgp3d_form     3D FGP launches: 1 = one inner iteration per launch (62 x 14 tiles); 2 or 3 =
+ *                  two per launch (7 values read and 6 written per voxel for two iterations
+ *                  instead of 20) on tiles of 8 waves x 2 rows or 4 waves x 4 rows (60 x 12
+ *                  outputs); 0 = automatic (2).  The form does not change results, not even their
+ *                  rounding.
  * "_full" applies to all-angle calls (subset = -1), "_subset" to single subsets. */
 typedef struct {
     int32_t proj_split_full, proj_split_subset;
@@ -119,6 +124,7 @@ typedef struct {
     int32_t bp_gather_rows;
     int32_t fgp3d_chunk;
     int32_t fgp_waves, fgp_rows;
+    int32_t fgp3d_form;
 } ps_plan;
 
 /* The plan in effect (automatic choices filled in) / replace the overrides.  set: fields out of
@@ -337,6 +343,43 @@ PS_API size_t pdhg_workspace_bytes(const ps_geometry *geom);
 PS_API ps_status pdhg_run(const ps_geometry *geom, const void *b, void *x, void *y1, void *y2,
                    double alpha, int32_t nonneg, int32_t n_iters, void *workspace,
                    size_t ws_bytes, void *stream);
+
+/* Measurement support (not part of the method): the GPU time of chosen classes of kernel launches
+ * inside later calls on any stream, from HIP events recorded on the launching stream right before
+ * and after each launch of a chosen class (the interval covers the kernel's execution and its
+ * dispatch).  A launch over a work list counts in the class of its first item.  Launches into a
+ * stream being captured as a graph are not timed; at most 16384 launches per class are.
+ * kernel_timer_start(mask): forget earlier timings and time the classes whose bit (1 << class)
+ * is set.  kernel_timer_read: synchronises the class's events and returns their summed time and
+ * count.  kernel_timer_stop: stop timing (what was timed can still be read).
+ * Errors: PS_EINVAL (unknown class), PS_EHIP. */
+typedef enum {
+    PS_KC_BACKPROJECT_SUBSET = 1,  /* scatter backprojector, subset launches                     */
+    PS_KC_BACKPROJECT_FULL = 2,    /* scatter backprojector, all-angle launches                  */
+    PS_KC_PROJECT_SUBSET = 3,      /* projector, subset launches                                 */
+    PS_KC_PROJECT_FULL = 4,        /* projector, all-angle launches                              */
+    PS_KC_BACKPROJECT_COMBINE = 5, /* the scatter's combine pass (partial images + epilogue)     */
+    PS_KC_PROJECT_REDUCE = 6,      /* the projector's split-ray sum                              */
+    PS_KC_BACKPROJECT_GATHER = 7,  /* pixel-driven backprojector                                 */
+    PS_KC_FGP2D = 8,               /* 2D FGP launches                                            */
+    PS_KC_FGP3D = 9                /* 3D FGP iteration launches                                  */
+} ps_kernel_class;
+PS_API ps_status kernel_timer_start(uint32_t class_mask);
+PS_API ps_status kernel_timer_read(int32_t kernel_class, double *total_ms, int32_t *launches);
+PS_API ps_status kernel_timer_stop(void);
+
+/* Measurement support: the average GPU time of one launch of one kernel class alone, with the
+ * geometry's plan on synthetic inputs: HIP events on `stream` around `reps` back-to-back launches,
+ * the median of three rounds (each launch's dispatch overlaps the previous launch, as inside a
+ * solve).  Classes: PS_KC_BACKPROJECT_SUBSET / _FULL (the scatter kernel without its combine
+ * pass; the plan must take the scatter for that call), PS_KC_BACKPROJECT_GATHER (subset 0; the
+ * plan must take the gather), PS_KC_PROJECT_SUBSET / _FULL (the projector kernel without the
+ * split-ray sum; subset launches read the two images x and xs, or one image where the solver
+ * keeps their difference, as the solver's do).  Subset launches use subset 0.  workspace: kernel_time_workspace_bytes(geom)
+ * bytes.  Synchronises `stream`.  Errors: PS_EINVAL, PS_EHIP. */
+PS_API size_t kernel_time_workspace_bytes(const ps_geometry *geom);
+PS_API ps_status kernel_time(const ps_geometry *geom, int32_t kernel_class, int32_t reps,
+                      void *workspace, size_t ws_bytes, void *stream, double *us_per_launch);
 
 /* Description of the last error on the calling thread ("" if none). */
 PS_API const char *last_error_message(void);

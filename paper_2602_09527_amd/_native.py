@@ -30,6 +30,8 @@ EXPORTS = (
     "solver_free", "sample_sequences", "sample_refresh_coins", "fista_workspace_bytes",
     "fista_run", "pdhg_workspace_bytes", "pdhg_run", "last_error_message",
     "proxskip_noalloc_max_bytes", "proxskip_svrg_run_noalloc",
+    "kernel_timer_start", "kernel_timer_read", "kernel_timer_stop", "kernel_time_workspace_bytes",
+    "kernel_time",
 )
 PS_EST_SVRG, PS_EST_LSVRG, PS_EST_SAGA = 0, 1, 2
 
@@ -49,7 +51,8 @@ class Plan(C.Structure):
                 ("bp_strip_full", C.c_int32), ("bp_strip_subset", C.c_int32),
                 ("fgp_iters", C.c_int32), ("bp_method_full", C.c_int32),
                 ("bp_method_subset", C.c_int32), ("bp_gather_rows", C.c_int32),
-                ("fgp3d_chunk", C.c_int32), ("fgp_waves", C.c_int32), ("fgp_rows", C.c_int32)]
+                ("fgp3d_chunk", C.c_int32), ("fgp_waves", C.c_int32), ("fgp_rows", C.c_int32),
+                ("fgp3d_form", C.c_int32)]
 
 
 class SolverParams(C.Structure):
@@ -123,6 +126,11 @@ def load():
         "pdhg_run": (st, [vp, vp, vp, vp, vp, d, i32, i32, vp, sz, vp]),
         "last_error_message": (C.c_char_p, []),
         "proxskip_noalloc_max_bytes": (sz, []),
+        "kernel_timer_start": (st, [C.c_uint32]),
+        "kernel_timer_read": (st, [i32, C.POINTER(d), C.POINTER(i32)]),
+        "kernel_timer_stop": (st, []),
+        "kernel_time_workspace_bytes": (sz, [vp]),
+        "kernel_time": (st, [vp, i32, i32, vp, sz, vp, C.POINTER(d)]),
         "proxskip_svrg_run_noalloc": (st, [vp, vp, vp, vp, vp, C.POINTER(SolverParams),
                                            C.POINTER(SolverStats), vp]),
     }

@@ -264,6 +264,55 @@ def solve_noalloc(g: Geometry, b: torch.Tensor, params: SolverParams, x=None, h=
     return x, h, dual, _stats(st)
 
 
+KERNEL_CLASSES = {"backproject_subset": 1, "backproject_full": 2, "project_subset": 3,
+                  "project_full": 4, "backproject_combine": 5, "project_reduce": 6,
+                  "backproject_gather": 7, "fgp2d": 8, "fgp3d": 9}
+
+
+class KernelTimer:
+    """GPU time of chosen kernel classes inside the calls made while it is active (HIP events
+    recorded by the library around each launch of those classes):
+
+        with api.KernelTimer(["backproject_subset"]) as kt:
+            solver.epochs(5)
+        ms, launches = kt.result("backproject_subset")
+    """
+
+    def __init__(self, classes):
+        self.lib = nat.load()
+        self.classes = list(classes)
+        self.mask = 0
+        for c in self.classes:
+            self.mask |= 1 << KERNEL_CLASSES[c]
+
+    def __enter__(self):
+        nat.check(self.lib.kernel_timer_start(self.mask), "kernel_timer_start")
+        return self
+
+    def __exit__(self, *exc):
+        nat.check(self.lib.kernel_timer_stop(), "kernel_timer_stop")
+        return False
+
+    def result(self, cls: str):
+        """(summed milliseconds, launches) of the class."""
+        ms, n = C.c_double(), C.c_int32()
+        nat.check(self.lib.kernel_timer_read(KERNEL_CLASSES[cls], C.byref(ms), C.byref(n)),
+                  "kernel_timer_read")
+        return ms.value, n.value
+
+
+def kernel_time(g: Geometry, cls: str, reps: int = 100) -> float:
+    """Average GPU time (microseconds) of one launch of one projector or backprojector kernel
+    class alone on this geometry (HIP events around `reps` back-to-back launches on the current
+    stream; see kernel_time in include/proxskip.h)."""
+    nbytes = g.lib.kernel_time_workspace_bytes(g.handle)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=g.device)
+    us = C.c_double()
+    nat.check(g.lib.kernel_time(g.handle, KERNEL_CLASSES[cls], int(reps), _ptr(ws), nbytes,
+                                _stream(g.device), C.byref(us)), "kernel_time")
+    return us.value
+
+
 class Solver:
     """Resumable ProxSkip-SVRG handle: owns its state tensors and workspace."""
 

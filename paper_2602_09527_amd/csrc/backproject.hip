@@ -116,7 +116,7 @@ struct BackItem {
 
 template <typename T, int NP, int kStrip>
 __global__ __launch_bounds__(kBlock) void k_backproject(WorkList<BackItem<T>> wl) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     T *acc_all = reinterpret_cast<T *>(smem_raw);
     constexpr bool kFixed = std::is_same<T, float>::value;
     int local;
@@ -152,7 +152,16 @@ __global__ __launch_bounds__(kBlock) void k_backproject(WorkList<BackItem<T>> wl
     const int e_lo = cls_lo + grp * per;
     const int e_hi = cls_lo + min(cls_cnt, (grp + 1) * per);
 
-    for (int e = threadIdx.x; e < nw * strip * stride; e += blockDim.x) acc_all[e] = T(0);
+    {
+        // zero the accumulator strips with 16-byte stores, then the few words past the last
+        // whole 16 bytes
+        const int total = nw * strip * stride;
+        const int n16 = total * static_cast<int>(sizeof(T)) / 16;
+        uint4 *a16 = reinterpret_cast<uint4 *>(acc_all);
+        for (int e = threadIdx.x; e < n16; e += blockDim.x) a16[e] = make_uint4(0u, 0u, 0u, 0u);
+        const int done = n16 * 16 / static_cast<int>(sizeof(T));
+        if (static_cast<int>(threadIdx.x) < total - done) acc_all[done + threadIdx.x] = T(0);
+    }
     // this workgroup's angles, staged once (the per-unit loads would otherwise wait on L2)
     // this workgroup's angles, staged kScatterAngles at a time (per-unit loads of the tables would
     // otherwise wait on L2 inside the deposit loop)
@@ -331,18 +340,31 @@ __global__ __launch_bounds__(kBlock) void k_backproject(WorkList<BackItem<T>> wl
 
     // sum the waves' strips (fixed order) and write this (class, group) partial image
     T *pz = part + (static_cast<size_t>(rowc ? 0 : 1) * groups + grp) * (plane * it.nz) + z * plane;
+    // (no integer division per element on full strips)
     if (rowc) {
+        for (int t = 0; t < nt; ++t) {
+            T *prow = pz + static_cast<size_t>(t_lo + t) * nx;
+            for (int j = threadIdx.x; j < ext; j += blockDim.x) {
+                T v = T(0);
+                for (int w = 0; w < nw; ++w) v += acc_all[(w * strip + t) * stride + j + 2];
+                prow[j] = v;
+            }
+        }
+    } else if (nt == kStrip) {
+        // nt adjacent lanes write the strip's nt adjacent columns of one image row (one 16- or
+        // 32-byte piece per row for the store); the row and column come from shifts
+        constexpr int sh = kStrip == 8 ? 3 : kStrip == 4 ? 2 : kStrip == 2 ? 1 : 0;
         for (int e = threadIdx.x; e < nt * ext; e += blockDim.x) {
-            const int t = e / ext, j = e - t * ext;
+            const int i = e >> sh, t = e & (kStrip - 1);
             T v = T(0);
-            for (int w = 0; w < nw; ++w) v += acc_all[(static_cast<size_t>(w) * strip + t) * stride + j + 2];
-            pz[static_cast<size_t>(t_lo + t) * nx + j] = v;
+            for (int w = 0; w < nw; ++w) v += acc_all[(w * strip + t) * stride + i + 2];
+            pz[static_cast<size_t>(i) * nx + t_lo + t] = v;
         }
     } else {
         for (int e = threadIdx.x; e < nt * ext; e += blockDim.x) {
             const int i = e / nt, t = e - i * nt;   // nt adjacent columns of one row
             T v = T(0);
-            for (int w = 0; w < nw; ++w) v += acc_all[(static_cast<size_t>(w) * strip + t) * stride + i + 2];
+            for (int w = 0; w < nw; ++w) v += acc_all[(w * strip + t) * stride + i + 2];
             pz[static_cast<size_t>(i) * nx + t_lo + t] = v;
         }
     }
@@ -730,8 +752,11 @@ __global__ __launch_bounds__(kBlock) void k_backproject_gather(WorkList<GatherIt
 template <typename T, int NP, int S>
 static ps_status launch_bp_list(const WorkList<BackItem<T>> &wl, int blocks, int waves, size_t lds,
                                 hipStream_t st) {
+    const int kc = wl.item[0].subset < 0 ? KC_BP_SCATTER_FULL : KC_BP_SCATTER_SUBSET;
+    timer_mark(kc, st, true);
     hipLaunchKernelGGL((k_backproject<T, NP, S>), dim3(blocks), dim3(kWave * waves), lds, st, wl);
     PS_LAUNCHED("k_backproject");
+    timer_mark(kc, st, false);
     return PS_OK;
 }
 
@@ -801,11 +826,13 @@ static ps_status backproject_many_t(const BackCall *calls, int n, hipStream_t st
     auto flush_gather = [&](int which) -> ps_status {
         ListBuilder<GatherItem<T>> &b = gl[which];
         if (b.empty()) return PS_OK;
+        timer_mark(KC_BP_GATHER, st, true);
         if (which == 0)
             hipLaunchKernelGGL((k_backproject_gather<T, 2>), dim3(b.blocks), dim3(kBlock), 0, st, b.wl);
         else
             hipLaunchKernelGGL((k_backproject_gather<T, 4>), dim3(b.blocks), dim3(kBlock), 0, st, b.wl);
         PS_LAUNCHED("k_backproject_gather");
+        timer_mark(KC_BP_GATHER, st, false);
         b.clear();
         return PS_OK;
     };
@@ -899,6 +926,7 @@ static ps_status backproject_many_t(const BackCall *calls, int n, hipStream_t st
     ListBuilder<CombineItem<T>> lb;
     for (size_t i = 0; i < items.size(); ++i) {
         const BackCall &bc = calls[call_of[i]];
+        if (bc.partials_only) continue;
         CombineItem<T> ci{};
         ci.part = items[i].part;
         ci.out = static_cast<T *>(bc.out);
@@ -909,14 +937,18 @@ static ps_status backproject_many_t(const BackCall *calls, int n, hipStream_t st
         ci.blocks = static_cast<int>(std::max<size_t>(1, std::min<size_t>((ci.n + kBlock - 1) / kBlock, 8192)));
         lb.add(ci, ci.blocks);
         if (lb.full()) {
+            timer_mark(KC_BP_COMBINE, st, true);
             hipLaunchKernelGGL((k_backproject_combine<T>), dim3(lb.blocks), dim3(kBlock), 0, st, lb.wl);
             PS_LAUNCHED("k_backproject_combine");
+            timer_mark(KC_BP_COMBINE, st, false);
             lb.clear();
         }
     }
     if (!lb.empty()) {
+        timer_mark(KC_BP_COMBINE, st, true);
         hipLaunchKernelGGL((k_backproject_combine<T>), dim3(lb.blocks), dim3(kBlock), 0, st, lb.wl);
         PS_LAUNCHED("k_backproject_combine");
+        timer_mark(KC_BP_COMBINE, st, false);
     }
     PS_TRY(flush_gather(0));
     return flush_gather(1);

@@ -453,6 +453,230 @@ __global__ __launch_bounds__(kBlock) void k_fgp3d_iter(Fgp3Args<T> a) {
     }
 }
 
+// Two whole 3D FGP iterations per launch.  From (pa, pb) = (p_{k-1}, p_{k-2}):
+//     r_k   = pa + c1 (pa - pb),    z_k   = P_C(v - tau D^T r_k),    p_k   = P_unit(r_k + step D z_k)
+//     r_k+1 = p_k + c2 (p_k - pa),  z_k+1 = P_C(v - tau D^T r_k+1),  p_k+1 = P_unit(r_k+1 + step D z_k+1)
+// writing p_k (pn1) and p_{k+1} (pn2): per voxel 7 values read and 6 written for two iterations
+// instead of 7 read and 3 written for each.  Every value is formed by the one-iteration kernel's
+// expressions, so a launch gives the bits of two one-iteration launches.
+// Tile: 64 lanes = columns and W waves of RW rows, with two halo columns and rows on each side
+// (60 x (W RW - 4) outputs): each iteration's D^T reaches one voxel back and its D one forward.
+// Marching up z, step s holds the loads of slice s and computes
+//     A  r_k(s)      B  z_k(s)      C  p_k(s-1)      D  r_k+1(s-1)      E  z_k+1(s-1)      F  p_k+1(s-2)
+// keeping slice s-1's r_k, z_k, pa, v and slice s-2's r_k+1, z_k+1 in registers; p_k(s-1) and
+// p_k+1(s-2) are written when they fall in the workgroup's chunk of slices [s_lo, s_hi).  The
+// steps run from s_lo - 1 to s_hi + 1 (r_k's z component at s_lo - 2 is loaded up front): values
+// at slices outside the chunk are halo and are never written.  Voxels outside the volume hold
+// zeros in every quantity, as the zero loads of the one-iteration kernel give it.
+constexpr int kF32X = kFgpEX - 4;   // output columns per tile
+
+template <typename T>
+struct Fgp3Args2 {
+    const T *v, *pa, *pb;
+    T *pn1, *pn2;
+    int nx, ny, nz, tiles_x, tiles_y, chunk;
+    T c1, c2, tau, step;
+    int nonneg;
+};
+
+template <typename T, int W, int RW>
+__global__ __launch_bounds__(W * kFgpEX) void k_fgp3d_iter2(Fgp3Args2<T> a) {
+    constexpr int kTY = W * RW - 4;   // output rows per tile
+    // two exchange slots per phase, alternating between the two phases of a step
+    __shared__ T xch[2][3][W][kFgpEX];
+    const int lane = threadIdx.x % kFgpEX;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x / kFgpEX));
+    const int b = blockIdx.x;
+    const int tx = b % a.tiles_x, ty = (b / a.tiles_x) % a.tiles_y, zc = b / (a.tiles_x * a.tiles_y);
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const size_t plane = static_cast<size_t>(nx) * ny, n = plane * nz;
+    const int gx = tx * kF32X - 2 + lane;                // lanes 0, 1, 62, 63: halo columns
+    const int gy0 = ty * kTY - 2 + wave * RW;            // row of this wave's first register row
+    const bool col_in = gx >= 0 && gx < nx;
+    const bool lane_out = lane >= 2 && lane < 2 + kF32X;
+    const int s_lo = zc * a.chunk, s_hi = min(nz, s_lo + a.chunk);
+    const T c1 = a.c1, c2 = a.c2, tau = a.tau, step = a.step;
+    const T *__restrict__ pa = a.pa;
+    const T *__restrict__ pb = a.pb;
+    const T *__restrict__ vp = a.v;
+    T *__restrict__ pn1 = a.pn1;
+    T *__restrict__ pn2 = a.pn2;
+
+    bool in[RW], row_out[RW];
+    // slice s-1: r_k (3), z_k, pa (3), v;  slice s-2: r_k+1 (3), z_k+1
+    T rkx[RW], rky[RW], rkz[RW], zk[RW], pax[RW], pay[RW], paz[RW], vv1[RW];
+    T r1x[RW], r1y[RW], r1z[RW], z1[RW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+        const int gy = gy0 + r;
+        in[r] = col_in && gy >= 0 && gy < ny;
+        row_out[r] = gy >= ty * kTY && gy < ty * kTY + kTY;
+        rkx[r] = rky[r] = rkz[r] = zk[r] = pax[r] = pay[r] = paz[r] = vv1[r] = T(0);
+        r1x[r] = r1y[r] = r1z[r] = z1[r] = T(0);
+    }
+    // r_k's z component at slice s_lo - 2 (all that z_k(s_lo - 1) needs of that slice)
+    if (s_lo >= 2) {
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            if (!in[r]) continue;
+            const size_t e = static_cast<size_t>(s_lo - 2) * plane + static_cast<size_t>(gy0 + r) * nx + gx;
+            const T pa_ = pa[e + 2 * n], pb_ = pb[e + 2 * n];
+            rkz[r] = fma(c1, pa_ - pb_, pa_);
+        }
+    }
+    // inputs of one slice, loaded one step ahead of their use
+    T lax[RW], lbx[RW], lay[RW], lby[RW], laz[RW], lbz[RW], lv[RW];
+    auto load_slice = [&](int s) {
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            lax[r] = lbx[r] = lay[r] = lby[r] = laz[r] = lbz[r] = lv[r] = T(0);
+            if (in[r] && s >= 0 && s < nz) {
+                const size_t e = static_cast<size_t>(s) * plane + static_cast<size_t>(gy0 + r) * nx + gx;
+                lax[r] = pa[e];
+                lbx[r] = pb[e];
+                lay[r] = pa[e + n];
+                lby[r] = pb[e + n];
+                laz[r] = pa[e + 2 * n];
+                lbz[r] = pb[e + 2 * n];
+                lv[r] = vp[e];
+            }
+        }
+    };
+    // unit-ball projection of the dual step at one voxel
+    auto dual_step = [&](T ux, T uy, T uz, T &ox, T &oy, T &oz) {
+        const T nrm = sqrt(ux * ux + uy * uy + uz * uz);
+        if (nrm > T(1)) {
+            ux /= nrm;
+            uy /= nrm;
+            uz /= nrm;
+        }
+        ox = ux;
+        oy = uy;
+        oz = uz;
+    };
+    load_slice(s_lo - 1);
+    for (int s = s_lo - 1; s <= s_hi + 1; ++s) {
+        const bool have0 = s >= 0 && s < nz;            // slice s
+        const bool have1 = s - 1 >= 0 && s - 1 < nz;    // slice s - 1
+        // A: r_k and v at slice s, then the next slice's loads go out
+        T ax[RW], ay[RW], az[RW], av[RW], sax[RW], say[RW], saz[RW];
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            ax[r] = fma(c1, lax[r] - lbx[r], lax[r]);
+            ay[r] = fma(c1, lay[r] - lby[r], lay[r]);
+            az[r] = fma(c1, laz[r] - lbz[r], laz[r]);
+            av[r] = lv[r];
+            sax[r] = lax[r];
+            say[r] = lay[r];
+            saz[r] = laz[r];
+        }
+        if (s <= s_hi) load_slice(s + 1);
+        // exchange 1: r_k,y(s) of the last row down, z_k(s-1) and z_k+1(s-2) of the first row up
+        const int ph = 0;
+        xch[ph][0][wave][lane] = ay[RW - 1];
+        xch[ph][1][wave][lane] = zk[0];
+        xch[ph][2][wave][lane] = z1[0];
+        __syncthreads();
+        const T ry_above = wave > 0 ? xch[ph][0][wave - 1][lane] : T(0);
+        const T zk_below = wave < W - 1 ? xch[ph][1][wave + 1][lane] : T(0);
+        const T z1_below = wave < W - 1 ? xch[ph][2][wave + 1][lane] : T(0);
+        // B: z_k at slice s
+        T zn[RW];
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            const int gy = gy0 + r;
+            const T rxl = lane_from_left(ax[r]);
+            const T ryu = r > 0 ? ay[r - 1] : ry_above;
+            const T rxh = gx < nx - 1 ? ax[r] : T(0);
+            const T ryh = gy < ny - 1 ? ay[r] : T(0);
+            const T rzh = s < nz - 1 ? az[r] : T(0);
+            T zv = av[r] - tau * (((rxl - rxh) + (ryu - ryh)) + (rkz[r] - rzh));
+            if (a.nonneg && zv < T(0)) zv = T(0);
+            zn[r] = (in[r] && have0) ? zv : T(0);
+        }
+        // C, D: p_k and r_k+1 at slice s - 1
+        T qx[RW], qy[RW], qz[RW];
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            const int gy = gy0 + r;
+            const T zr = lane_from_right(zk[r]);
+            const T zb = r < RW - 1 ? zk[r + 1] : zk_below;
+            const T dzx = gx < nx - 1 ? zr - zk[r] : T(0);
+            const T dzy = gy < ny - 1 ? zb - zk[r] : T(0);
+            const T dzz = s - 1 < nz - 1 ? zn[r] - zk[r] : T(0);
+            T px, py, pz;
+            dual_step(fma(step, dzx, rkx[r]), fma(step, dzy, rky[r]), fma(step, dzz, rkz[r]), px, py, pz);
+            const bool live = in[r] && have1;
+            px = live ? px : T(0);
+            py = live ? py : T(0);
+            pz = live ? pz : T(0);
+            if (live && lane_out && row_out[r] && s - 1 >= s_lo && s - 1 < s_hi) {
+                const size_t e = static_cast<size_t>(s - 1) * plane + static_cast<size_t>(gy) * nx + gx;
+                pn1[e] = px;
+                pn1[e + n] = py;
+                pn1[e + 2 * n] = pz;
+            }
+            qx[r] = fma(c2, px - pax[r], px);
+            qy[r] = fma(c2, py - pay[r], py);
+            qz[r] = fma(c2, pz - paz[r], pz);
+        }
+        // exchange 2: r_k+1,y(s-1) of the last row down
+        xch[1][0][wave][lane] = qy[RW - 1];
+        __syncthreads();
+        const T qy_above = wave > 0 ? xch[1][0][wave - 1][lane] : T(0);
+        // E: z_k+1 at slice s - 1
+        T z1n[RW];
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            const int gy = gy0 + r;
+            const T rxl = lane_from_left(qx[r]);
+            const T ryu = r > 0 ? qy[r - 1] : qy_above;
+            const T rxh = gx < nx - 1 ? qx[r] : T(0);
+            const T ryh = gy < ny - 1 ? qy[r] : T(0);
+            const T rzh = s - 1 < nz - 1 ? qz[r] : T(0);
+            T zv = vv1[r] - tau * (((rxl - rxh) + (ryu - ryh)) + (r1z[r] - rzh));
+            if (a.nonneg && zv < T(0)) zv = T(0);
+            z1n[r] = (in[r] && have1) ? zv : T(0);
+        }
+        // F: p_k+1 at slice s - 2
+        if (s - 2 >= s_lo && s - 2 < s_hi) {
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                const int gy = gy0 + r;
+                const T zr = lane_from_right(z1[r]);
+                const T zb = r < RW - 1 ? z1[r + 1] : z1_below;
+                const T dzx = gx < nx - 1 ? zr - z1[r] : T(0);
+                const T dzy = gy < ny - 1 ? zb - z1[r] : T(0);
+                const T dzz = s - 2 < nz - 1 ? z1n[r] - z1[r] : T(0);
+                T px, py, pz;
+                dual_step(fma(step, dzx, r1x[r]), fma(step, dzy, r1y[r]), fma(step, dzz, r1z[r]), px, py, pz);
+                if (in[r] && lane_out && row_out[r]) {
+                    const size_t e = static_cast<size_t>(s - 2) * plane + static_cast<size_t>(gy) * nx + gx;
+                    pn2[e] = px;
+                    pn2[e + n] = py;
+                    pn2[e + 2 * n] = pz;
+                }
+            }
+        }
+        // shift: slice s becomes s - 1, slice s - 1 becomes s - 2
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            r1x[r] = qx[r];
+            r1y[r] = qy[r];
+            r1z[r] = qz[r];
+            z1[r] = z1n[r];
+            rkx[r] = ax[r];
+            rky[r] = ay[r];
+            rkz[r] = az[r];
+            zk[r] = zn[r];
+            pax[r] = sax[r];
+            pay[r] = say[r];
+            paz[r] = saz[r];
+            vv1[r] = av[r];
+        }
+    }
+}
+
 // tau = 0: z = P_C(v) (and the ProxSkip outputs).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_prox_identity(const T *__restrict__ v, size_t n, int nonneg,
@@ -510,6 +734,18 @@ size_t fgp_workspace(const ps_geometry *g) {
 // taller tiles go deeper (at 512^2 a 16 x 4 tile at 10 or 12 per launch beats every tile at 8 by
 // 14%), which tuned plans choose.  Neither choice changes results.
 // A tile of height EY leaves EY - 2 (T + 1) interior rows, so T is capped at EY / 2 - 2.
+int fgp3d_form_of(const ps_geometry *g) {
+    const int f = g->plan.fgp3d_form;
+    return f >= 1 && f <= 3 ? f : 2;
+}
+
+// Slices per 3D workgroup: 4 for one iteration per launch (short chunks spread the accesses
+// over more of the volume), 16 for two (its z halo of three slices is paid once per chunk).
+int fgp3d_chunk_of(const ps_geometry *g) {
+    if (g->plan.fgp3d_chunk > 0) return g->plan.fgp3d_chunk;
+    return fgp3d_form_of(g) == 1 ? kF3Chunk : 16;
+}
+
 int fgp_max_iters_of(const ps_geometry *g) {
     return g->elem == sizeof(double) ? fgp_max_iters<double>() : fgp_max_iters<float>();
 }
@@ -651,7 +887,9 @@ static ps_status fgp2d_program(const FgpCall &c, bool shared, FgpProgram<T> &pro
 
 template <typename T, int W, int RW>
 static void launch_fgp2d_tile(const WorkList<FgpItem<T>> &wl, int blocks, hipStream_t st) {
+    timer_mark(KC_FGP2D, st, true);
     hipLaunchKernelGGL((k_fgp2d<T, W, RW>), dim3(blocks), dim3(W * kFgpEX), 0, st, wl);
+    timer_mark(KC_FGP2D, st, false);
 }
 
 static_assert(sizeof(WorkList<FgpItem<float>>) <= 4096 && sizeof(WorkList<FgpItem<double>>) <= 4096,
@@ -733,24 +971,73 @@ static ps_status fgp_single_t(const FgpCall &c, hipStream_t st) {
     fa.tau = tauT;
     fa.step = stepT;
     fa.nonneg = c.nonneg;
-    fa.chunk = g->plan.fgp3d_chunk > 0 ? g->plan.fgp3d_chunk : kF3Chunk;
+    fa.chunk = fgp3d_chunk_of(g);
     const long f3_blocks = static_cast<long>(fa.tiles_x) * fa.tiles_y * ((d.nz + fa.chunk - 1) / fa.chunk);
     if (f3_blocks > (1L << 30)) return fail(PS_EUNSUPPORTED, "3D TV grid too large");
     (void)mid;
     (void)zscratch;
-    for (int k = 1; k <= K; ++k) {
-        T *pn = rot[next];
-        if (pn == pa || pn == pb) pn = rot[(next + 1) % 3];
-        if (pn == pa || pn == pb) pn = rot[(next + 2) % 3];
-        fa.pa = pa;
-        fa.pb = pb;
-        fa.pn = pn;
-        fa.c = static_cast<T>(cs[k]);
-        hipLaunchKernelGGL((k_fgp3d_iter<T>), dim3(static_cast<unsigned>(f3_blocks)), dim3(kBlock), 0, st, fa);
-        PS_LAUNCHED("k_fgp3d_iter");
-        pb = pa;
-        pa = pn;
-        next = (next + 1) % 3;
+    (void)rot;
+    (void)next;
+    // launch form: 1 = one iteration per launch; 2, 3 = two per launch on 8 x 2 or 4 x 4 tiles
+    const int form = fgp3d_form_of(g);
+    Fgp3Args2<T> fb{};
+    fb.v = vin;
+    fb.nx = d.nx;
+    fb.ny = d.ny;
+    fb.nz = d.nz;
+    fb.tau = tauT;
+    fb.step = stepT;
+    fb.nonneg = c.nonneg;
+    fb.chunk = fa.chunk;
+    const int ty2 = form == 2 ? 8 * 2 - 4 : 4 * 4 - 4;
+    fb.tiles_x = (d.nx + kF32X - 1) / kF32X;
+    fb.tiles_y = (d.ny + ty2 - 1) / ty2;
+    const long f32_blocks = static_cast<long>(fb.tiles_x) * fb.tiles_y * ((d.nz + fb.chunk - 1) / fb.chunk);
+    if (f32_blocks > (1L << 30)) return fail(PS_EUNSUPPORTED, "3D TV grid too large");
+    // dual buffers: any of the four workspace buffers that the launch does not read; the last
+    // launch writes the caller's dual directly when it does not read it
+    T *pool[4] = {buf[0], buf[1], buf[2], buf[3]};
+    auto pick = [&](const T *x1, const T *x2, const T *x3) -> T * {
+        for (T *q : pool)
+            if (q != x1 && q != x2 && q != x3) return q;
+        return nullptr;
+    };
+    for (int k = 1; k <= K;) {
+        const bool last = [&] { return form == 1 ? k == K : k + 1 >= K; }();
+        const bool direct = last && dual && dual != pa && dual != pb;
+        if (form != 1 && k + 1 <= K) {
+            T *p1 = pick(pa, pb, nullptr);
+            T *p2 = direct ? dual : pick(pa, pb, p1);
+            fb.pa = pa;
+            fb.pb = pb;
+            fb.pn1 = p1;
+            fb.pn2 = p2;
+            fb.c1 = static_cast<T>(cs[k]);
+            fb.c2 = static_cast<T>(cs[k + 1]);
+            timer_mark(KC_FGP3D, st, true);
+            if (form == 2)
+                hipLaunchKernelGGL((k_fgp3d_iter2<T, 8, 2>), dim3(static_cast<unsigned>(f32_blocks)), dim3(8 * kFgpEX), 0, st, fb);
+            else
+                hipLaunchKernelGGL((k_fgp3d_iter2<T, 4, 4>), dim3(static_cast<unsigned>(f32_blocks)), dim3(4 * kFgpEX), 0, st, fb);
+            PS_LAUNCHED("k_fgp3d_iter2");
+            timer_mark(KC_FGP3D, st, false);
+            pb = p1;
+            pa = p2;
+            k += 2;
+        } else {
+            T *pn = direct ? dual : pick(pa, pb, nullptr);
+            fa.pa = pa;
+            fa.pb = pb;
+            fa.pn = pn;
+            fa.c = static_cast<T>(cs[k]);
+            timer_mark(KC_FGP3D, st, true);
+            hipLaunchKernelGGL((k_fgp3d_iter<T>), dim3(static_cast<unsigned>(f3_blocks)), dim3(kBlock), 0, st, fa);
+            PS_LAUNCHED("k_fgp3d_iter");
+            timer_mark(KC_FGP3D, st, false);
+            pb = pa;
+            pa = pn;
+            k += 1;
+        }
     }
     // z = P_C(v - tau D^T p_K); the final dual p_K sits in `pa`
     FgpFinal<T> f = fin;
@@ -758,7 +1045,7 @@ static ps_status fgp_single_t(const FgpCall &c, hipStream_t st) {
     hipLaunchKernelGGL((k_fgp3d_primal<T>), dim3(gr), dim3(kBlock), 0, st, vin, pa, pa, T(0), d.nx,
                        d.ny, d.nz, tauT, c.nonneg, zscratch, f);
     PS_LAUNCHED("k_fgp3d_primal(final)");
-    if (dual && K > 0) {
+    if (dual && K > 0 && pa != dual) {
         hipLaunchKernelGGL((k_copy<T>), dim3(grid_for(dn)), dim3(kBlock), 0, st, dual, pa, dn);
         PS_LAUNCHED("k_copy");
     }

@@ -182,6 +182,15 @@ __device__ inline int work_item_xcd(const WorkList<Item> &wl, int &local) {
     return i;
 }
 
+// Measurement support (timer.hip): classes of kernel launches whose GPU time kernel_timer_start
+// asks for; launch sites mark the launch of their class before and after it.  A launch of a list
+// counts in the class of its first item.
+enum KernelClass {
+    KC_BP_SCATTER_SUBSET = 1, KC_BP_SCATTER_FULL = 2, KC_PROJECT_SUBSET = 3, KC_PROJECT_FULL = 4,
+    KC_BP_COMBINE = 5, KC_PROJECT_REDUCE = 6, KC_BP_GATHER = 7, KC_FGP2D = 8, KC_FGP3D = 9
+};
+void timer_mark(int kernel_class, hipStream_t st, bool begin);
+
 // Host side: append items, launching a kernel whenever the list is full.
 template <typename Item>
 struct ListBuilder {
@@ -217,6 +226,7 @@ struct ProjCall {
     void *y, *ws;
     size_t ws_bytes;
     const void *sig = nullptr;   // PDHG dual step: y = (y + sig (A x - b)) / (1 + sig), per ray
+    bool first_pass_only = false;   // skip the split-ray sum (kernel timing: the partials stay)
 };
 ps_status launch_project_many(const ProjCall *calls, int n, hipStream_t st);
 ps_status launch_project(const ps_geometry *g, int subset, const void *x, const void *xs,
@@ -265,6 +275,7 @@ struct BackCall {
     UpdateArgs upd;
     void *ws;
     size_t ws_bytes;
+    bool partials_only = false;     // scatter: skip the combine pass (kernel timing)
 };
 ps_status launch_backproject_many(const BackCall *calls, int n, hipStream_t st);
 ps_status launch_backproject(const ps_geometry *g, int subset, const void *y, void *out, int mode,
@@ -278,6 +289,11 @@ int fgp_iters_per_launch(const ps_geometry *g);
 int fgp_max_iters_of(const ps_geometry *g);
 bool fgp_tile_ok(int waves, int rows);                 // a built 2D FGP tile shape
 void fgp_tile_of(const ps_geometry *g, int *waves, int *rows);   // the shape in effect
+int fgp3d_form_of(const ps_geometry *g);                          // 3D launch form in effect
+int fgp3d_chunk_of(const ps_geometry *g);                         // 3D z chunk in effect
+// The SVRG solver's subset projections read one image (the kept difference x - xs) once x and xs
+// together outgrow an XCD's L2, else the two images x and xs (solver.hip).
+bool solver_reads_one_image(const ps_geometry *g);
 // Finalise modes: write z (FGP_Z) or the ProxSkip update x = z, h = hscale (z - v) (FGP_PROXSKIP).
 struct FgpOut {
     void *z;        // FGP_Z: output image (may alias v)

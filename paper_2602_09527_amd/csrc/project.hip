@@ -342,10 +342,13 @@ __global__ __launch_bounds__(kBlock) void k_project_reduce(WorkList<ReduceItem<T
     const size_t total = static_cast<size_t>(it.nz) * na * nbins;
     for (size_t e = local * static_cast<size_t>(kBlock) + threadIdx.x; e < total;
          e += static_cast<size_t>(it.blocks) * kBlock) {
-        const int u = static_cast<int>(e % nbins);
-        const size_t zl = e / nbins;
-        const int l = static_cast<int>(zl % na);
-        const int z = static_cast<int>(zl / na);
+        // (ray, angle, slice) of element e: 32-bit divisions (every sinogram here has fewer than
+        // 2^32 elements; a 64-bit division is a long software sequence on this chip)
+        const uint32_t e32 = static_cast<uint32_t>(e);
+        const uint32_t zl = e32 / static_cast<uint32_t>(nbins);
+        const int u = static_cast<int>(e32 - zl * static_cast<uint32_t>(nbins));
+        const int z = static_cast<int>(zl / static_cast<uint32_t>(na));
+        const int l = static_cast<int>(zl - static_cast<uint32_t>(z) * static_cast<uint32_t>(na));
         const int k = it.subset < 0 ? l : it.subset + l * it.nsub;
         // fixed order over the split partials; a batch's 8 loads are unconditional (clamped to
         // the last partial) so that they are all in flight before the first add
@@ -370,8 +373,11 @@ __global__ __launch_bounds__(kBlock) void k_project_reduce(WorkList<ReduceItem<T
 template <typename T, int R>
 static ps_status launch_proj_list(const WorkList<ProjItem<T>> &wl, int blocks, size_t lds,
                                   hipStream_t st) {
+    const int kc = wl.item[0].subset < 0 ? KC_PROJECT_FULL : KC_PROJECT_SUBSET;
+    timer_mark(kc, st, true);
     hipLaunchKernelGGL((k_project<T, R>), dim3(blocks), dim3(kBlock), lds, st, wl);
     PS_LAUNCHED("k_project");
+    timer_mark(kc, st, false);
     return PS_OK;
 }
 
@@ -396,6 +402,7 @@ template <typename T>
 static ps_status project_many_t(const ProjCall *calls, int n, hipStream_t st) {
     std::vector<ProjItem<T>> items;
     std::vector<ProjPlan> plans;
+    std::vector<bool> reduce;   // the item's split-ray sum runs
     items.reserve(n);
     plans.reserve(n);
     for (int c = 0; c < n; ++c) {
@@ -437,6 +444,7 @@ static ps_status project_many_t(const ProjCall *calls, int n, hipStream_t st) {
         it.vec = (d.nx % 4 == 0 && aligned && sizeof(T) == 4) ? 1 : 0;
         items.push_back(it);
         plans.push_back(p);
+        reduce.push_back(!pc.first_pass_only);
     }
     // projector: one list per rays-per-thread value, flushed every kMaxItems items
     for (int rpt = 1; rpt <= 8; ++rpt) {
@@ -459,7 +467,7 @@ static ps_status project_many_t(const ProjCall *calls, int n, hipStream_t st) {
     // reductions of the split items
     ListBuilder<ReduceItem<T>> lb;
     for (size_t i = 0; i < items.size(); ++i) {
-        if (plans[i].split <= 1) continue;
+        if (plans[i].split <= 1 || !reduce[i]) continue;
         const ProjItem<T> &pi = items[i];
         ReduceItem<T> r{};
         r.part = pi.part;
@@ -475,17 +483,23 @@ static ps_status project_many_t(const ProjCall *calls, int n, hipStream_t st) {
         r.split = pi.split;
         r.n_angles = pi.n_angles;
         const size_t total = static_cast<size_t>(pi.nz) * pi.na * pi.nbins;
+        if (total >= (static_cast<size_t>(1) << 32))
+            return fail(PS_EUNSUPPORTED, "a split projection of %zu rays (at most 2^32 - 1)", total);
         r.blocks = static_cast<int>(std::min<size_t>((total + kBlock - 1) / kBlock, 65535));
         lb.add(r, r.blocks);
         if (lb.full()) {
+            timer_mark(KC_PROJECT_REDUCE, st, true);
             hipLaunchKernelGGL((k_project_reduce<T>), dim3(lb.blocks), dim3(kBlock), 0, st, lb.wl);
             PS_LAUNCHED("k_project_reduce");
+            timer_mark(KC_PROJECT_REDUCE, st, false);
             lb.clear();
         }
     }
     if (!lb.empty()) {
+        timer_mark(KC_PROJECT_REDUCE, st, true);
         hipLaunchKernelGGL((k_project_reduce<T>), dim3(lb.blocks), dim3(kBlock), 0, st, lb.wl);
         PS_LAUNCHED("k_project_reduce");
+        timer_mark(KC_PROJECT_REDUCE, st, false);
     }
     return PS_OK;
 }

@@ -171,10 +171,18 @@ struct Layout {
 // (the backprojector epilogue, or k_diff after a prox), with the projector's own subtraction, so
 // the results are bit for bit the same either way.
 static bool keeps_difference(const ps_geometry *g, int estimator) {
+    return estimator != PS_EST_SAGA && solver_reads_one_image(g);
+}
+
+}  // namespace ps
+
+bool ps::solver_reads_one_image(const ps_geometry *g) {
     const auto &d = g->desc;
     const size_t n = static_cast<size_t>(d.nx) * d.ny * d.nz;
-    return estimator != PS_EST_SAGA && 2 * n * g->elem > (static_cast<size_t>(4) << 20);
+    return 2 * n * g->elem > (static_cast<size_t>(4) << 20);
 }
+
+namespace ps {
 
 static Layout layout(const ps_geometry *g, int n_epochs, int estimator) {
     const auto &d = g->desc;

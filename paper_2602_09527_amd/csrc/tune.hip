@@ -7,6 +7,7 @@
 // computed; split and grouping change the order of floating-point sums.
 #include <algorithm>
 #include <array>
+#include <functional>
 #include <utility>
 #include <vector>
 
@@ -136,8 +137,9 @@ extern "C" ps_status geometry_get_plan(const ps_geometry *g, ps_plan *out) {
     out->bp_method_full = back_method(g, -1);
     out->bp_method_subset = back_method(g, 0);
     out->bp_gather_rows = gather_rows(g, 0);
-    out->fgp3d_chunk = g->plan.fgp3d_chunk > 0 ? g->plan.fgp3d_chunk : 4;
+    out->fgp3d_chunk = fgp3d_chunk_of(g);
     fgp_tile_of(g, &out->fgp_waves, &out->fgp_rows);
+    out->fgp3d_form = fgp3d_form_of(g);
     return PS_OK;
 }
 
@@ -160,6 +162,7 @@ extern "C" ps_status geometry_set_plan(ps_geometry *g, const ps_plan *p) {
     if (p->bp_gather_rows != 0 && p->bp_gather_rows != 2 && p->bp_gather_rows != 4)
         return fail(PS_EINVAL, "bp_gather_rows must be 0, 2 or 4");
     if (p->fgp3d_chunk < 0 || p->fgp3d_chunk > 256) return fail(PS_EINVAL, "fgp3d_chunk must be in [0, 256]");
+    if (p->fgp3d_form < 0 || p->fgp3d_form > 3) return fail(PS_EINVAL, "fgp3d_form must be in [0, 3]");
     if (!(p->fgp_waves == 0 && p->fgp_rows == 0) && !fgp_tile_ok(p->fgp_waves, p->fgp_rows))
         return fail(PS_EINVAL, "FGP tile %d x %d: waves x rows must be 4x4, 4x8, 8x2, 8x4, 8x8, 16x2, 16x4 or 0x0",
                     p->fgp_waves, p->fgp_rows);
@@ -344,14 +347,23 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
         best.fgp_waves = pick_w;
         best.fgp_rows = pick_r;
     }
-    // 3D FGP: slices per workgroup (10 inner iterations per timed call)
+    // 3D FGP: launch form and slices per workgroup (10 inner iterations per timed call); the
+    // automatic (two iterations per launch on 8 x 2 tiles, chunks of 16) is timed first
     if (g->tv_dims == 3) {
         PS_TRY(fill(g, w + L.dual, 3 * n, st));
         float best_ms = 0.f;
-        int pick = 0;
-        for (int ch : {4, 6, 8, 2, 16}) {
+        int pick_ch = 0, pick_form = 0;
+        bool auto_best = true;
+        std::vector<std::array<int, 2>> cands{{2, 16}};
+        for (int form : {2, 3})
+            for (int ch : {8, 32, 4, 16})
+                if (!(form == 2 && ch == 16)) cands.push_back({form, ch});
+        for (int ch : {4, 8, 2, 16}) cands.push_back({1, ch});
+        for (const auto &fc : cands) {
+            const int form = fc[0], ch = fc[1];
             ps_plan trial = best;
             trial.fgp3d_chunk = ch;
+            trial.fgp3d_form = form;
             g->plan = trial;
             FgpOut o{};
             o.z = w + L.img;
@@ -359,14 +371,101 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
             PS_TRY(restore_on_error(time_calls([&] {
                 return launch_fgp(g, w + L.x, w + L.dual, 1e-3, 10, 1, o, w + L.fws, L.fws_bytes, st);
             }, reps, st, tm, &ms)));
-            if (pick == 0 || ms < best_ms * (pick == 4 ? kMinGain : 1.0f)) {
+            if (pick_ch == 0 || ms < best_ms * (auto_best ? kMinGain : 1.0f)) {
                 best_ms = ms;
-                pick = ch;
+                auto_best = pick_ch == 0;
+                pick_ch = ch;
+                pick_form = form;
             }
         }
-        best.fgp3d_chunk = pick;
+        best.fgp3d_chunk = pick_ch;
+        best.fgp3d_form = pick_form;
     }
     g->plan = best;
     if (out) PS_TRY(geometry_get_plan(g, out));
+    return PS_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Measurement support: one kernel class timed alone on synthetic inputs, `reps` back-to-back
+// launches between two HIP events (median of three rounds), with the geometry's plan.
+// ---------------------------------------------------------------------------------------------
+namespace ps {
+
+struct KtLayout {
+    size_t x, y, img, pws, bws, total, pws_bytes, bws_bytes;
+};
+
+static KtLayout kt_layout(const ps_geometry *g) {
+    const auto &d = g->desc;
+    const size_t n = n_image(g);
+    const size_t m = static_cast<size_t>(d.nz) * d.n_angles * d.n_bins;
+    KtLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes); return o; };
+    L.x = take(n * g->elem);
+    L.y = take(m * g->elem);
+    L.img = take(n * g->elem);
+    L.pws_bytes = std::max(proj_workspace(g, d.n_angles), proj_workspace(g, max_subset_count(g)));
+    L.pws = take(L.pws_bytes);
+    L.bws_bytes = std::max(back_workspace(g, -1), back_workspace(g, 0));
+    L.bws = take(L.bws_bytes);
+    L.total = off;
+    return L;
+}
+
+}  // namespace ps
+
+extern "C" size_t kernel_time_workspace_bytes(const ps_geometry *g) { return g ? kt_layout(g).total : 0; }
+
+extern "C" ps_status kernel_time(const ps_geometry *g, int32_t kernel_class, int32_t reps,
+                                 void *workspace, size_t ws_bytes, void *stream, double *us_per_launch) {
+    clear_error();
+    PS_TRY(check_ready(g));
+    PS_TRY(check_ptr(workspace, "workspace", kAlign));
+    if (!us_per_launch) return fail(PS_EINVAL, "us_per_launch is null");
+    if (reps < 1) return fail(PS_EINVAL, "reps must be >= 1");
+    const KtLayout L = kt_layout(g);
+    if (ws_bytes < L.total)
+        return fail(PS_EINVAL, "kernel_time workspace: %zu bytes given, %zu needed", ws_bytes, L.total);
+    const int subset = (kernel_class == KC_BP_SCATTER_FULL || kernel_class == KC_PROJECT_FULL) ? -1 : 0;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    unsigned char *w = static_cast<unsigned char *>(workspace);
+    std::function<ps_status()> fn;
+    if (kernel_class == KC_BP_SCATTER_SUBSET || kernel_class == KC_BP_SCATTER_FULL ||
+        kernel_class == KC_BP_GATHER) {
+        const bool gather = back_method(g, subset) == BP_GATHER;
+        if (gather != (kernel_class == KC_BP_GATHER))
+            return fail(PS_EINVAL, "kernel class %d: the plan backprojects %s with the %s", kernel_class,
+                        subset < 0 ? "all angles" : "subsets", gather ? "gather" : "scatter");
+        BackCall c{};
+        c.g = g;
+        c.subset = subset;
+        c.y = w + L.y;
+        c.out = w + L.img;
+        c.mode = BP_OVERWRITE;
+        c.ws = w + L.bws;
+        c.ws_bytes = L.bws_bytes;
+        c.partials_only = !gather;   // the scatter kernel alone, without its combine pass
+        fn = [=] { return launch_backproject_many(&c, 1, st); };
+    } else if (kernel_class == KC_PROJECT_SUBSET || kernel_class == KC_PROJECT_FULL) {
+        // subset launches read what the solver's do: x - xs, or the one kept difference image
+        const bool two = subset >= 0 && !solver_reads_one_image(g);
+        ProjCall c{g, subset, w + L.x, two ? w + L.img : nullptr, nullptr, w + L.y, w + L.pws, L.pws_bytes};
+        c.first_pass_only = true;    // the projector kernel alone, without the split-ray sum
+        fn = [=] { return launch_project_many(&c, 1, st); };
+    } else {
+        return fail(PS_EINVAL, "kernel_time supports the projector and backprojector classes, not %d",
+                    kernel_class);
+    }
+    PS_TRY(fill(g, w + L.x, n_image(g), st));
+    PS_TRY(fill(g, w + L.img, n_image(g), st));
+    PS_TRY(fill(g, w + L.y, static_cast<size_t>(g->desc.nz) * g->desc.n_angles * g->desc.n_bins, st));
+    Timer tm;
+    PS_HIP(hipEventCreate(&tm.e0));
+    PS_HIP(hipEventCreate(&tm.e1));
+    float ms = 0.f;
+    PS_TRY(time_calls(fn, reps, st, tm, &ms));
+    *us_per_launch = 1e3 * static_cast<double>(ms);
     return PS_OK;
 }

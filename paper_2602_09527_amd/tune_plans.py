@@ -1,6 +1,6 @@
 """Tune the launch plans of the benchmarked and served geometries on this GPU and store them.
 
-    python -m paper_2602_09527_amd.tune_plans [--out PATH] [--reps R]
+    python -m paper_2602_09527_amd.tune_plans [--out PATH] [--reps R] [--only SUBSTRING ...]
 
 Writes a JSON object keyed by Geometry.key (default: plans_mi355x.json beside this file), which
 bench.py and the serving loop load instead of re-tuning, so that every run -- including the ones
@@ -36,16 +36,25 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_PATH)
     ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--only", nargs="*", default=None,
+                    help="re-tune only the geometries whose key contains one of these strings and "
+                         "keep the other stored plans")
     args = ap.parse_args(argv)
     import torch  # noqa: F401
     from . import api
     plans = {}
+    if args.only is not None and os.path.exists(args.out):
+        with open(args.out) as f:
+            plans = json.load(f)
+    done = set()
     for s in shapes():
         g = api.Geometry(s["nx"], s["ny"], s["n_angles"], s["n_bins"], n_subsets=s["n_subsets"],
                          nz=s["nz"])
-        if g.key in plans:   # a served shape equal to a workload's: tuned once
+        skip = g.key in done or (args.only is not None and not any(o in g.key for o in args.only))
+        if skip:   # a served shape equal to a workload's is tuned once; --only skips the rest
             del g
             continue
+        done.add(g.key)
         t0 = time.perf_counter()
         reps = args.reps if s["nz"] <= 64 else max(2, args.reps // 4)   # volumes: long launches
         plans[g.key] = api.autotune(g, reps=reps, store=False)

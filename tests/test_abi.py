@@ -293,3 +293,32 @@ def test_noalloc_entry_rejects_on_the_host(nat):
         assert b"static scratch" in lib.last_error_message()
     finally:
         lib.free_geometry(big)
+
+
+def test_kernel_timer_arguments(nat):
+    # measurement support: class masks and class numbers outside 1..9 are refused on the host
+    lib = nat.load()
+    ms, n = C.c_double(), C.c_int32()
+    assert lib.kernel_timer_start(1) == nat.PS_EINVAL          # bit 0 is no class
+    assert lib.kernel_timer_start(1 << 10) == nat.PS_EINVAL
+    assert lib.kernel_timer_read(0, C.byref(ms), C.byref(n)) == nat.PS_EINVAL
+    assert lib.kernel_timer_read(10, C.byref(ms), C.byref(n)) == nat.PS_EINVAL
+    assert lib.kernel_timer_start((1 << 1) | (1 << 9)) == nat.PS_OK
+    assert lib.kernel_timer_read(1, C.byref(ms), C.byref(n)) == nat.PS_OK
+    assert n.value == 0 and ms.value == 0.0                    # nothing launched
+    assert lib.kernel_timer_read(1, None, C.byref(n)) == nat.PS_EINVAL
+    assert lib.kernel_timer_stop() == nat.PS_OK
+
+
+def test_kernel_time_arguments(nat):
+    lib = nat.load()
+    h = C.c_void_p()
+    assert lib.make_geometry(C.byref(_desc(nat)), C.byref(h)) == nat.PS_OK
+    try:
+        assert lib.kernel_time_workspace_bytes(h) > 0
+        us = C.c_double()
+        # not uploaded: refused before any device work
+        assert lib.kernel_time(h, 1, 10, C.c_void_p(256), 1 << 30, None, C.byref(us)) == nat.PS_EINVAL
+        assert lib.kernel_time(None, 1, 10, C.c_void_p(256), 1 << 30, None, C.byref(us)) == nat.PS_EINVAL
+    finally:
+        lib.free_geometry(h)

@@ -1,0 +1,82 @@
+"""3D FGP launch forms on the GPU: one inner iteration per launch, and two per launch on 8 x 2
+and 4 x 4 wave tiles, over z chunks of several lengths, give the same bits (each value is formed
+by the same expressions), and match the FP64 oracle (FP32 within 1e-5, FP64 within 1e-11), on
+ragged volumes that span several tiles in x, y and z, with odd and even inner-iteration counts,
+cold and warm starts, with and without the constraint."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+# (nx, ny, nz): several 60-column and 12-row tiles with ragged tails, slices not a multiple of
+# the chunk, and degenerate volumes (two slices, one voxel per slice)
+SHAPES = [(130, 70, 11), (61, 13, 2), (9, 7, 3), (64, 25, 7), (1, 1, 2), (24, 20, 4)]
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _prox(g, v, tau, K, nonneg, dual0, dtype, form, chunk):
+    from paper_2602_09527_amd import api
+    plan = g.get_plan()
+    plan.update(fgp3d_form=form, fgp3d_chunk=chunk)
+    g.set_plan(plan)
+    d = None if dual0 is None else torch.from_numpy(dual0).to(device="cuda", dtype=dtype)
+    z = api.tv_prox(g, torch.from_numpy(v).to(device="cuda", dtype=dtype), tau, K,
+                    nonneg=nonneg, dual=d)
+    torch.cuda.synchronize()
+    return z.cpu(), None if d is None else d.cpu()
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float32, 1e-5), (torch.float64, 1e-11)],
+                         ids=["f32", "f64"])
+@pytest.mark.parametrize("shape", SHAPES, ids=[f"{s[0]}x{s[1]}x{s[2]}" for s in SHAPES])
+def test_forms_bitwise_and_oracle(orc, shape, dtype, tol):
+    from paper_2602_09527_amd import api
+    nx, ny, nz = shape
+    g = api.Geometry(nx, ny, 4, 8, nz=nz, dtype=dtype)
+    rng = np.random.default_rng(nx * 131 + ny * 7 + nz)
+    v = rng.uniform(-0.2, 1.0, g.image_shape)
+    dual0 = rng.uniform(-0.6, 0.6, g.dual_shape())
+    for K in (1, 2, 3, 6, 9):
+        for nonneg, warm, tau in ((True, True, 0.05), (False, True, 0.4), (True, False, 0.02)):
+            d0 = dual0 if warm else None
+            ref_z, ref_d = _prox(g, v, tau, K, nonneg, d0, dtype, 1, 4)
+            d_o = dual0.copy() if warm else None
+            zo = orc.tv_prox_fgp(v, tau, K, nonneg=nonneg, dual=d_o)
+            assert _rel(ref_z.double().numpy(), zo) <= tol, (K, nonneg, warm)
+            if warm:
+                assert _rel(ref_d.double().numpy(), d_o) <= 10 * tol, (K, nonneg)
+            for form in (1, 2, 3):
+                for chunk in (1, 2, 4, 16):
+                    if form == 1 and chunk == 4:
+                        continue
+                    z, d = _prox(g, v, tau, K, nonneg, d0, dtype, form, chunk)
+                    assert torch.equal(z, ref_z), (K, form, chunk, nonneg, warm)
+                    if warm:
+                        assert torch.equal(d, ref_d), (K, form, chunk, nonneg)
+
+
+def test_solver_on_a_volume_is_the_same_for_every_form():
+    # a 3D-TV ProxSkip-SVRG solve (6 x 40 x 72 volume, 24 angles x 80 bins, 4 subsets, p = 0.5)
+    # gives the same iterate bit for bit with every 3D FGP launch form
+    from paper_2602_09527_amd import api, synth
+    nx, ny, nz, A, B = 72, 40, 6, 24, 80
+    prob = synth.make_problem(nx, ny, A, B, seed=19, nz=nz, with_phantom=False)
+    b = torch.from_numpy(prob.b).to(device="cuda", dtype=torch.float32)
+    xs = []
+    for form in (1, 2, 3):
+        g = api.Geometry(nx, ny, A, B, n_subsets=4, nz=nz)
+        plan = g.get_plan()
+        plan.update(fgp3d_form=form)
+        g.set_plan(plan)
+        kw = dict(gamma=1.0 / 2000.0, p=0.5, alpha=0.02, fgp_inner=7, n_epochs=3, seed=4)
+        x, _, _, st = api.solve(g, b, api.SolverParams(**kw))
+        torch.cuda.synchronize()
+        assert st["prox_calls"] > 0
+        xs.append(x.cpu())
+    assert torch.equal(xs[0], xs[1]) and torch.equal(xs[0], xs[2])
