@@ -7,10 +7,12 @@ the SVRG snapshot with its full projection/backprojection, 20 subset projection/
 pairs with the fused SVRG/ProxSkip update, and the FGP prox on the coin flips that hit).
 
 Prints one JSON line.  Besides the timed epochs it reports:
-  roofline      the dominant kernel (the backprojector) on its all-angle launch: algorithmic lane
-                operations per second against the VALU issue peak, the duration measured here
-                with HIP events on the launching stream, and the HBM bytes per launch from the
-                committed rocprofv3 counter summary (null once the kernel source has changed);
+  roofline      the kernel class with the most GPU time per epoch (per-launch HIP events on the
+                launching stream over a second pass of the solve), rated on one launch timed
+                alone: algorithmic lane operations per second against the VALU issue peak, and
+                the HBM bytes per launch from the committed rocprofv3 counter summary (null once
+                the kernel source has changed);
+  kernel_time_per_epoch  that per-class breakdown of the epoch;
   kernels       each operator's rate in samples/s, lane operations/s and algorithmic GB/s;
   sweep         epochs/s and prox calls at p in {1, 0.1, 0.02}, non-skipped ProxSVRG, ProxLSVRGSkip
                 and ProxSAGASkip at p = 0.1, and iterations/s (one data pass each) of ISTA,
@@ -21,7 +23,11 @@ Prints one JSON line.  Besides the timed epochs it reports:
   serving       a Poisson trace of mixed-size requests with continuous batching against one
                 request at a time (p50/p99 latency, throughput);
   cpu_baseline  the FP64 oracle timed on the host cores over a bounded sample of the same solve;
-  parity        the GPU iterate against the oracle's after that sample.
+  parity        the GPU iterate against the oracle's after that sample;
+  volume        the 256 x 1024^2 volume with 3D TV as a bounded leg (1 warm-up and 2 timed epochs
+                unless --volume-epochs says otherwise): per-operator times with the stored and the
+                automatic plan, one epoch eager against a HIP graph, the oracle's per-operator
+                times on a few slices.
 
 --volume times the 256 x 1024^2 volume instead (5 epochs after 1 warm-up unless --steps and
 --warmup say otherwise); --calibrate-copy runs only a plain device copy
@@ -323,11 +329,66 @@ def volume_leg(epochs, warmup, log_fn, graph_check=True, plan_check=True, oracle
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps * 1e-3
 
+    del s
+    torch.cuda.empty_cache()
+
+    # per-operator times: stored (tuned) plan against the automatic plan
+    n = w.nx * w.ny * w.nz
+    a = g.subset_size(0)
+    x = torch.rand(g.image_shape, device=dev)
+    ysub = torch.empty(g.sino_shape(0), device=dev)
+    img = torch.empty_like(x)
+    dual = torch.zeros(g.dual_shape(), device=dev)
+    copy_src = torch.ones(256 * 1024 * 1024, device=dev)
+    copy_dst = torch.empty_like(copy_src)
+    t_copy = event_time(lambda: copy_dst.copy_(copy_src), reps=5)
+    copy_gbs = 2.0 * copy_src.numel() * 4 / t_copy / 1e9
+    del copy_src, copy_dst
+    def ops(geom):
+        tp = event_time(lambda: api.project(geom, x, 0, out=ysub))
+        tb = event_time(lambda: api.backproject(geom, ysub, 0, out=img))
+        # one inner iteration: a 12-iteration prox less a 2-iteration one (the finalize and the
+        # copies around the iterations cancel), per iteration
+        t12 = event_time(lambda: api.tv_prox(geom, x, 1e-4, 12, dual=dual, out=img), reps=2)
+        t2 = event_time(lambda: api.tv_prox(geom, x, 1e-4, 2, dual=dual, out=img), reps=2)
+        return tp, tb, (t12 - t2) / 10
+    t_fp, t_bp, t_it = ops(g)
+    steps_fp = a * w.n_bins * w.nz * max(w.nx, w.ny)
+    form = g.get_plan()["fgp3d_form"]
+    # bytes per voxel and iteration: 40 as one iteration per launch moves them (read v, p (3),
+    # p_prev (3); write p (3)); a two-iteration launch reads 7 and writes 6 values per voxel
+    b_one = 40.0 * n
+    b_form = (26.0 if form >= 2 else 40.0) * n
+    rec["kernels"] = {
+        "project_subset_ms": round(t_fp * 1e3, 3),
+        "project_subset_gsamples_per_s": round(steps_fp / t_fp / 1e9, 1),
+        "backproject_subset_ms": round(t_bp * 1e3, 3),
+        "fgp3d_form": form,
+        "fgp3d_iteration_ms": round(t_it * 1e3, 3),
+        "fgp3d_gbs_at_40B": round(b_one / t_it / 1e9, 1),
+        "fgp3d_hbm_frac_at_40B": round(b_one / t_it / 1e9 / HBM_PEAK_GBS, 4),
+        "fgp3d_gbs_moved": round(b_form / t_it / 1e9, 1),
+        "fgp3d_hbm_frac_moved": round(b_form / t_it / 1e9 / HBM_PEAK_GBS, 4),
+        "device_copy_gbs": round(copy_gbs, 1)}
+    log_fn(f"bench: volume kernels {rec['kernels']}")
+    if plan_check:
+        gd = api.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=N, nz=w.nz, device=dev)
+        d_fp, d_bp, d_tv = ops(gd)
+        rec["tuned_vs_automatic_plan"] = {
+            "automatic_plan": gd.get_plan(),
+            "project_subset_ms": [round(t_fp * 1e3, 3), round(d_fp * 1e3, 3)],
+            "backproject_subset_ms": [round(t_bp * 1e3, 3), round(d_bp * 1e3, 3)],
+            "fgp3d_iteration_ms": [round(t_it * 1e3, 3), round(d_tv * 1e3, 3)]}
+        log_fn(f"bench: volume tuned vs automatic {rec['tuned_vs_automatic_plan']}")
+        del gd
+    del x, ysub, img, dual
+    torch.cuda.empty_cache()
+    # last: kernels timed after HIP graphs have run measured slower here (3D FGP 1.9 -> 2.7 ms per
+    # iteration), so the per-operator times above come first
     if graph_check:
         # epoch W + 1 eager (a fresh handle from the saved state) against the same epoch as a HIP
         # graph (another handle from the same state): identical work, bit for bit the same x
         xs_, hs_, ds_ = state
-        del s
         times = {}
         xs_out = {}
         for mode in ("eager", "graph"):
@@ -346,54 +407,8 @@ def volume_leg(epochs, warmup, log_fn, graph_check=True, plan_check=True, oracle
                                  "graph_over_eager": round(times["graph"] / times["eager"], 4),
                                  "bitwise_equal": bool(torch.equal(xs_out["eager"], xs_out["graph"]))}
         del xs_out, state, xs_, hs_, ds_
-    else:
-        del s
-    torch.cuda.empty_cache()
+        torch.cuda.empty_cache()
 
-    # per-operator times: stored (tuned) plan against the automatic plan
-    n = w.nx * w.ny * w.nz
-    a = g.subset_size(0)
-    x = torch.rand(g.image_shape, device=dev)
-    ysub = torch.empty(g.sino_shape(0), device=dev)
-    img = torch.empty_like(x)
-    dual = torch.zeros(g.dual_shape(), device=dev)
-    copy_src = torch.ones(256 * 1024 * 1024, device=dev)
-    copy_dst = torch.empty_like(copy_src)
-    t_copy = event_time(lambda: copy_dst.copy_(copy_src), reps=5)
-    copy_gbs = 2.0 * copy_src.numel() * 4 / t_copy / 1e9
-    del copy_src, copy_dst
-    fgp_iters = 10
-
-    def ops(geom):
-        tp = event_time(lambda: api.project(geom, x, 0, out=ysub))
-        tb = event_time(lambda: api.backproject(geom, ysub, 0, out=img))
-        tf = event_time(lambda: api.tv_prox(geom, x, 1e-4, fgp_iters, dual=dual, out=img), reps=2)
-        return tp, tb, tf
-    t_fp, t_bp, t_tv = ops(g)
-    steps_fp = a * w.n_bins * w.nz * max(w.nx, w.ny)
-    fgp_bytes = 40.0 * n * fgp_iters   # per iteration: read v, p (3), p_prev (3); write p (3)
-    rec["kernels"] = {
-        "project_subset_ms": round(t_fp * 1e3, 3),
-        "project_subset_gsamples_per_s": round(steps_fp / t_fp / 1e9, 1),
-        "backproject_subset_ms": round(t_bp * 1e3, 3),
-        "fgp3d_iteration_ms": round(t_tv * 1e3 / fgp_iters, 3),
-        "fgp3d_algorithmic_gbs": round(fgp_bytes / t_tv / 1e9, 1),
-        "fgp3d_hbm_frac": round(fgp_bytes / t_tv / 1e9 / HBM_PEAK_GBS, 4),
-        "device_copy_gbs": round(copy_gbs, 1),
-        "fgp3d_frac_of_copy": round(fgp_bytes / t_tv / 1e9 / copy_gbs, 4)}
-    log_fn(f"bench: volume kernels {rec['kernels']}")
-    if plan_check:
-        gd = api.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=N, nz=w.nz, device=dev)
-        d_fp, d_bp, d_tv = ops(gd)
-        rec["tuned_vs_automatic_plan"] = {
-            "automatic_plan": gd.get_plan(),
-            "project_subset_ms": [round(t_fp * 1e3, 3), round(d_fp * 1e3, 3)],
-            "backproject_subset_ms": [round(t_bp * 1e3, 3), round(d_bp * 1e3, 3)],
-            "fgp3d_iteration_ms": [round(t_tv * 1e3 / fgp_iters, 3), round(d_tv * 1e3 / fgp_iters, 3)]}
-        log_fn(f"bench: volume tuned vs automatic {rec['tuned_vs_automatic_plan']}")
-        del gd
-    del x, ysub, img, dual
-    torch.cuda.empty_cache()
     if oracle_ops:
         rec["oracle_ops"] = oracle_volume_ops(w, log_fn)
     return rec

@@ -19,8 +19,9 @@
  *     (3D TV couples slices).
  *   - Every floating-point buffer has the geometry's dtype (float or double).
  *   - Device pointers are HIP device memory owned by the caller, contiguous, aligned to at least
- *     the dtype size.  The library never allocates or frees device memory: work buffers are
- *     passed in as a caller-owned workspace whose size the *_workspace_bytes queries return.
+ *     the dtype size.  No compute call allocates or frees device memory: work buffers are
+ *     passed in as a caller-owned workspace whose size the *_workspace_bytes queries return
+ *     (device_alloc below is an optional allocator for them; the caller still owns the memory).
  *   - `stream` is a hipStream_t (NULL = the default stream).  Calls that launch kernels return
  *     as soon as the work is queued (stream-ordered); asynchronous faults surface at the next
  *     synchronisation.
@@ -102,18 +103,19 @@ PS_API int32_t subset_size(const ps_geometry *geom, int32_t subset);
  *                  with the update fused (needs bins at least one pixel apart along every ray's
  *                  stepping axis, e.g. bin_width >= 1; otherwise scatter is used)
  *   bp_gather_rows rows per wave of the gather's tiles (63 columns x 4 waves x rows): 2 or 4
- *   fgp3d_chunk    slices each workgroup of the 3D FGP marches through: 1..256 (default 4)
+ *   fgp3d_chunk    slices each workgroup of the 3D FGP marches through: 1..256, 0 = automatic
+ *                  (4 for one iteration per launch, 16 for two)
  *   fgp_waves, fgp_rows  2D FGP tile: waves per workgroup and image rows per wave, one of
  *                  (4,4) (4,8) (8,2) (8,4) (8,8) (16,2) (16,4); both 0 = automatic (8,4 FP32;
  *                  16,2 FP64).  The tile does not change results, not even their rounding.
  *                  fgp_iters and the tile apply to a prox computed alone: the proxes of several
  *                  handles advanced together (solver_epochs / solver_steps over several
  *                  handles) share launches on the automatic tile and depth.
- *   fgp3d_form     3D FGP launches: 1 = one inner iteration per launch (62 x 14 tiles); 2 or 3 =
+ *   fgp3d_form     3D FGP launches: 1 = one inner iteration per launch (62 x 14 tiles); 2..5 =
  *                  two per launch (7 values read and 6 written per voxel for two iterations
- *                  instead of 20) on tiles of 8 waves x 2 rows or 4 waves x 4 rows (60 x 12
- *                  outputs); 0 = automatic (2).  The form does not change results, not even their
- *                  rounding.
+ *                  instead of 20) on tiles of 8 waves x 2 rows (2), 4 x 4 (3), both 60 x 12
+ *                  outputs, 16 x 2 (4) or 8 x 4 (5), both 60 x 28 outputs; 0 = automatic (5 FP32,
+ *                  2 FP64).  The form does not change results, not even their rounding.
  * "_full" applies to all-angle calls (subset = -1), "_subset" to single subsets. */
 typedef struct {
     int32_t proj_split_full, proj_split_subset;
@@ -343,6 +345,20 @@ PS_API size_t pdhg_workspace_bytes(const ps_geometry *geom);
 PS_API ps_status pdhg_run(const ps_geometry *geom, const void *b, void *x, void *y1, void *y2,
                    double alpha, int32_t nonneg, int32_t n_iters, void *workspace,
                    size_t ws_bytes, void *stream);
+
+/* Optional allocator for large caller-owned buffers such as workspaces (not part of the method).
+ * Many-GiB allocations made after many earlier allocations and frees can consist of small
+ * physical pieces; kernels that stream several such arrays at once (the 3D FGP iteration walks
+ * thirteen) then stall on address translation.  device_alloc(bytes, device, &ptr, &contiguous)
+ * requests physically contiguous device memory on `device` and falls back to an ordinary
+ * allocation when the driver cannot provide it; *contiguous (may be NULL) tells which.  The
+ * memory is uninitialised and owned by the caller, who releases it with device_free, which first
+ * waits for all work on that device (a buffer may still be in use by queued kernels).
+ * device_free(NULL) does nothing.  The current device is unchanged on return.
+ * Errors: PS_EINVAL (bytes == 0, out == NULL, no such device, not device memory), PS_EHIP
+ * (the ordinary allocation failed too). */
+PS_API ps_status device_alloc(size_t bytes, int32_t device, void **out, int32_t *contiguous);
+PS_API ps_status device_free(void *ptr);
 
 /* Measurement support (not part of the method): the GPU time of chosen classes of kernel launches
  * inside later calls on any stream, from HIP events recorded on the launching stream right before

@@ -31,7 +31,7 @@ EXPORTS = (
     "fista_run", "pdhg_workspace_bytes", "pdhg_run", "last_error_message",
     "proxskip_noalloc_max_bytes", "proxskip_svrg_run_noalloc",
     "kernel_timer_start", "kernel_timer_read", "kernel_timer_stop", "kernel_time_workspace_bytes",
-    "kernel_time",
+    "kernel_time", "device_alloc", "device_free",
 )
 PS_EST_SVRG, PS_EST_LSVRG, PS_EST_SAGA = 0, 1, 2
 
@@ -133,6 +133,8 @@ def load():
         "kernel_time": (st, [vp, i32, i32, vp, sz, vp, C.POINTER(d)]),
         "proxskip_svrg_run_noalloc": (st, [vp, vp, vp, vp, vp, C.POINTER(SolverParams),
                                            C.POINTER(SolverStats), vp]),
+        "device_alloc": (st, [sz, i32, C.POINTER(vp), C.POINTER(i32)]),
+        "device_free": (st, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

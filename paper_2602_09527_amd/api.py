@@ -26,6 +26,48 @@ def _ptr(t: torch.Tensor | None) -> C.c_void_p:
     return C.c_void_p(t.data_ptr() if t is not None else None)
 
 
+# Workspaces of at least this many bytes come from the library's device_alloc (physically
+# contiguous when the driver can provide it); smaller ones from torch's caching allocator.  A
+# multi-GiB buffer built from small physical pieces slows the kernels that stream several of
+# them at once (address translation), and only volume-sized workspaces reach this size.
+CONTIGUOUS_MIN_BYTES = 1 << 30
+
+
+class DeviceBuffer:
+    """Device memory from device_alloc, used as a workspace: only its address and size are read
+    (data_ptr, numel, like a uint8 tensor's).  Released with device_free -- which first waits for
+    the device's queued work -- when the last reference goes."""
+
+    def __init__(self, nbytes: int, device: torch.device):
+        self.lib = nat.load()
+        p, contig = C.c_void_p(), C.c_int32()
+        nat.check(self.lib.device_alloc(int(nbytes), int(device.index), C.byref(p), C.byref(contig)),
+                  "device_alloc")
+        self.ptr, self.nbytes, self.contiguous = p.value, int(nbytes), bool(contig.value)
+
+    def data_ptr(self) -> int:
+        return self.ptr
+
+    def numel(self) -> int:
+        return self.nbytes
+
+    def __del__(self):
+        p = getattr(self, "ptr", None)
+        if p:
+            self.ptr = None
+            try:
+                self.lib.device_free(C.c_void_p(p))
+            except Exception:   # interpreter shutdown
+                pass
+
+
+def workspace_buffer(nbytes: int, device: torch.device):
+    """A workspace of `nbytes` on `device` (see CONTIGUOUS_MIN_BYTES)."""
+    if nbytes >= CONTIGUOUS_MIN_BYTES:
+        return DeviceBuffer(nbytes, device)
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
 class Geometry:
     """Parallel-beam geometry with its per-angle tables resident on ``device``."""
 
@@ -140,7 +182,7 @@ class Geometry:
             return None
         ws = self._ws.get(key)
         if ws is None or ws.numel() < nbytes:
-            ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            ws = workspace_buffer(nbytes, self.device)
             self._ws[key] = ws
         return ws
 
@@ -235,7 +277,7 @@ def solve(g: Geometry, b: torch.Tensor, params: SolverParams, x=None, h=None, du
             else g.check(dual, g.dual_shape(), "dual"))
     prm = params.c()
     nbytes = g.lib.proxskip_workspace_bytes(g.handle, C.byref(prm))
-    ws = torch.empty(nbytes, dtype=torch.uint8, device=g.device)
+    ws = workspace_buffer(nbytes, g.device)
     st = nat.SolverStats()
     nat.check(g.lib.proxskip_svrg_run(g.handle, _ptr(b), _ptr(x), _ptr(h), _ptr(dual), C.byref(prm),
                                       C.byref(st), _ptr(ws), nbytes, _stream(g.device)),
@@ -306,7 +348,7 @@ def kernel_time(g: Geometry, cls: str, reps: int = 100) -> float:
     class alone on this geometry (HIP events around `reps` back-to-back launches on the current
     stream; see kernel_time in include/proxskip.h)."""
     nbytes = g.lib.kernel_time_workspace_bytes(g.handle)
-    ws = torch.empty(nbytes, dtype=torch.uint8, device=g.device)
+    ws = workspace_buffer(nbytes, g.device)
     us = C.c_double()
     nat.check(g.lib.kernel_time(g.handle, KERNEL_CLASSES[cls], int(reps), _ptr(ws), nbytes,
                                 _stream(g.device), C.byref(us)), "kernel_time")
@@ -327,7 +369,7 @@ class Solver:
         self.params = params
         self._prm = params.c()
         nbytes = g.lib.proxskip_workspace_bytes(g.handle, C.byref(self._prm))
-        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=g.device)
+        self.ws = workspace_buffer(nbytes, g.device)
         h_ = C.c_void_p()
         nat.check(g.lib.solver_init(g.handle, _ptr(self.b), _ptr(self.x), _ptr(self.h),
                                     _ptr(self.dual), C.byref(self._prm), _ptr(self.ws), nbytes,
@@ -424,7 +466,7 @@ class Fista:
         self.t = C.c_double(1.0)
         self.gamma, self.alpha, self.fgp_inner, self.nonneg = gamma, alpha, fgp_inner, nonneg
         self.nbytes = g.lib.fista_workspace_bytes(g.handle)
-        self.ws = torch.empty(max(self.nbytes, 1), dtype=torch.uint8, device=g.device)
+        self.ws = workspace_buffer(self.nbytes, g.device)
 
     def run(self, n_iters: int):
         g = self.g
@@ -480,7 +522,7 @@ def autotune(g: Geometry, reps: int = 5, cache_path: str | None = None, store: b
     if not tune_missing:
         return g.get_plan()
     nbytes = g.lib.geometry_autotune_workspace_bytes(g.handle)
-    ws = torch.empty(nbytes, dtype=torch.uint8, device=g.device)
+    ws = workspace_buffer(nbytes, g.device)
     p = nat.Plan()
     nat.check(g.lib.geometry_autotune(g.handle, _ptr(ws), nbytes, int(reps), _stream(g.device),
                                       C.byref(p)), "geometry_autotune")

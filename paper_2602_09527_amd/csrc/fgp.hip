@@ -11,12 +11,20 @@
 // keeps a contiguous block of RW = EY/W rows of (v, p, r, z) in registers, takes horizontal
 // neighbours from lane shuffles and exchanges only its first and last rows through LDS.  Between
 // launches the state is (p_k, r_{k+1}), the dual and its extrapolation.
-// 3D (slices coupled): one launch per half-iteration over global memory (HBM-bound volumes).
+// 3D (slices coupled): marching tiles over global memory, one or two whole inner iterations per
+// launch (HBM-bound volumes).
 #include <algorithm>
 #include <cmath>
 #include <vector>
 
 #include "internal.h"
+
+// No implicit fusing of a multiply and an add into one rounding: every fused multiply-add below is
+// written as fma(), so each value is rounded the same way in every kernel and tile shape that
+// forms it, and the plan's tile, depth and launch form never change results.  Left to the
+// compiler, the fusing differs between template instantiations (measured: the 3D iteration on
+// 16 x 2 wave tiles differed from 8 x 2 in the last bit).
+#pragma clang fp contract(off)
 
 namespace ps {
 
@@ -231,6 +239,27 @@ __device__ inline T mom(const T *pa, const T *pb, size_t q, T c) {
     return fma(c, pa[q] - pb[q], pa[q]);
 }
 
+// Projection of one voxel's dual 3-vector onto the unit ball: scaled by 1/||u|| when ||u|| > 1
+// (FP32: one correctly rounded reciprocal square root and three products, as the 2D kernel
+// does; FP64: the square root and three divisions).
+template <typename T>
+__device__ inline void unit_ball3(T &ux, T &uy, T &uz) {
+    const T n2 = ux * ux + uy * uy + uz * uz;
+    if (n2 > T(1)) {
+        if constexpr (std::is_same<T, float>::value) {
+            const T sc = __frsqrt_rn(n2);
+            ux *= sc;
+            uy *= sc;
+            uz *= sc;
+        } else {
+            const T nrm = sqrt(n2);
+            ux /= nrm;
+            uy /= nrm;
+            uz /= nrm;
+        }
+    }
+}
+
 // zbuf = P_C(v - tau D^T r), r = pa + c (pa - pb); with c = 0 and pa = p this is z(p).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fgp3d_primal(
@@ -285,12 +314,7 @@ __global__ __launch_bounds__(kBlock) void k_fgp3d_dual(
         T px = fma(step, dx, mom(pa, pb, e, c));
         T py = fma(step, dy, mom(pa + n, pb + n, e, c));
         T pz = fma(step, dz, mom(pa + 2 * n, pb + 2 * n, e, c));
-        const T nrm = sqrt(px * px + py * py + pz * pz);
-        if (nrm > T(1)) {
-            px /= nrm;
-            py /= nrm;
-            pz /= nrm;
-        }
+        unit_ball3(px, py, pz);
         pn[e] = px;
         pn[e + n] = py;
         pn[e + 2 * n] = pz;
@@ -426,12 +450,7 @@ __global__ __launch_bounds__(kBlock) void k_fgp3d_iter(Fgp3Args<T> a) {
                 const T dzy = gy < ny - 1 ? zb - pz[r] : T(0);
                 const T dzz = s - 1 < nz - 1 ? zz[r] - pz[r] : T(0);
                 T ux = fma(step, dzx, prx[r]), uy = fma(step, dzy, pry[r]), uz = fma(step, dzz, prz[r]);
-                const T nrm = sqrt(ux * ux + uy * uy + uz * uz);
-                if (nrm > T(1)) {
-                    ux /= nrm;
-                    uy /= nrm;
-                    uz /= nrm;
-                }
+                unit_ball3(ux, uy, uz);
                 const bool out = in[r] && lane >= 1 && lane <= kF3TX && gy >= ty * kF3TY &&
                                  gy < ty * kF3TY + kF3TY;
                 if (out) {
@@ -469,6 +488,10 @@ __global__ __launch_bounds__(kBlock) void k_fgp3d_iter(Fgp3Args<T> a) {
 // at slices outside the chunk are halo and are never written.  Voxels outside the volume hold
 // zeros in every quantity, as the zero loads of the one-iteration kernel give it.
 constexpr int kF32X = kFgpEX - 4;   // output columns per tile
+// launch forms: 1 = one iteration per launch; 2..5 = two per launch on tiles of (waves x rows
+// per wave) 8 x 2, 4 x 4, 16 x 2, 8 x 4
+constexpr int kF32Waves[kF3Forms + 1] = {0, 0, 8, 4, 16, 8};
+constexpr int kF32Rows[kF3Forms + 1] = {0, 0, 2, 4, 2, 4};
 
 template <typename T>
 struct Fgp3Args2 {
@@ -544,12 +567,7 @@ __global__ __launch_bounds__(W * kFgpEX) void k_fgp3d_iter2(Fgp3Args2<T> a) {
     };
     // unit-ball projection of the dual step at one voxel
     auto dual_step = [&](T ux, T uy, T uz, T &ox, T &oy, T &oz) {
-        const T nrm = sqrt(ux * ux + uy * uy + uz * uz);
-        if (nrm > T(1)) {
-            ux /= nrm;
-            uy /= nrm;
-            uz /= nrm;
-        }
+        unit_ball3(ux, uy, uz);
         ox = ux;
         oy = uy;
         oz = uz;
@@ -736,11 +754,12 @@ size_t fgp_workspace(const ps_geometry *g) {
 // A tile of height EY leaves EY - 2 (T + 1) interior rows, so T is capped at EY / 2 - 2.
 int fgp3d_form_of(const ps_geometry *g) {
     const int f = g->plan.fgp3d_form;
-    return f >= 1 && f <= 3 ? f : 2;
+    if (f >= 1 && f <= kF3Forms) return f;
+    return g->desc.dtype == PS_F64 ? 2 : 5;
 }
 
 // Slices per 3D workgroup: 4 for one iteration per launch (short chunks spread the accesses
-// over more of the volume), 16 for two (its z halo of three slices is paid once per chunk).
+// over more of the volume), 16 for two (their z halo of three slices is paid once per chunk).
 int fgp3d_chunk_of(const ps_geometry *g) {
     if (g->plan.fgp3d_chunk > 0) return g->plan.fgp3d_chunk;
     return fgp3d_form_of(g) == 1 ? kF3Chunk : 16;
@@ -954,13 +973,8 @@ static ps_status fgp_single_t(const FgpCall &c, hipStream_t st) {
     const std::vector<double> cs = momentum(std::max(K, 1));
     const T tauT = static_cast<T>(c.tau);
     const T stepT = static_cast<T>(1.0 / (4.0 * dims * c.tau));
-    // rotate three dual buffers p_{k-2}, p_{k-1}, p_k; buf[3] may hold the zero cold start
     const unsigned gr = grid_for(n);
-    FgpFinal<T> mid{};
-    mid.mode = 0;
     const T *pb = dual_in, *pa = dual_in;
-    T *rot[3] = {buf[0], buf[1], buf[2]};
-    int next = 0;
     Fgp3Args<T> fa{};
     fa.v = vin;
     fa.nx = d.nx;
@@ -974,10 +988,6 @@ static ps_status fgp_single_t(const FgpCall &c, hipStream_t st) {
     fa.chunk = fgp3d_chunk_of(g);
     const long f3_blocks = static_cast<long>(fa.tiles_x) * fa.tiles_y * ((d.nz + fa.chunk - 1) / fa.chunk);
     if (f3_blocks > (1L << 30)) return fail(PS_EUNSUPPORTED, "3D TV grid too large");
-    (void)mid;
-    (void)zscratch;
-    (void)rot;
-    (void)next;
     // launch form: 1 = one iteration per launch; 2, 3 = two per launch on 8 x 2 or 4 x 4 tiles
     const int form = fgp3d_form_of(g);
     Fgp3Args2<T> fb{};
@@ -989,7 +999,7 @@ static ps_status fgp_single_t(const FgpCall &c, hipStream_t st) {
     fb.step = stepT;
     fb.nonneg = c.nonneg;
     fb.chunk = fa.chunk;
-    const int ty2 = form == 2 ? 8 * 2 - 4 : 4 * 4 - 4;
+    const int ty2 = kF32Waves[form] * kF32Rows[form] - 4;
     fb.tiles_x = (d.nx + kF32X - 1) / kF32X;
     fb.tiles_y = (d.ny + ty2 - 1) / ty2;
     const long f32_blocks = static_cast<long>(fb.tiles_x) * fb.tiles_y * ((d.nz + fb.chunk - 1) / fb.chunk);
@@ -1015,10 +1025,13 @@ static ps_status fgp_single_t(const FgpCall &c, hipStream_t st) {
             fb.c1 = static_cast<T>(cs[k]);
             fb.c2 = static_cast<T>(cs[k + 1]);
             timer_mark(KC_FGP3D, st, true);
-            if (form == 2)
-                hipLaunchKernelGGL((k_fgp3d_iter2<T, 8, 2>), dim3(static_cast<unsigned>(f32_blocks)), dim3(8 * kFgpEX), 0, st, fb);
-            else
-                hipLaunchKernelGGL((k_fgp3d_iter2<T, 4, 4>), dim3(static_cast<unsigned>(f32_blocks)), dim3(4 * kFgpEX), 0, st, fb);
+            const dim3 grid(static_cast<unsigned>(f32_blocks));
+            switch (form) {
+            case 2: hipLaunchKernelGGL((k_fgp3d_iter2<T, 8, 2>), grid, dim3(8 * kFgpEX), 0, st, fb); break;
+            case 3: hipLaunchKernelGGL((k_fgp3d_iter2<T, 4, 4>), grid, dim3(4 * kFgpEX), 0, st, fb); break;
+            case 4: hipLaunchKernelGGL((k_fgp3d_iter2<T, 16, 2>), grid, dim3(16 * kFgpEX), 0, st, fb); break;
+            default: hipLaunchKernelGGL((k_fgp3d_iter2<T, 8, 4>), grid, dim3(8 * kFgpEX), 0, st, fb); break;
+            }
             PS_LAUNCHED("k_fgp3d_iter2");
             timer_mark(KC_FGP3D, st, false);
             pb = p1;

@@ -162,7 +162,7 @@ extern "C" ps_status geometry_set_plan(ps_geometry *g, const ps_plan *p) {
     if (p->bp_gather_rows != 0 && p->bp_gather_rows != 2 && p->bp_gather_rows != 4)
         return fail(PS_EINVAL, "bp_gather_rows must be 0, 2 or 4");
     if (p->fgp3d_chunk < 0 || p->fgp3d_chunk > 256) return fail(PS_EINVAL, "fgp3d_chunk must be in [0, 256]");
-    if (p->fgp3d_form < 0 || p->fgp3d_form > 3) return fail(PS_EINVAL, "fgp3d_form must be in [0, 3]");
+    if (p->fgp3d_form < 0 || p->fgp3d_form > kF3Forms) return fail(PS_EINVAL, "fgp3d_form must be in [0, %d]", kF3Forms);
     if (!(p->fgp_waves == 0 && p->fgp_rows == 0) && !fgp_tile_ok(p->fgp_waves, p->fgp_rows))
         return fail(PS_EINVAL, "FGP tile %d x %d: waves x rows must be 4x4, 4x8, 8x2, 8x4, 8x8, 16x2, 16x4 or 0x0",
                     p->fgp_waves, p->fgp_rows);
@@ -348,16 +348,20 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
         best.fgp_rows = pick_r;
     }
     // 3D FGP: launch form and slices per workgroup (10 inner iterations per timed call); the
-    // automatic (two iterations per launch on 8 x 2 tiles, chunks of 16) is timed first
+    // automatic form with chunks of 16 is timed first
     if (g->tv_dims == 3) {
         PS_TRY(fill(g, w + L.dual, 3 * n, st));
         float best_ms = 0.f;
         int pick_ch = 0, pick_form = 0;
         bool auto_best = true;
-        std::vector<std::array<int, 2>> cands{{2, 16}};
-        for (int form : {2, 3})
-            for (int ch : {8, 32, 4, 16})
-                if (!(form == 2 && ch == 16)) cands.push_back({form, ch});
+        ps_plan automatic = best;
+        automatic.fgp3d_form = 0;
+        g->plan = automatic;
+        const int auto_form = fgp3d_form_of(g);
+        std::vector<std::array<int, 2>> cands{{auto_form, 16}};
+        for (int form = 2; form <= kF3Forms; ++form)
+            for (int ch : {8, 16, 24, 32})
+                if (!(form == auto_form && ch == 16)) cands.push_back({form, ch});
         for (int ch : {4, 8, 2, 16}) cands.push_back({1, ch});
         for (const auto &fc : cands) {
             const int form = fc[0], ch = fc[1];

@@ -155,7 +155,8 @@ def test_plan_get_set_and_validation(nat):
             (2, 1, 4, 2, 4, 2, 5)
         for bad in (dict(proj_split_full=-1), dict(bp_groups_subset=17), dict(bp_strip_full=3),
                     dict(fgp_iters=17), dict(bp_method_subset=3), dict(fgp_waves=4, fgp_rows=2),
-                    dict(fgp_waves=8), dict(fgp_rows=4), dict(fgp_waves=32, fgp_rows=2)):
+                    dict(fgp_waves=8), dict(fgp_rows=4), dict(fgp_waves=32, fgp_rows=2),
+                    dict(fgp3d_form=6), dict(fgp3d_form=-1), dict(fgp3d_chunk=257)):
             assert lib.geometry_set_plan(h, C.byref(nat.Plan(**bad))) == nat.PS_EINVAL
         # a rejected plan leaves the previous one in place
         assert lib.geometry_get_plan(h, C.byref(got)) == nat.PS_OK and got.fgp_iters == 5
@@ -320,5 +321,34 @@ def test_kernel_time_arguments(nat):
         # not uploaded: refused before any device work
         assert lib.kernel_time(h, 1, 10, C.c_void_p(256), 1 << 30, None, C.byref(us)) == nat.PS_EINVAL
         assert lib.kernel_time(None, 1, 10, C.c_void_p(256), 1 << 30, None, C.byref(us)) == nat.PS_EINVAL
+    finally:
+        lib.free_geometry(h)
+
+
+def test_device_alloc_arguments(nat):
+    lib = nat.load()
+    p, contig = C.c_void_p(), C.c_int32(7)
+    # refused on the host before any HIP call
+    assert lib.device_alloc(0, 0, C.byref(p), C.byref(contig)) == nat.PS_EINVAL
+    assert p.value is None and contig.value == 0
+    assert lib.device_alloc(1 << 20, 0, None, None) == nat.PS_EINVAL
+    assert lib.device_free(None) == nat.PS_OK
+
+
+@pytest.mark.parametrize("dtype,form", [(0, 5), (1, 2)], ids=["f32", "f64"])
+def test_automatic_3d_form_per_dtype(nat, dtype, form):
+    # two inner iterations per launch: 8 x 4 wave tiles in FP32, 8 x 2 in FP64 (whose 8 x 4 tile
+    # needs all 256 registers); chunks of 16 slices
+    lib = nat.load()
+    h = C.c_void_p()
+    d = _desc(nat, nx=40, ny=30, nz=5, n_angles=12, n_bins=50, n_subsets=3, dtype=dtype)
+    assert lib.make_geometry(C.byref(d), C.byref(h)) == nat.PS_OK
+    try:
+        got = nat.Plan()
+        assert lib.geometry_get_plan(h, C.byref(got)) == nat.PS_OK
+        assert (got.fgp3d_form, got.fgp3d_chunk) == (form, 16)
+        assert lib.geometry_set_plan(h, C.byref(nat.Plan(fgp3d_form=1))) == nat.PS_OK
+        assert lib.geometry_get_plan(h, C.byref(got)) == nat.PS_OK
+        assert (got.fgp3d_form, got.fgp3d_chunk) == (1, 4)
     finally:
         lib.free_geometry(h)

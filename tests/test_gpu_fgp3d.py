@@ -1,6 +1,7 @@
-"""3D FGP launch forms on the GPU: one inner iteration per launch, and two per launch on 8 x 2
-and 4 x 4 wave tiles, over z chunks of several lengths, give the same bits (each value is formed
-by the same expressions), and match the FP64 oracle (FP32 within 1e-5, FP64 within 1e-11), on
+"""3D FGP launch forms on the GPU: one inner iteration per launch, and two per launch on 8 x 2,
+4 x 4, 16 x 2 and 8 x 4 wave tiles, over z chunks of several lengths, give the same bits (each
+value is formed by the same expressions, with no implicit multiply-add fusing), and match the FP64
+oracle (FP32 within 1e-5, FP64 within 1e-11), on
 ragged volumes that span several tiles in x, y and z, with odd and even inner-iteration counts,
 cold and warm starts, with and without the constraint."""
 import numpy as np
@@ -51,7 +52,7 @@ def test_forms_bitwise_and_oracle(orc, shape, dtype, tol):
             assert _rel(ref_z.double().numpy(), zo) <= tol, (K, nonneg, warm)
             if warm:
                 assert _rel(ref_d.double().numpy(), d_o) <= 10 * tol, (K, nonneg)
-            for form in (1, 2, 3):
+            for form in (1, 2, 3, 4, 5):
                 for chunk in (1, 2, 4, 16):
                     if form == 1 and chunk == 4:
                         continue
@@ -69,7 +70,7 @@ def test_solver_on_a_volume_is_the_same_for_every_form():
     prob = synth.make_problem(nx, ny, A, B, seed=19, nz=nz, with_phantom=False)
     b = torch.from_numpy(prob.b).to(device="cuda", dtype=torch.float32)
     xs = []
-    for form in (1, 2, 3):
+    for form in (1, 2, 3, 4, 5):
         g = api.Geometry(nx, ny, A, B, n_subsets=4, nz=nz)
         plan = g.get_plan()
         plan.update(fgp3d_form=form)

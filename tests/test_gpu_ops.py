@@ -207,3 +207,29 @@ def test_strided_buffers_are_refused_not_copied():
     api.tv_prox(g, v, 0.1, 5, dual=flat)
     torch.cuda.synchronize()
     assert float(flat.abs().sum()) > 0
+
+
+def test_device_alloc_workspace():
+    """A workspace from device_alloc (physically contiguous when the driver can provide it) gives
+    the same bits as one from torch; workspaces of CONTIGUOUS_MIN_BYTES and more come from it."""
+    from paper_2602_09527_amd import api
+    g = api.Geometry(61, 13, 20, 30, nz=5)
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    v = torch.rand(g.image_shape, device="cuda", generator=gen)
+    nbytes = g.lib.tv_prox_workspace_bytes(g.handle)
+    outs = []
+    for ws in (torch.empty(nbytes, dtype=torch.uint8, device="cuda"), api.DeviceBuffer(nbytes, g.device)):
+        g._ws = {"fgp": ws}
+        dual = torch.zeros(g.dual_shape(), device="cuda")
+        outs.append((api.tv_prox(g, v, 0.05, 9, dual=dual), dual))
+        torch.cuda.synchronize()
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+    buf = g._ws["fgp"]
+    assert isinstance(buf.contiguous, bool) and buf.numel() == nbytes
+    g._ws = {}
+    del buf   # device_free waits for the queued work, then frees
+    small = api.workspace_buffer(1 << 20, g.device)
+    assert isinstance(small, torch.Tensor) and small.numel() == 1 << 20
+    big = api.workspace_buffer(api.CONTIGUOUS_MIN_BYTES, g.device)
+    assert isinstance(big, api.DeviceBuffer) and big.numel() == api.CONTIGUOUS_MIN_BYTES
+    del big
