@@ -103,6 +103,10 @@ PS_API int32_t subset_size(const ps_geometry *geom, int32_t subset);
  *                  with the update fused (needs bins at least one pixel apart along every ray's
  *                  stepping axis, e.g. bin_width >= 1; otherwise scatter is used)
  *   bp_gather_rows rows per wave of the gather's tiles (63 columns x 4 waves x rows): 2 or 4
+ *   bp_gather_split waves of a gather workgroup that share one block of rows, each taking every
+ *                  split-th angle (their sums added in LDS in wave order): 1, 2 or 4; the tile
+ *                  is then 63 columns x (4 / split) x rows.  0 = automatic: 4 when the
+ *                  unsplit tiles number fewer than 256, 2 below 1024, else 1.
  *   fgp3d_chunk    slices each workgroup of the 3D FGP marches through: 1..256, 0 = automatic
  *                  (4 for one iteration per launch, 16 for two)
  *   fgp_waves, fgp_rows  2D FGP tile: waves per workgroup and image rows per wave, one of
@@ -127,6 +131,7 @@ typedef struct {
     int32_t fgp3d_chunk;
     int32_t fgp_waves, fgp_rows;
     int32_t fgp3d_form;
+    int32_t bp_gather_split;
 } ps_plan;
 
 /* The plan in effect (automatic choices filled in) / replace the overrides.  set: fields out of

@@ -103,6 +103,17 @@ int gather_rows(const ps_geometry *g, int subset) {
     return tiles4 < 512 ? 2 : 4;
 }
 
+int gather_split(const ps_geometry *g, int subset) {
+    const int forced = g->plan.bp_gather_split;
+    if (forced == 1 || forced == 2 || forced == 4) return forced;
+    // small images: split the angles until there are about 1024 workgroups (at 128^2 the 4-way
+    // split cuts a subset's gather from 9.7 to 6.2 us)
+    const auto &d = g->desc;
+    const int rows = gather_rows(g, subset);
+    const long tiles = static_cast<long>((d.nx + kGatherTX - 1) / kGatherTX) * ((d.ny + 4 * rows - 1) / (4 * rows)) * d.nz;
+    return tiles < 256 ? 4 : tiles < 1024 ? 2 : 1;
+}
+
 // One backprojector application: partial images of A_sub^T y, one per (angle class, group).
 template <typename T>
 struct BackItem {
@@ -633,13 +644,20 @@ __device__ inline void cell_ray(const GatherAngle<T> &ga, int p, T c, int64_t ba
     next = hit ? m : T(0);
 }
 
-template <typename T, int R>
+// AS waves share each block of R rows, each taking every AS-th angle of the chunk; their sums are
+// added in LDS in wave order (a fixed order) before the epilogue.  A tile is 4 / AS blocks of R
+// rows: splitting the angles gives small images more workgroups without shrinking the staged
+// windows' reuse below R rows.
+template <typename T, int R, int AS>
 __global__ __launch_bounds__(kBlock) void k_backproject_gather(WorkList<GatherItem<T>> wl) {
+    static_assert(AS == 1 || AS == 2 || AS == 4, "angle split");
     constexpr int kGatherRows = R;                 // rows per wave
-    constexpr int kGatherTY = 4 * R;               // rows per tile
+    constexpr int kRowBlocks = 4 / AS;             // row blocks per tile
+    constexpr int kGatherTY = kRowBlocks * R;      // rows per tile
     __shared__ T ywin[kGatherChunk][kGatherWin];
     __shared__ int ulo[kGatherChunk];
     __shared__ GatherAngle<T> s_ang[kGatherChunk];
+    __shared__ T red[AS > 1 ? (AS - 1) * kRowBlocks * R * kWave : 1];
     int local;
     const GatherItem<T> &it = wl.item[work_item(wl, local)];
     const AngleTab<T> &tab = it.tab;
@@ -648,8 +666,9 @@ __global__ __launch_bounds__(kBlock) void k_backproject_gather(WorkList<GatherIt
     const int lane = threadIdx.x % kWave;
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x / kWave));
     const int nx = it.nx, ny = it.ny, B = it.nbins;
+    const int rb = wave % kRowBlocks, ag = wave / kRowBlocks;   // row block, angle group
     const int j = tx * kGatherTX - 1 + lane;           // lane 0: halo column
-    const int i0 = ty * kGatherTY + wave * kGatherRows;
+    const int i0 = ty * kGatherTY + rb * kGatherRows;
     const T *yz = it.y + static_cast<size_t>(z) * it.na * B;
     T acc[kGatherRows];
 #pragma unroll
@@ -702,14 +721,14 @@ __global__ __launch_bounds__(kBlock) void k_backproject_gather(WorkList<GatherIt
         }
         __syncthreads();
         // the next angle's record is read while this one is processed
-        GatherAngle<T> raw = s_ang[0];
-        int raw_ub = ulo[0];
-        for (int a = 0; a < cn; ++a) {
+        GatherAngle<T> raw = s_ang[min(ag, cn - 1)];
+        int raw_ub = ulo[min(ag, cn - 1)];
+        for (int a = ag; a < cn; a += AS) {
             const GatherAngle<T> ga = uni(raw);
             const int ub = uni(raw_ub);
-            if (a + 1 < cn) {
-                raw = s_ang[a + 1];
-                raw_ub = ulo[a + 1];
+            if (a + AS < cn) {
+                raw = s_ang[a + AS];
+                raw_ub = ulo[a + AS];
             }
             const T *yw = ywin[a];
             if (ga.row) {
@@ -739,6 +758,21 @@ __global__ __launch_bounds__(kBlock) void k_backproject_gather(WorkList<GatherIt
                 }
             }
         }
+    }
+    if constexpr (AS > 1) {
+        // the angle groups' sums, added to group 0's in group order
+        if (ag > 0) {
+#pragma unroll
+            for (int r = 0; r < kGatherRows; ++r)
+                red[(((ag - 1) * kRowBlocks + rb) * kGatherRows + r) * kWave + lane] = acc[r];
+        }
+        __syncthreads();
+        if (ag > 0) return;
+#pragma unroll
+        for (int q = 1; q < AS; ++q)
+#pragma unroll
+            for (int r = 0; r < kGatherRows; ++r)
+                acc[r] += red[(((q - 1) * kRowBlocks + rb) * kGatherRows + r) * kWave + lane];
     }
     if (lane == 0 || j >= nx) return;
     const size_t plane = static_cast<size_t>(nx) * ny;
@@ -822,15 +856,20 @@ static ps_status backproject_many_t(const BackCall *calls, int n, hipStream_t st
     std::vector<BackItem<T>> items;
     std::vector<BackPlan> plans;
     std::vector<int> call_of;
-    ListBuilder<GatherItem<T>> gl[2];   // rows per wave 2 and 4
+    ListBuilder<GatherItem<T>> gl[6];   // rows per wave {2, 4} x angle split {1, 2, 4}
     auto flush_gather = [&](int which) -> ps_status {
         ListBuilder<GatherItem<T>> &b = gl[which];
         if (b.empty()) return PS_OK;
         timer_mark(KC_BP_GATHER, st, true);
-        if (which == 0)
-            hipLaunchKernelGGL((k_backproject_gather<T, 2>), dim3(b.blocks), dim3(kBlock), 0, st, b.wl);
-        else
-            hipLaunchKernelGGL((k_backproject_gather<T, 4>), dim3(b.blocks), dim3(kBlock), 0, st, b.wl);
+        const dim3 grid(b.blocks), block(kBlock);
+        switch (which) {
+        case 0: hipLaunchKernelGGL((k_backproject_gather<T, 2, 1>), grid, block, 0, st, b.wl); break;
+        case 1: hipLaunchKernelGGL((k_backproject_gather<T, 2, 2>), grid, block, 0, st, b.wl); break;
+        case 2: hipLaunchKernelGGL((k_backproject_gather<T, 2, 4>), grid, block, 0, st, b.wl); break;
+        case 3: hipLaunchKernelGGL((k_backproject_gather<T, 4, 1>), grid, block, 0, st, b.wl); break;
+        case 4: hipLaunchKernelGGL((k_backproject_gather<T, 4, 2>), grid, block, 0, st, b.wl); break;
+        default: hipLaunchKernelGGL((k_backproject_gather<T, 4, 4>), grid, block, 0, st, b.wl); break;
+        }
         PS_LAUNCHED("k_backproject_gather");
         timer_mark(KC_BP_GATHER, st, false);
         b.clear();
@@ -854,10 +893,11 @@ static ps_status backproject_many_t(const BackCall *calls, int n, hipStream_t st
             gi.nx = d.nx;
             gi.ny = d.ny;
             gi.nbins = d.n_bins;
-            const int rows = gather_rows(g, bc.subset);
-            const int which = rows == 2 ? 0 : 1;
+            const int rows = gather_rows(g, bc.subset), split = gather_split(g, bc.subset);
+            const int which = (rows == 2 ? 0 : 3) + (split == 1 ? 0 : split == 2 ? 1 : 2);
+            const int tile_rows = (4 / split) * rows;
             gi.tiles_x = (d.nx + kGatherTX - 1) / kGatherTX;
-            gi.tiles_y = (d.ny + 4 * rows - 1) / (4 * rows);
+            gi.tiles_y = (d.ny + tile_rows - 1) / tile_rows;
             gi.mode = bc.mode;
             const long blocks = static_cast<long>(gi.tiles_x) * gi.tiles_y * d.nz;
             if (blocks > (1L << 30)) return fail(PS_EUNSUPPORTED, "backprojector grid too large");
@@ -950,8 +990,8 @@ static ps_status backproject_many_t(const BackCall *calls, int n, hipStream_t st
         PS_LAUNCHED("k_backproject_combine");
         timer_mark(KC_BP_COMBINE, st, false);
     }
-    PS_TRY(flush_gather(0));
-    return flush_gather(1);
+    for (int which = 0; which < 6; ++which) PS_TRY(flush_gather(which));
+    return PS_OK;
 }
 
 ps_status launch_backproject_many(const BackCall *calls, int n, hipStream_t st) {

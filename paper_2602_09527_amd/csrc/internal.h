@@ -266,6 +266,7 @@ size_t back_workspace(const ps_geometry *g, int subset);
 enum BackMethod { BP_SCATTER = 1, BP_GATHER = 2 };
 int back_method(const ps_geometry *g, int subset);   // BP_SCATTER or BP_GATHER
 int gather_rows(const ps_geometry *g, int subset);   // rows per wave of the gather tiles: 2 or 4
+int gather_split(const ps_geometry *g, int subset);  // waves sharing a gather tile's rows: 1, 2 or 4
 struct BackCall {
     const ps_geometry *g;
     int subset;

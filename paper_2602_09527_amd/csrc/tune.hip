@@ -137,6 +137,7 @@ extern "C" ps_status geometry_get_plan(const ps_geometry *g, ps_plan *out) {
     out->bp_method_full = back_method(g, -1);
     out->bp_method_subset = back_method(g, 0);
     out->bp_gather_rows = gather_rows(g, 0);
+    out->bp_gather_split = gather_split(g, 0);
     out->fgp3d_chunk = fgp3d_chunk_of(g);
     fgp_tile_of(g, &out->fgp_waves, &out->fgp_rows);
     out->fgp3d_form = fgp3d_form_of(g);
@@ -161,6 +162,8 @@ extern "C" ps_status geometry_set_plan(ps_geometry *g, const ps_plan *p) {
         return fail(PS_EINVAL, "bp_method must be 0 (automatic), 1 (scatter) or 2 (gather)");
     if (p->bp_gather_rows != 0 && p->bp_gather_rows != 2 && p->bp_gather_rows != 4)
         return fail(PS_EINVAL, "bp_gather_rows must be 0, 2 or 4");
+    if (p->bp_gather_split != 0 && p->bp_gather_split != 1 && p->bp_gather_split != 2 && p->bp_gather_split != 4)
+        return fail(PS_EINVAL, "bp_gather_split must be 0, 1, 2 or 4");
     if (p->fgp3d_chunk < 0 || p->fgp3d_chunk > 256) return fail(PS_EINVAL, "fgp3d_chunk must be in [0, 256]");
     if (p->fgp3d_form < 0 || p->fgp3d_form > kF3Forms) return fail(PS_EINVAL, "fgp3d_form must be in [0, %d]", kF3Forms);
     if (!(p->fgp_waves == 0 && p->fgp_rows == 0) && !fgp_tile_ok(p->fgp_waves, p->fgp_rows))
@@ -240,9 +243,10 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
         g->plan = best;
         const int auto_method = back_method(g, subset);
         const BackPlan auto_bp = back_plan(g, subset);
-        // candidate (method, strip, groups); the automatic choice first
+        // candidate (method, strip, groups) or (gather, rows, angle split); the automatic first
         std::vector<std::array<int, 3>> cand;
-        if (auto_method == BP_GATHER) cand.push_back({BP_GATHER, gather_rows(g, subset), 0});
+        const int auto_rows = gather_rows(g, subset), auto_split = gather_split(g, subset);
+        if (auto_method == BP_GATHER) cand.push_back({BP_GATHER, auto_rows, auto_split});
         cand.push_back({BP_SCATTER, auto_bp.strip, auto_bp.groups});
         for (int s : {8, 4, 2})
             for (int G : {1, 2, 4, 8, 16})
@@ -250,7 +254,9 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
                     cand.push_back({BP_SCATTER, s, G});
         if (g->gather_ok)
             for (int rows : {2, 4})
-                if (!(auto_method == BP_GATHER && rows == gather_rows(g, subset))) cand.push_back({BP_GATHER, rows, 0});
+                for (int split : {1, 2, 4})
+                    if (!(auto_method == BP_GATHER && rows == auto_rows && split == auto_split))
+                        cand.push_back({BP_GATHER, rows, split});
         float best_ms = 0.f;
         std::array<int, 3> pick = cand[0];
         bool have = false;
@@ -266,6 +272,7 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
                 gr = cand[c][2];
             } else {
                 trial.bp_gather_rows = cand[c][1];
+                trial.bp_gather_split = cand[c][2];
             }
             g->plan = trial;
             if (cand[c][0] == BP_SCATTER) {
@@ -298,7 +305,8 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
                 best.bp_strip_subset = pick[1];
                 best.bp_groups_subset = pick[2];
             } else {
-                best.bp_gather_rows = pick[1];   // the subset calls dominate: their tile height
+                best.bp_gather_rows = pick[1];   // the subset calls dominate: their tile
+                best.bp_gather_split = pick[2];
             }
         }
     }

@@ -177,13 +177,16 @@ def test_tv_prox_full_size_512(orc):
 
 @pytest.mark.parametrize("dtype,tol", [(torch.float32, 1e-5), (torch.float64, 1e-12)])
 @pytest.mark.parametrize("shape", SHAPES)
-@pytest.mark.parametrize("method", [1, 2])
-def test_backproject_methods_parity(orc, shape, dtype, tol, method):
+@pytest.mark.parametrize("method,rows,split", [(1, 0, 0), (2, 0, 0), (2, 2, 2), (2, 4, 2), (2, 2, 4),
+                                               (2, 4, 4)])
+def test_backproject_methods_parity(orc, shape, dtype, tol, method, rows, split):
     # both backprojector methods forced for all angles and for subsets (the gather applies where
-    # adjacent rays are at least one pixel apart; elsewhere the scatter serves the call)
+    # adjacent rays are at least one pixel apart; elsewhere the scatter serves the call), the
+    # gather with its tiles' rows per wave and angle split
     from paper_2602_09527_amd import api
     g, o = _pair(orc, shape, dtype)
-    g.set_plan(dict(bp_method_full=method, bp_method_subset=method))
+    g.set_plan(dict(bp_method_full=method, bp_method_subset=method, bp_gather_rows=rows,
+                    bp_gather_split=split))
     rng = np.random.default_rng(40 + method)
     for subset in [-1] + list(range(g.n_subsets)):
         y = rng.standard_normal(g.sino_shape(subset))

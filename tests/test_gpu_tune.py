@@ -77,6 +77,26 @@ def test_forced_plans_keep_parity(orc, plan):
     assert _rel(z.cpu().numpy(), z_ref) <= 1e-5
 
 
+@pytest.mark.parametrize("dtype,tol", [(torch.float32, 1e-4), (torch.float64, 1e-9)])
+@pytest.mark.parametrize("rows,split", [(2, 2), (4, 4)])
+def test_gather_split_solve_matches_oracle(orc, dtype, tol, rows, split):
+    # the 128^2 solve (180 x 128, 10 subsets) with the pixel-driven backprojector whose waves
+    # split the angles (its fused SVRG / ProxSkip update included), 10 epochs
+    from paper_2602_09527_amd import api, synth, workloads
+    w = workloads.SMALL_2D
+    prob = synth.make_problem(w.nx, w.ny, w.n_angles, w.n_bins, seed=w.seed, with_phantom=False)
+    g = api.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=w.n_subsets, dtype=dtype)
+    g.set_plan(dict(bp_method_full=2, bp_method_subset=2, bp_gather_rows=rows, bp_gather_split=split))
+    o = orc.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=w.n_subsets)
+    L = json.load(open(__file__.replace("test_gpu_tune.py", "golden/lipschitz.json")))[w.key]["L"]
+    kw = dict(gamma=1.0 / L, p=w.p, alpha=w.alpha, fgp_inner=w.fgp_inner, n_epochs=10,
+              nonneg=True, seed=w.seed + 2)
+    x, _, _, st = api.solve(g, torch.from_numpy(prob.b).to("cuda", dtype), api.SolverParams(**kw))
+    xo, _, _, so, _ = orc.proxskip_svrg(o, prob.b, **kw)
+    assert st["prox_calls"] == so["prox_calls"] > 0
+    assert _rel(x.cpu().double().numpy(), xo) <= tol
+
+
 def test_tuned_solve_matches_oracle(orc):
     from paper_2602_09527_amd import api, synth, workloads
     w = workloads.SMALL_2D
