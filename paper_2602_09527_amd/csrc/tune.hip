@@ -260,6 +260,7 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
         float best_ms = 0.f;
         std::array<int, 3> pick = cand[0];
         bool have = false;
+        std::vector<std::pair<float, size_t>> timed;   // (ms, candidate)
         const int r = reps;
         for (size_t c = 0; c < cand.size(); ++c) {
             ps_plan trial = best;
@@ -286,12 +287,30 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
                 return launch_backproject(g, subset, w + L.y, w + L.img, BP_OVERWRITE, nullptr, w + L.bws,
                                           L.bws_bytes, st);
             }, r, st, tm, &ms)));
-            if (!have || ms < best_ms * (pick == cand[0] ? kMinGain : 1.0f)) {
-                best_ms = ms;
-                pick = cand[c];
+            timed.push_back({ms, c});
+            if (c == 0 && full && ms > kLongLaunchMs) break;
+        }
+        // the method and plan: the automatic one unless another is 3% faster, else the fastest
+        for (const auto &t : timed) {
+            if (!have || t.first < best_ms * (pick == cand[0] ? kMinGain : 1.0f)) {
+                best_ms = t.first;
+                pick = cand[t.second];
                 have = true;
             }
-            if (c == 0 && full && ms > kLongLaunchMs) break;
+        }
+        // a scatter pick gives way to a scatter plan with fewer angle groups that is within 3%
+        // of it (the timing noise): each group writes its own partial images, whose bytes are
+        // most of the launch's HBM traffic
+        if (pick[0] == BP_SCATTER) {
+            const float limit = best_ms / kMinGain;
+            for (const auto &t : timed) {
+                const std::array<int, 3> &k = cand[t.second];
+                if (k[0] != BP_SCATTER || t.first > limit) continue;
+                if (k[2] < pick[2] || (k[2] == pick[2] && t.first < best_ms)) {
+                    best_ms = t.first;
+                    pick = k;
+                }
+            }
         }
         if (full) {
             best.bp_method_full = pick[0];
