@@ -212,6 +212,7 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
         float best_ms = 0.f;
         int best_s = 0;
         bool have = false;
+        std::vector<std::pair<float, int>> timed;   // (ms, split)
         g->plan = best;
         const int auto_split = full ? proj_plan(g, d.n_angles).split : proj_plan(g, max_subset_count(g)).split;
         std::vector<int> cand{auto_split};
@@ -231,8 +232,14 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
                 best_s = cand[c];
                 have = true;
             }
+            timed.push_back({ms, cand[c]});
             if (c == 0 && full && ms > kLongLaunchMs) break;
         }
+        // the pick gives way to a smaller split within 3% of its time (the timing noise): every
+        // split writes one partial sum per ray, most of the launch's HBM traffic
+        const float limit = best_ms / kMinGain;
+        for (const auto &t : timed)
+            if (t.second < best_s && t.first <= limit) best_s = t.second;
         (full ? best.proj_split_full : best.proj_split_subset) = best_s;
     }
 
