@@ -107,6 +107,9 @@ PS_API int32_t subset_size(const ps_geometry *geom, int32_t subset);
  *                  split-th angle (their sums added in LDS in wave order): 1, 2 or 4; the tile
  *                  is then 63 columns x (4 / split) x rows.  0 = automatic: 4 when the
  *                  unsplit tiles number fewer than 256, 2 below 1024, else 1.
+ *   fgp_cols       2D FGP columns per lane: 1 (tiles 64 columns wide) or 2 (128 wide: the halo
+ *                  of T + 1 columns per side is a smaller share); 0 = automatic (1).  Does not
+ *                  change results, not even their rounding.
  *   fgp3d_chunk    slices each workgroup of the 3D FGP marches through: 1..256, 0 = automatic
  *                  (4 for one iteration per launch, 16 for two)
  *   fgp_waves, fgp_rows  2D FGP tile: waves per workgroup and image rows per wave, one of
@@ -132,6 +135,7 @@ typedef struct {
     int32_t fgp_waves, fgp_rows;
     int32_t fgp3d_form;
     int32_t bp_gather_split;
+    int32_t fgp_cols;
 } ps_plan;
 
 /* The plan in effect (automatic choices filled in) / replace the overrides.  set: fields out of

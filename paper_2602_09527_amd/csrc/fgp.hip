@@ -35,6 +35,7 @@ constexpr int kFgpWaves = 4;
 template <typename T>
 constexpr int fgp_max_iters() { return std::is_same<T, double>::value ? 8 : 16; }
 constexpr int kFgpAutoIters = 8;
+constexpr int kFgpAutoCols = 1;     // columns per lane unless a plan asks
 
 template <typename T>
 struct FgpCoef {
@@ -54,6 +55,7 @@ struct FgpFinal {
 // taller tiles recompute less halo but give fewer workgroups.
 struct FgpTile {
     int waves, rows;
+    int cols = 1;   // columns per lane (the tile is 64 cols wide)
 };
 constexpr FgpTile kFgpTiles[] = {{4, 4}, {4, 8}, {8, 2}, {8, 4}, {8, 8}, {16, 2}, {16, 4}};
 
@@ -94,10 +96,16 @@ struct FgpItem {
     FgpFinal<T> fin;
 };
 
-template <typename T, int W, int RW>
+// CX columns per lane: the tile is 64 CX columns wide, so its halo of T + 1 columns on each side
+// is a smaller share of it (T = 15: 32 of 64 columns are interior with one column per lane, 96 of
+// 128 with two).  A lane's two columns are neighbours in registers; across lanes the DPP shifts
+// carry the edge columns.  Every value is formed by the same expressions whatever the tile.
+template <typename T, int W, int RW, int CX>
 __global__ __launch_bounds__(W * kFgpEX) void k_fgp2d(WorkList<FgpItem<T>> wl) {
+    static_assert(CX == 1 || CX == 2, "columns per lane");
     constexpr int EY = W * RW;
-    __shared__ T xch[2][W][kFgpEX];   // last-row values (down) and first-row values (up)
+    constexpr int EX = kFgpEX * CX;
+    __shared__ T xch[2][W][CX][kFgpEX];   // last-row values (down) and first-row values (up)
     int local;
     const FgpItem<T> &it = wl.item[work_item(wl, local)];
     const int nx = it.nx, ny = it.ny, halo = it.halo, iters = it.iters, nonneg = it.nonneg;
@@ -110,84 +118,109 @@ __global__ __launch_bounds__(W * kFgpEX) void k_fgp2d(WorkList<FgpItem<T>> wl) {
     const T *__restrict__ v = it.v + zoff;
     const T *__restrict__ p_in = it.p_in + zoff;
     const T *__restrict__ r_in = it.r_in + zoff;
-    const int TX = kFgpEX - 2 * halo, TY = EY - 2 * halo;
+    const int TX = EX - 2 * halo, TY = EY - 2 * halo;
     const int lane = threadIdx.x % kFgpEX, wave = threadIdx.x / kFgpEX;
     const int i0 = ty * TY - halo + wave * RW;   // image row of this wave's row 0
-    const int gj = tx * TX - halo + lane;
-    const bool col_in = gj >= 0 && gj < nx;
-    const bool has_left = gj > 0 && lane > 0, has_right = gj < nx - 1 && lane < kFgpEX - 1;
+    const int gj0 = tx * TX - halo + CX * lane;  // image column of this lane's column 0
+    bool has_left[CX], has_right[CX], col_in[CX];
+#pragma unroll
+    for (int c = 0; c < CX; ++c) {
+        const int gj = gj0 + c;
+        col_in[c] = gj >= 0 && gj < nx;
+        has_left[c] = gj > 0 && (c > 0 || lane > 0);
+        has_right[c] = gj < nx - 1 && (c < CX - 1 || lane < kFgpEX - 1);
+    }
 
-    T vv[RW], px[RW], py[RW], rx[RW], ry[RW], zz[RW];
-    bool in[RW];
+    T vv[RW][CX], px[RW][CX], py[RW][CX], rx[RW][CX], ry[RW][CX], zz[RW][CX];
+    bool in[RW][CX];
 #pragma unroll
     for (int r = 0; r < RW; ++r) {
         const int gi = i0 + r;
-        in[r] = col_in && gi >= 0 && gi < ny;
-        if (in[r]) {
-            const size_t q = static_cast<size_t>(gi) * nx + gj;
-            vv[r] = v[q];
-            px[r] = p_in[q];
-            py[r] = p_in[q + it.ncomp];
-            rx[r] = r_in[q];
-            ry[r] = r_in[q + it.ncomp];
-        } else {
-            vv[r] = px[r] = py[r] = rx[r] = ry[r] = T(0);
+#pragma unroll
+        for (int c = 0; c < CX; ++c) {
+            in[r][c] = col_in[c] && gi >= 0 && gi < ny;
+            if (in[r][c]) {
+                const size_t q = static_cast<size_t>(gi) * nx + gj0 + c;
+                vv[r][c] = v[q];
+                px[r][c] = p_in[q];
+                py[r][c] = p_in[q + it.ncomp];
+                rx[r][c] = r_in[q];
+                ry[r][c] = r_in[q + it.ncomp];
+            } else {
+                vv[r][c] = px[r][c] = py[r][c] = rx[r][c] = ry[r][c] = T(0);
+            }
         }
     }
 
     for (int t = 0; t < iters; ++t) {
         // z = P_C(v - tau D^T r): needs r^x of the left neighbour and r^y of the row above
-        xch[0][wave][lane] = ry[RW - 1];
+#pragma unroll
+        for (int c = 0; c < CX; ++c) xch[0][wave][c][lane] = ry[RW - 1][c];
         __syncthreads();
-        const T ry_above = wave > 0 ? xch[0][wave - 1][lane] : T(0);
+        T ry_above[CX];
+#pragma unroll
+        for (int c = 0; c < CX; ++c) ry_above[c] = wave > 0 ? xch[0][wave - 1][c][lane] : T(0);
 #pragma unroll
         for (int r = 0; r < RW; ++r) {
             const int gi = i0 + r;
-            const T rxl = lane_from_left(rx[r]);
-            const T rx_here = (gj < nx - 1) ? rx[r] : T(0);
-            const T rx_left = has_left ? rxl : T(0);
-            const T ry_here = (gi < ny - 1) ? ry[r] : T(0);
-            const T ry_up = (gi > 0) ? (r > 0 ? ry[r - 1] : ry_above) : T(0);
-            T zv = vv[r] - tau * ((rx_left - rx_here) + (ry_up - ry_here));
-            if (nonneg && zv < T(0)) zv = T(0);
-            zz[r] = in[r] ? zv : T(0);
+            const T rxl = lane_from_left(rx[r][CX - 1]);
+#pragma unroll
+            for (int c = 0; c < CX; ++c) {
+                const int gj = gj0 + c;
+                const T rx_here = (gj < nx - 1) ? rx[r][c] : T(0);
+                const T rx_left = has_left[c] ? (c == 0 ? rxl : rx[r][c > 0 ? c - 1 : 0]) : T(0);
+                const T ry_here = (gi < ny - 1) ? ry[r][c] : T(0);
+                const T ry_up = (gi > 0) ? (r > 0 ? ry[r > 0 ? r - 1 : 0][c] : ry_above[c]) : T(0);
+                T zv = vv[r][c] - tau * ((rx_left - rx_here) + (ry_up - ry_here));
+                if (nonneg && zv < T(0)) zv = T(0);
+                zz[r][c] = in[r][c] ? zv : T(0);
+            }
         }
         // p+ = P_P(r + step D z); r+ = p+ + c (p+ - p): needs z of the right neighbour and below
-        xch[1][wave][lane] = zz[0];
+#pragma unroll
+        for (int c = 0; c < CX; ++c) xch[1][wave][c][lane] = zz[0][c];
         __syncthreads();
-        const T z_below = wave < W - 1 ? xch[1][wave + 1][lane] : T(0);
-        const T c = it.cf.c[t];
+        T z_below[CX];
+#pragma unroll
+        for (int c = 0; c < CX; ++c) z_below[c] = wave < W - 1 ? xch[1][wave + 1][c][lane] : T(0);
+        const T cm = it.cf.c[t];
 #pragma unroll
         for (int r = 0; r < RW; ++r) {
             const int gi = i0 + r;
-            const T zr = lane_from_right(zz[r]);
-            const T zb = r < RW - 1 ? zz[r + 1] : z_below;
-            const T dzx = has_right ? zr - zz[r] : T(0);
-            const T dzy = (gi < ny - 1) ? zb - zz[r] : T(0);
-            T ax = fma(step, dzx, rx[r]), ay = fma(step, dzy, ry[r]);
-            const T n2 = fma(ax, ax, ay * ay);
-            if (n2 > T(1)) {
-                if constexpr (std::is_same<T, float>::value) {
-                    const T sc = __frsqrt_rn(n2);   // 1 / ||(ax, ay)||
-                    ax *= sc;
-                    ay *= sc;
-                } else {
-                    const T nrm = sqrt(n2);
-                    ax /= nrm;
-                    ay /= nrm;
+            const T zrl = lane_from_right(zz[r][0]);
+#pragma unroll
+            for (int c = 0; c < CX; ++c) {
+                const T zr = c == CX - 1 ? zrl : zz[r][c < CX - 1 ? c + 1 : 0];
+                const T zb = r < RW - 1 ? zz[r < RW - 1 ? r + 1 : 0][c] : z_below[c];
+                const T dzx = has_right[c] ? zr - zz[r][c] : T(0);
+                const T dzy = (gi < ny - 1) ? zb - zz[r][c] : T(0);
+                T ax = fma(step, dzx, rx[r][c]), ay = fma(step, dzy, ry[r][c]);
+                const T n2 = fma(ax, ax, ay * ay);
+                if (n2 > T(1)) {
+                    if constexpr (std::is_same<T, float>::value) {
+                        const T sc = __frsqrt_rn(n2);   // 1 / ||(ax, ay)||
+                        ax *= sc;
+                        ay *= sc;
+                    } else {
+                        const T nrm = sqrt(n2);
+                        ax /= nrm;
+                        ay /= nrm;
+                    }
                 }
-            }
-            if (in[r]) {
-                rx[r] = fma(c, ax - px[r], ax);
-                ry[r] = fma(c, ay - py[r], ay);
-                px[r] = ax;
-                py[r] = ay;
+                if (in[r][c]) {
+                    rx[r][c] = fma(cm, ax - px[r][c], ax);
+                    ry[r][c] = fma(cm, ay - py[r][c], ay);
+                    px[r][c] = ax;
+                    py[r][c] = ay;
+                }
             }
         }
     }
 
     // write back the interior
-    const bool col_int = lane >= halo && lane < halo + TX;
+    bool col_int[CX];
+#pragma unroll
+    for (int c = 0; c < CX; ++c) col_int[c] = CX * lane + c >= halo && CX * lane + c < halo + TX;
     const size_t nc = it.ncomp;
     if (fin.mode == 0) {
         T *__restrict__ p_out = it.p_out + zoff;
@@ -195,40 +228,51 @@ __global__ __launch_bounds__(W * kFgpEX) void k_fgp2d(WorkList<FgpItem<T>> wl) {
 #pragma unroll
         for (int r = 0; r < RW; ++r) {
             const int ey = wave * RW + r;
-            if (!in[r] || !col_int || ey < halo || ey >= halo + TY) continue;
-            const size_t q = static_cast<size_t>(i0 + r) * nx + gj;
-            p_out[q] = px[r];
-            p_out[q + nc] = py[r];
-            r_out[q] = rx[r];
-            r_out[q + nc] = ry[r];
+#pragma unroll
+            for (int c = 0; c < CX; ++c) {
+                if (!in[r][c] || !col_int[c] || ey < halo || ey >= halo + TY) continue;
+                const size_t q = static_cast<size_t>(i0 + r) * nx + gj0 + c;
+                p_out[q] = px[r][c];
+                p_out[q + nc] = py[r][c];
+                r_out[q] = rx[r][c];
+                r_out[q + nc] = ry[r][c];
+            }
         }
         return;
     }
     // z = P_C(v - tau D^T p_K)
     __syncthreads();
-    xch[0][wave][lane] = py[RW - 1];
+#pragma unroll
+    for (int c = 0; c < CX; ++c) xch[0][wave][c][lane] = py[RW - 1][c];
     __syncthreads();
-    const T py_above = wave > 0 ? xch[0][wave - 1][lane] : T(0);
+    T py_above[CX];
+#pragma unroll
+    for (int c = 0; c < CX; ++c) py_above[c] = wave > 0 ? xch[0][wave - 1][c][lane] : T(0);
 #pragma unroll
     for (int r = 0; r < RW; ++r) {
         const int gi = i0 + r, ey = wave * RW + r;
-        const T pxl = lane_from_left(px[r]);
-        if (!in[r] || !col_int || ey < halo || ey >= halo + TY) continue;
-        const T ph = (gj < nx - 1) ? px[r] : T(0);
-        const T pl = (gj > 0) ? pxl : T(0);
-        const T qh = (gi < ny - 1) ? py[r] : T(0);
-        const T qu = (gi > 0) ? (r > 0 ? py[r - 1] : py_above) : T(0);
-        T zv = vv[r] - tau * ((pl - ph) + (qu - qh));
-        if (nonneg && zv < T(0)) zv = T(0);
-        const size_t q = zoff + static_cast<size_t>(gi) * nx + gj;
-        if (fin.mode == 1) {
-            fin.z[q] = zv;
-        } else {
-            fin.x[q] = zv;
-            if (fin.mode == 2) fin.h[q] = fin.hscale * (zv - vv[r]);
+        const T pxl_lane = lane_from_left(px[r][CX - 1]);
+#pragma unroll
+        for (int c = 0; c < CX; ++c) {
+            const int gj = gj0 + c;
+            const T pxl = c == 0 ? pxl_lane : px[r][c > 0 ? c - 1 : 0];
+            if (!in[r][c] || !col_int[c] || ey < halo || ey >= halo + TY) continue;
+            const T ph = (gj < nx - 1) ? px[r][c] : T(0);
+            const T pl = (gj > 0) ? pxl : T(0);
+            const T qh = (gi < ny - 1) ? py[r][c] : T(0);
+            const T qu = (gi > 0) ? (r > 0 ? py[r > 0 ? r - 1 : 0][c] : py_above[c]) : T(0);
+            T zv = vv[r][c] - tau * ((pl - ph) + (qu - qh));
+            if (nonneg && zv < T(0)) zv = T(0);
+            const size_t q = zoff + static_cast<size_t>(gi) * nx + gj;
+            if (fin.mode == 1) {
+                fin.z[q] = zv;
+            } else {
+                fin.x[q] = zv;
+                if (fin.mode == 2) fin.h[q] = fin.hscale * (zv - vv[r][c]);
+            }
+            fin.dual_out[q] = px[r][c];
+            fin.dual_out[q + nc] = py[r][c];
         }
-        fin.dual_out[q] = px[r];
-        fin.dual_out[q + nc] = py[r];
     }
 }
 
@@ -768,6 +812,10 @@ int fgp3d_chunk_of(const ps_geometry *g) {
 int fgp_max_iters_of(const ps_geometry *g) {
     return g->elem == sizeof(double) ? fgp_max_iters<double>() : fgp_max_iters<float>();
 }
+int fgp_cols_of(const ps_geometry *g) {
+    const int c = g->plan.fgp_cols;
+    return c == 1 || c == 2 ? c : kFgpAutoCols;
+}
 static void fgp_auto_tile(const ps_geometry *g, int *waves, int *rows) {
     // 8 x 4 (FP32), 16 x 2 (FP64): at or near the fastest from 256^2 to 512^2 alone, and the
     // best throughput measured for batches (64 x 128^2)
@@ -848,9 +896,11 @@ static ps_status fgp2d_program(const FgpCall &c, bool shared, FgpProgram<T> &pro
     int tmax;
     if (shared) {
         fgp_auto_tile(g, &prog.tile.waves, &prog.tile.rows);
+        prog.tile.cols = kFgpAutoCols;
         tmax = std::min(kFgpAutoIters, fgp_cap(prog.tile.waves, prog.tile.rows));
     } else {
         fgp_tile_of(g, &prog.tile.waves, &prog.tile.rows);
+        prog.tile.cols = fgp_cols_of(g);
         tmax = fgp_iters_per_launch(g);
     }
     const int EY = prog.tile.waves * prog.tile.rows;
@@ -861,7 +911,7 @@ static ps_status fgp2d_program(const FgpCall &c, bool shared, FgpProgram<T> &pro
     for (int L = 0; L < launches; ++L) {
         const int iters = std::min(tmax, K - done);
         const int halo = iters + 1;
-        const int TX = kFgpEX - 2 * halo, TY = EY - 2 * halo;
+        const int TX = kFgpEX * prog.tile.cols - 2 * halo, TY = EY - 2 * halo;
         FgpItem<T> it{};
         it.v = vin;
         it.p_in = in_p;
@@ -905,9 +955,12 @@ static ps_status fgp2d_program(const FgpCall &c, bool shared, FgpProgram<T> &pro
 }
 
 template <typename T, int W, int RW>
-static void launch_fgp2d_tile(const WorkList<FgpItem<T>> &wl, int blocks, hipStream_t st) {
+static void launch_fgp2d_tile(const WorkList<FgpItem<T>> &wl, int blocks, int cols, hipStream_t st) {
     timer_mark(KC_FGP2D, st, true);
-    hipLaunchKernelGGL((k_fgp2d<T, W, RW>), dim3(blocks), dim3(W * kFgpEX), 0, st, wl);
+    if (cols == 2)
+        hipLaunchKernelGGL((k_fgp2d<T, W, RW, 2>), dim3(blocks), dim3(W * kFgpEX), 0, st, wl);
+    else
+        hipLaunchKernelGGL((k_fgp2d<T, W, RW, 1>), dim3(blocks), dim3(W * kFgpEX), 0, st, wl);
     timer_mark(KC_FGP2D, st, false);
 }
 
@@ -917,13 +970,13 @@ static_assert(sizeof(WorkList<FgpItem<float>>) <= 4096 && sizeof(WorkList<FgpIte
 template <typename T>
 static ps_status launch_fgp2d_list(const WorkList<FgpItem<T>> &wl, int blocks, FgpTile tile, hipStream_t st) {
     switch (tile.waves * 100 + tile.rows) {
-    case 404: launch_fgp2d_tile<T, 4, 4>(wl, blocks, st); break;
-    case 408: launch_fgp2d_tile<T, 4, 8>(wl, blocks, st); break;
-    case 802: launch_fgp2d_tile<T, 8, 2>(wl, blocks, st); break;
-    case 804: launch_fgp2d_tile<T, 8, 4>(wl, blocks, st); break;
-    case 808: launch_fgp2d_tile<T, 8, 8>(wl, blocks, st); break;
-    case 1602: launch_fgp2d_tile<T, 16, 2>(wl, blocks, st); break;
-    case 1604: launch_fgp2d_tile<T, 16, 4>(wl, blocks, st); break;
+    case 404: launch_fgp2d_tile<T, 4, 4>(wl, blocks, tile.cols, st); break;
+    case 408: launch_fgp2d_tile<T, 4, 8>(wl, blocks, tile.cols, st); break;
+    case 802: launch_fgp2d_tile<T, 8, 2>(wl, blocks, tile.cols, st); break;
+    case 804: launch_fgp2d_tile<T, 8, 4>(wl, blocks, tile.cols, st); break;
+    case 808: launch_fgp2d_tile<T, 8, 8>(wl, blocks, tile.cols, st); break;
+    case 1602: launch_fgp2d_tile<T, 16, 2>(wl, blocks, tile.cols, st); break;
+    case 1604: launch_fgp2d_tile<T, 16, 4>(wl, blocks, tile.cols, st); break;
     default: return fail(PS_EINVAL, "FGP tile %d x %d not built", tile.waves, tile.rows);
     }
     PS_LAUNCHED("k_fgp2d");
@@ -1100,14 +1153,17 @@ static ps_status fgp_many_t(const FgpCall *calls, int n, hipStream_t st) {
     std::vector<FgpTile> tiles;
     for (const auto &p : progs) {
         bool seen = false;
-        for (const FgpTile &t : tiles) seen = seen || (t.waves == p.tile.waves && t.rows == p.tile.rows);
+        for (const FgpTile &t : tiles)
+            seen = seen || (t.waves == p.tile.waves && t.rows == p.tile.rows && t.cols == p.tile.cols);
         if (!seen) tiles.push_back(p.tile);
     }
     for (size_t r = 0; r < rounds; ++r) {
         for (const FgpTile &tile : tiles) {
             ListBuilder<FgpItem<T>> lb;
             for (const auto &p : progs) {
-                if (r >= p.launches.size() || p.tile.waves != tile.waves || p.tile.rows != tile.rows) continue;
+                if (r >= p.launches.size() || p.tile.waves != tile.waves || p.tile.rows != tile.rows ||
+                    p.tile.cols != tile.cols)
+                    continue;
                 const FgpItem<T> &it = p.launches[r];
                 const long blocks = static_cast<long>(it.tiles_x) * it.tiles_y * (it.ncomp / (static_cast<size_t>(it.nx) * it.ny));
                 lb.add(it, static_cast<int>(blocks));

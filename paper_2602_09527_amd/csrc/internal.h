@@ -290,6 +290,7 @@ int fgp_iters_per_launch(const ps_geometry *g);
 int fgp_max_iters_of(const ps_geometry *g);
 bool fgp_tile_ok(int waves, int rows);                 // a built 2D FGP tile shape
 void fgp_tile_of(const ps_geometry *g, int *waves, int *rows);   // the shape in effect
+int fgp_cols_of(const ps_geometry *g);                            // 2D FGP columns per lane: 1 or 2
 constexpr int kF3Forms = 5;                                       // 3D launch forms 1..5
 int fgp3d_form_of(const ps_geometry *g);                          // 3D launch form in effect
 int fgp3d_chunk_of(const ps_geometry *g);                         // 3D z chunk in effect

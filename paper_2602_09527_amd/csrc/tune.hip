@@ -138,6 +138,7 @@ extern "C" ps_status geometry_get_plan(const ps_geometry *g, ps_plan *out) {
     out->bp_method_subset = back_method(g, 0);
     out->bp_gather_rows = gather_rows(g, 0);
     out->bp_gather_split = gather_split(g, 0);
+    out->fgp_cols = fgp_cols_of(g);
     out->fgp3d_chunk = fgp3d_chunk_of(g);
     fgp_tile_of(g, &out->fgp_waves, &out->fgp_rows);
     out->fgp3d_form = fgp3d_form_of(g);
@@ -164,6 +165,7 @@ extern "C" ps_status geometry_set_plan(ps_geometry *g, const ps_plan *p) {
         return fail(PS_EINVAL, "bp_gather_rows must be 0, 2 or 4");
     if (p->bp_gather_split != 0 && p->bp_gather_split != 1 && p->bp_gather_split != 2 && p->bp_gather_split != 4)
         return fail(PS_EINVAL, "bp_gather_split must be 0, 1, 2 or 4");
+    if (p->fgp_cols < 0 || p->fgp_cols > 2) return fail(PS_EINVAL, "fgp_cols must be 0, 1 or 2");
     if (p->fgp3d_chunk < 0 || p->fgp3d_chunk > 256) return fail(PS_EINVAL, "fgp3d_chunk must be in [0, 256]");
     if (p->fgp3d_form < 0 || p->fgp3d_form > kF3Forms) return fail(PS_EINVAL, "fgp3d_form must be in [0, %d]", kF3Forms);
     if (!(p->fgp_waves == 0 && p->fgp_rows == 0) && !fgp_tile_ok(p->fgp_waves, p->fgp_rows))
@@ -342,26 +344,29 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
     if (g->tv_dims == 2) {
         PS_TRY(fill(g, w + L.dual, 2 * n, st));
         g->plan = best;
-        g->plan.fgp_waves = g->plan.fgp_rows = g->plan.fgp_iters = 0;
+        g->plan.fgp_waves = g->plan.fgp_rows = g->plan.fgp_iters = g->plan.fgp_cols = 0;
         int auto_w, auto_r;
         fgp_tile_of(g, &auto_w, &auto_r);
-        const int auto_t = fgp_iters_per_launch(g);
-        std::vector<std::array<int, 3>> cands{{auto_w, auto_r, auto_t}};
-        for (int w8 : {4, 8, 16})
-            for (int r8 : {2, 4, 8}) {
-                if (!fgp_tile_ok(w8, r8)) continue;
-                const int cap = std::min(fgp_max_iters_of(g), w8 * r8 / 2 - 2);
-                for (int T = cap; T >= 2; --T)
-                    if (!(w8 == auto_w && r8 == auto_r && T == auto_t)) cands.push_back({w8, r8, T});
-            }
+        const int auto_t = fgp_iters_per_launch(g), auto_c = fgp_cols_of(g);
+        std::vector<std::array<int, 4>> cands{{auto_w, auto_r, auto_t, auto_c}};
+        for (int cx : {1, 2})
+            for (int w8 : {4, 8, 16})
+                for (int r8 : {2, 4, 8}) {
+                    if (!fgp_tile_ok(w8, r8)) continue;
+                    const int cap = std::min(fgp_max_iters_of(g), w8 * r8 / 2 - 2);
+                    for (int T = cap; T >= 2; --T)
+                        if (!(w8 == auto_w && r8 == auto_r && T == auto_t && cx == auto_c))
+                            cands.push_back({w8, r8, T, cx});
+                }
         float best_ms = 0.f;
-        int pick_t = 0, pick_w = 0, pick_r = 0;
+        int pick_t = 0, pick_w = 0, pick_r = 0, pick_c = 0;
         bool auto_best = true;
         for (size_t ci = 0; ci < cands.size(); ++ci) {
             ps_plan trial = best;
             trial.fgp_waves = cands[ci][0];
             trial.fgp_rows = cands[ci][1];
             trial.fgp_iters = cands[ci][2];
+            trial.fgp_cols = cands[ci][3];
             g->plan = trial;
             FgpOut o{};
             o.z = w + L.img;
@@ -374,12 +379,14 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
                 pick_w = cands[ci][0];
                 pick_r = cands[ci][1];
                 pick_t = cands[ci][2];
+                pick_c = cands[ci][3];
                 auto_best = ci == 0;
             }
         }
         best.fgp_iters = pick_t;
         best.fgp_waves = pick_w;
         best.fgp_rows = pick_r;
+        best.fgp_cols = pick_c;
     }
     // 3D FGP: launch form and slices per workgroup (10 inner iterations per timed call); the
     // automatic form with chunks of 16 is timed first

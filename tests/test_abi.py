@@ -156,7 +156,8 @@ def test_plan_get_set_and_validation(nat):
         for bad in (dict(proj_split_full=-1), dict(bp_groups_subset=17), dict(bp_strip_full=3),
                     dict(fgp_iters=17), dict(bp_method_subset=3), dict(fgp_waves=4, fgp_rows=2),
                     dict(fgp_waves=8), dict(fgp_rows=4), dict(fgp_waves=32, fgp_rows=2),
-                    dict(fgp3d_form=6), dict(fgp3d_form=-1), dict(fgp3d_chunk=257)):
+                    dict(fgp3d_form=6), dict(fgp3d_form=-1), dict(fgp3d_chunk=257),
+                    dict(bp_gather_split=3), dict(fgp_cols=3), dict(fgp_cols=-1)):
             assert lib.geometry_set_plan(h, C.byref(nat.Plan(**bad))) == nat.PS_EINVAL
         # a rejected plan leaves the previous one in place
         assert lib.geometry_get_plan(h, C.byref(got)) == nat.PS_OK and got.fgp_iters == 5

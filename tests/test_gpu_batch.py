@@ -99,15 +99,15 @@ def test_batch_member_matches_oracle(orc):
 def test_batch_with_different_fgp_tiles_bitwise_equals_alone():
     # solves whose 2D TV prox runs on different tile shapes share rounds but not launches
     from paper_2602_09527_amd import api
-    tiles = [(4, 8, 8), (16, 2, 5), (8, 8, 0), (16, 4, 3)]
+    tiles = [(4, 8, 8, 1), (16, 2, 5, 2), (8, 8, 0, 2), (16, 4, 3, 1)]
     mix = [(128, 128, 180, 128, 10, 21, torch.float32, {}),
            (96, 80, 90, 144, 5, 22, torch.float32, dict(fgp_inner=13)),
            (150, 97, 72, 160, 8, 23, torch.float32, dict(p=0.5)),
            (64, 64, 60, 96, 6, 24, torch.float64, dict(fgp_inner=7))]
     probs = []
-    for m, (w, r, t) in zip(mix, tiles):
+    for m, (w, r, t, cx) in zip(mix, tiles):
         g, b, prm = _problem(*m[:7], **m[7])
-        g.set_plan(dict(g.get_plan(), fgp_waves=w, fgp_rows=r, fgp_iters=t))
+        g.set_plan(dict(g.get_plan(), fgp_waves=w, fgp_rows=r, fgp_iters=t, fgp_cols=cx))
         assert (g.get_plan()["fgp_waves"], g.get_plan()["fgp_rows"]) == (w, r)
         probs.append((g, b, prm))
     alone = []

@@ -118,8 +118,9 @@ TILES = [(4, 4), (4, 8), (8, 2), (8, 4), (8, 8), (16, 2), (16, 4)]
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_fgp_tiles_bitwise_equal(orc, dtype):
-    # the tile shape and iterations per launch (up to 16 in FP32) decide only which workgroup
-    # computes a pixel: every (tile, T) gives the same bits, and those match the FP64 oracle
+    # the tile shape, columns per lane and iterations per launch (up to 16 in FP32) decide only
+    # which workgroup computes a pixel: every (tile, cols, T) gives the same bits, and those match
+    # the FP64 oracle
     from paper_2602_09527_amd import api
     nx, ny = 150, 97   # several tiles of every shape, ragged in both directions
     g = api.Geometry(nx, ny, 30, 40, n_subsets=2, dtype=dtype)
@@ -128,19 +129,21 @@ def test_fgp_tiles_bitwise_equal(orc, dtype):
     d0 = 0.3 * rng.standard_normal((2, 1, ny, nx))
     vt = torch.from_numpy(v).to("cuda", dtype)
     ref = None
-    for w, r in TILES:
-        for T in (1, 3, 8) + ((12, 16) if dtype == torch.float32 else ()):
-            g.set_plan(dict(fgp_waves=w, fgp_rows=r, fgp_iters=T))
-            assert g.get_plan()["fgp_iters"] == min(T, w * r // 2 - 2)
-            dual = torch.from_numpy(d0).to("cuda", dtype)
-            z = api.tv_prox(g, vt, 0.05, 29, dual=dual)
-            torch.cuda.synchronize()
-            if ref is None:
-                ref = (z.clone(), dual.clone())
-                z_ref = orc.tv_prox_fgp(v, 0.05, 29, nonneg=True, dual=d0.copy())
-                assert _rel(z.cpu().numpy(), z_ref) <= (1e-5 if dtype == torch.float32 else 1e-12)
-            else:
-                assert torch.equal(z, ref[0]) and torch.equal(dual, ref[1]), (w, r, T)
+    for cols in (1, 2):
+        for w, r in TILES:
+            for T in (1, 3, 8) + ((12, 16) if dtype == torch.float32 else ()):
+                g.set_plan(dict(fgp_waves=w, fgp_rows=r, fgp_iters=T, fgp_cols=cols))
+                assert g.get_plan()["fgp_iters"] == min(T, w * r // 2 - 2)
+                assert g.get_plan()["fgp_cols"] == cols
+                dual = torch.from_numpy(d0).to("cuda", dtype)
+                z = api.tv_prox(g, vt, 0.05, 29, dual=dual)
+                torch.cuda.synchronize()
+                if ref is None:
+                    ref = (z.clone(), dual.clone())
+                    z_ref = orc.tv_prox_fgp(v, 0.05, 29, nonneg=True, dual=d0.copy())
+                    assert _rel(z.cpu().numpy(), z_ref) <= (1e-5 if dtype == torch.float32 else 1e-12)
+                else:
+                    assert torch.equal(z, ref[0]) and torch.equal(dual, ref[1]), (w, r, T, cols)
 
 
 @pytest.mark.parametrize("shape", [(1, 40), (37, 1), (5, 3), (70, 2), (2, 65)])
@@ -154,8 +157,9 @@ def test_fgp_tiles_on_degenerate_images(orc, shape):
     v = rng.random((1, ny, nx))
     z_ref = orc.tv_prox_fgp(v, 0.1, 23, nonneg=True, dual=np.zeros((2, 1, ny, nx)))
     vt = torch.from_numpy(v).to("cuda", torch.float32)
-    for w, r in TILES:
-        for T in (1, 8, 16):
-            g.set_plan(dict(fgp_waves=w, fgp_rows=r, fgp_iters=T))
-            z = api.tv_prox(g, vt, 0.1, 23, dual=torch.zeros(g.dual_shape(), device="cuda"))
-            assert _rel(z.cpu().numpy(), z_ref) <= 1e-5, (w, r, T)
+    for cols in (1, 2):
+        for w, r in TILES:
+            for T in (1, 8, 16):
+                g.set_plan(dict(fgp_waves=w, fgp_rows=r, fgp_iters=T, fgp_cols=cols))
+                z = api.tv_prox(g, vt, 0.1, 23, dual=torch.zeros(g.dual_shape(), device="cuda"))
+                assert _rel(z.cpu().numpy(), z_ref) <= 1e-5, (w, r, T, cols)
