@@ -236,3 +236,29 @@ def test_device_alloc_workspace():
     big = api.workspace_buffer(api.CONTIGUOUS_MIN_BYTES, g.device)
     assert isinstance(big, api.DeviceBuffer) and big.numel() == api.CONTIGUOUS_MIN_BYTES
     del big
+
+
+def test_solver_with_device_alloc_workspaces(monkeypatch):
+    """Every workspace of a solve, a prox and an autotune taken from device_alloc (the threshold
+    lowered so that a small problem uses it) gives the same bits as torch workspaces."""
+    from paper_2602_09527_amd import api, synth
+    prob = synth.make_problem(96, 96, 60, 140, seed=4, with_phantom=False)
+    b = torch.from_numpy(prob.b).float().cuda()
+    runs = []
+    for threshold in (1 << 62, 1):
+        monkeypatch.setattr(api, "CONTIGUOUS_MIN_BYTES", threshold)
+        g = api.Geometry(96, 96, 60, 140, n_subsets=6)
+        api.autotune(g, reps=1, store=False)          # its workspace too; then one fixed plan
+        g.set_plan(dict(proj_split_full=2, proj_split_subset=3, bp_method_subset=2))
+        s = api.Solver(g, b, api.SolverParams(gamma=1.0 / 4000.0, p=0.5, alpha=0.01, fgp_inner=9,
+                                              n_epochs=3, seed=2))
+        assert isinstance(s.ws, api.DeviceBuffer) == (threshold == 1)
+        s.epochs(3)
+        dual = torch.zeros(g.dual_shape(), device="cuda")
+        z = api.tv_prox(g, s.x, 0.02, 7, dual=dual)
+        torch.cuda.synchronize()
+        runs.append((s.x.clone(), s.h.clone(), z.clone(), dual.clone(), g.get_plan()))
+        del s
+    (xa, ha, za, da, pa), (xb, hb, zb, db, pb) = runs
+    assert pa == pb
+    assert torch.equal(xa, xb) and torch.equal(ha, hb) and torch.equal(za, zb) and torch.equal(da, db)
