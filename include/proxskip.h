@@ -110,6 +110,12 @@ PS_API int32_t subset_size(const ps_geometry *geom, int32_t subset);
  *   fgp_cols       2D FGP columns per lane: 1 (tiles 64 columns wide) or 2 (128 wide: the halo
  *                  of T + 1 columns per side is a smaller share); 0 = automatic (1).  Does not
  *                  change results, not even their rounding.
+ *   bp_gather_fused inside solver iterations that backproject subsets with the gather while the
+ *                  projector splits rays: 2 = the gather adds the projector's partial sums itself
+ *                  as it stages the ray values (no reduction pass: one launch fewer per
+ *                  iteration), 1 = the reduction pass runs; 0 = automatic (2 for splits up to
+ *                  8 whose partials take at most 32 MiB).  Same results either way, to the bit.
+ *                  get_plan reports 2 only where it takes effect.
  *   fgp3d_chunk    slices each workgroup of the 3D FGP marches through: 1..256, 0 = automatic
  *                  (4 for one iteration per launch, 16 for two)
  *   fgp_waves, fgp_rows  2D FGP tile: waves per workgroup and image rows per wave, one of
@@ -136,6 +142,7 @@ typedef struct {
     int32_t fgp3d_form;
     int32_t bp_gather_split;
     int32_t fgp_cols;
+    int32_t bp_gather_fused;
 } ps_plan;
 
 /* The plan in effect (automatic choices filled in) / replace the overrides.  set: fields out of

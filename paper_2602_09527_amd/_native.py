@@ -53,7 +53,8 @@ class Plan(C.Structure):
                 ("bp_method_subset", C.c_int32), ("bp_gather_rows", C.c_int32),
                 ("fgp3d_chunk", C.c_int32), ("fgp_waves", C.c_int32), ("fgp_rows", C.c_int32),
                 ("fgp3d_form", C.c_int32), ("bp_gather_split", C.c_int32),
-                ("fgp_cols", C.c_int32)]
+                ("fgp_cols", C.c_int32),
+                ("bp_gather_fused", C.c_int32)]
 
 
 class SolverParams(C.Structure):

@@ -114,6 +114,23 @@ int gather_split(const ps_geometry *g, int subset) {
     return tiles < 256 ? 4 : tiles < 1024 ? 2 : 1;
 }
 
+// Automatic fusion of the projector's reduction into the subset gather: up to this many partials
+// per ray value (each staged value then costs that many loads instead of one), and while all of
+// them fit in the caches (the 1024^2 x 256 volume's 356 MB of subset partials, re-read from HBM
+// by every tile that stages them, made its epoch 1% slower fused).
+constexpr int kGatherFuseSplit = 8;
+constexpr size_t kGatherFuseBytes = static_cast<size_t>(32) << 20;
+
+bool gather_fused(const ps_geometry *g, int subset) {
+    if (subset < 0 || back_method(g, subset) != BP_GATHER) return false;
+    const int split = proj_plan(g, subset_count(g, subset)).split;
+    const size_t bytes = proj_workspace(g, subset_count(g, subset));
+    if (split <= 1 || bytes >= (static_cast<size_t>(1) << 32)) return false;
+    const int forced = g->plan.bp_gather_fused;
+    if (forced == 1 || forced == 2) return forced == 2;
+    return split <= kGatherFuseSplit && bytes <= kGatherFuseBytes;
+}
+
 // One backprojector application: partial images of A_sub^T y, one per (angle class, group).
 template <typename T>
 struct BackItem {
@@ -514,16 +531,24 @@ __global__ __launch_bounds__(kBlock) void k_backproject_combine(WorkList<Combine
 //   The rays an angle can send into the tile form a window of at most kGatherWin consecutive
 //   bins; the windows of up to kGatherChunk angles (y / |.|, zero outside [0, B)) are staged in
 //   LDS at a time.
+//   Inside a solver iteration the gather may also take the projector's split partial sums in
+//   place of y (psplit > 1): the staging then forms each staged ray value as the projector's
+//   reduction pass does -- the partials added in split order, times 1/|.|, minus b when a data
+//   term is subtracted -- with the same operations, so the result has the same bits as the
+//   reduction pass followed by the gather, and the iteration needs one launch fewer.
 constexpr int kGatherChunk = 32;
 constexpr int kGatherWin = 96;
 
 template <typename T>
 struct GatherItem {
-    const T *y;
+    const T *y;       // the sinogram (nz x na x B), or with psplit > 1 the projector's partials
     T *out;
     UpdateT<T> upd;
     AngleTab<T> tab;
+    const T *pb;      // psplit > 1: b (nz x A x B) subtracted from the summed rays, or null
     int subset, nsub, na, nx, ny, nbins, tiles_x, tiles_y, mode;
+    int psplit, n_angles;
+    uint32_t pbytes;  // psplit > 1: bytes between consecutive partials (nz na B elements)
 };
 
 template <typename T>
@@ -647,8 +672,9 @@ __device__ inline void cell_ray(const GatherAngle<T> &ga, int p, T c, int64_t ba
 // AS waves share each block of R rows, each taking every AS-th angle of the chunk; their sums are
 // added in LDS in wave order (a fixed order) before the epilogue.  A tile is 4 / AS blocks of R
 // rows: splitting the angles gives small images more workgroups without shrinking the staged
-// windows' reuse below R rows.
-template <typename T, int R, int AS>
+// windows' reuse below R rows.  PF: the staged values are formed from the projector's split
+// partials (GatherItem::psplit > 1) rather than read from a sinogram.
+template <typename T, int R, int AS, bool PF>
 __global__ __launch_bounds__(kBlock) void k_backproject_gather(WorkList<GatherItem<T>> wl) {
     static_assert(AS == 1 || AS == 2 || AS == 4, "angle split");
     constexpr int kGatherRows = R;                 // rows per wave
@@ -696,10 +722,58 @@ __global__ __launch_bounds__(kBlock) void k_backproject_gather(WorkList<GatherIt
             ulo[threadIdx.x] = static_cast<int>(floor(min(min(u1, u2), min(u3, u4)))) - 3;
         }
         __syncthreads();
-        // each thread's window entries: all loads first (bins clamped into range), then the
-        // scaled values (zero outside the detector) go to LDS
         constexpr int kWinPer = (kGatherChunk * kGatherWin + kBlock - 1) / kBlock;
-        {
+        if constexpr (PF) {
+            // the projector's reduction pass, element by element: partials in split order (kPb
+            // of them in flight, the last one re-read past the end), times 1/|.|, minus b; then
+            // the gather's own 1/|.|.  32-bit byte offsets from the plane's base, the partial's
+            // included, so that the loads take the scalar-base form (the host keeps all
+            // partials within 4 GiB)
+            constexpr int kPb = 2;
+            const int ps = it.psplit;
+            uint32_t off[kWinPer];
+            T acc[kWinPer];
+#pragma unroll
+            for (int r = 0; r < kWinPer; ++r) {
+                const int e = static_cast<int>(threadIdx.x) + r * kBlock;
+                const int a = min(e / kGatherWin, cn - 1), w = e - (e / kGatherWin) * kGatherWin;
+                off[r] = static_cast<uint32_t>((c0 + a) * B + min(max(ulo[a] + w, 0), B - 1)) *
+                         static_cast<uint32_t>(sizeof(T));
+                acc[r] = T(0);
+            }
+#pragma unroll 1
+            for (int t0 = 0; t0 < ps; t0 += kPb) {
+                T v[kPb][kWinPer];
+#pragma unroll
+                for (int q = 0; q < kPb; ++q) {
+                    const uint32_t pt = static_cast<uint32_t>(min(t0 + q, ps - 1)) * it.pbytes;
+#pragma unroll
+                    for (int r = 0; r < kWinPer; ++r)
+                        v[q][r] = *reinterpret_cast<const T *>(reinterpret_cast<const char *>(yz) + (off[r] + pt));
+                }
+#pragma unroll
+                for (int q = 0; q < kPb; ++q)
+#pragma unroll
+                    for (int r = 0; r < kWinPer; ++r) acc[r] = t0 + q < ps ? acc[r] + v[q][r] : acc[r];
+            }
+            const T *bz = it.pb ? it.pb + static_cast<size_t>(z) * it.n_angles * B : nullptr;
+#pragma unroll
+            for (int r = 0; r < kWinPer; ++r) {
+                const int e = static_cast<int>(threadIdx.x) + r * kBlock;
+                const int a = e / kGatherWin, w = e - a * kGatherWin;
+                if (a < cn) {
+                    const int u = ulo[a] + w;
+                    const int l = c0 + a;
+                    const int k = it.subset < 0 ? l : it.subset + l * it.nsub;
+                    const T inv = s_ang[a].inv;
+                    const T val = bz ? fma(acc[r], inv, -bz[static_cast<size_t>(k) * B + min(max(u, 0), B - 1)])
+                                     : acc[r] * inv;
+                    ywin[a][w] = (u >= 0 && u < B) ? val * inv : T(0);
+                }
+            }
+        } else {
+            // each thread's window entries: all loads first (bins clamped into range), then the
+            // scaled values (zero outside the detector) go to LDS
             T raw[kWinPer];
 #pragma unroll
             for (int r = 0; r < kWinPer; ++r) {
@@ -856,19 +930,26 @@ static ps_status backproject_many_t(const BackCall *calls, int n, hipStream_t st
     std::vector<BackItem<T>> items;
     std::vector<BackPlan> plans;
     std::vector<int> call_of;
-    ListBuilder<GatherItem<T>> gl[6];   // rows per wave {2, 4} x angle split {1, 2, 4}
+    // rows per wave {2, 4} x angle split {1, 2, 4} x (sinogram, projector partials)
+    ListBuilder<GatherItem<T>> gl[12];
     auto flush_gather = [&](int which) -> ps_status {
         ListBuilder<GatherItem<T>> &b = gl[which];
         if (b.empty()) return PS_OK;
         timer_mark(KC_BP_GATHER, st, true);
         const dim3 grid(b.blocks), block(kBlock);
         switch (which) {
-        case 0: hipLaunchKernelGGL((k_backproject_gather<T, 2, 1>), grid, block, 0, st, b.wl); break;
-        case 1: hipLaunchKernelGGL((k_backproject_gather<T, 2, 2>), grid, block, 0, st, b.wl); break;
-        case 2: hipLaunchKernelGGL((k_backproject_gather<T, 2, 4>), grid, block, 0, st, b.wl); break;
-        case 3: hipLaunchKernelGGL((k_backproject_gather<T, 4, 1>), grid, block, 0, st, b.wl); break;
-        case 4: hipLaunchKernelGGL((k_backproject_gather<T, 4, 2>), grid, block, 0, st, b.wl); break;
-        default: hipLaunchKernelGGL((k_backproject_gather<T, 4, 4>), grid, block, 0, st, b.wl); break;
+        case 0: hipLaunchKernelGGL((k_backproject_gather<T, 2, 1, false>), grid, block, 0, st, b.wl); break;
+        case 1: hipLaunchKernelGGL((k_backproject_gather<T, 2, 2, false>), grid, block, 0, st, b.wl); break;
+        case 2: hipLaunchKernelGGL((k_backproject_gather<T, 2, 4, false>), grid, block, 0, st, b.wl); break;
+        case 3: hipLaunchKernelGGL((k_backproject_gather<T, 4, 1, false>), grid, block, 0, st, b.wl); break;
+        case 4: hipLaunchKernelGGL((k_backproject_gather<T, 4, 2, false>), grid, block, 0, st, b.wl); break;
+        case 5: hipLaunchKernelGGL((k_backproject_gather<T, 4, 4, false>), grid, block, 0, st, b.wl); break;
+        case 6: hipLaunchKernelGGL((k_backproject_gather<T, 2, 1, true>), grid, block, 0, st, b.wl); break;
+        case 7: hipLaunchKernelGGL((k_backproject_gather<T, 2, 2, true>), grid, block, 0, st, b.wl); break;
+        case 8: hipLaunchKernelGGL((k_backproject_gather<T, 2, 4, true>), grid, block, 0, st, b.wl); break;
+        case 9: hipLaunchKernelGGL((k_backproject_gather<T, 4, 1, true>), grid, block, 0, st, b.wl); break;
+        case 10: hipLaunchKernelGGL((k_backproject_gather<T, 4, 2, true>), grid, block, 0, st, b.wl); break;
+        default: hipLaunchKernelGGL((k_backproject_gather<T, 4, 4, true>), grid, block, 0, st, b.wl); break;
         }
         PS_LAUNCHED("k_backproject_gather");
         timer_mark(KC_BP_GATHER, st, false);
@@ -894,17 +975,30 @@ static ps_status backproject_many_t(const BackCall *calls, int n, hipStream_t st
             gi.ny = d.ny;
             gi.nbins = d.n_bins;
             const int rows = gather_rows(g, bc.subset), split = gather_split(g, bc.subset);
-            const int which = (rows == 2 ? 0 : 3) + (split == 1 ? 0 : split == 2 ? 1 : 2);
+            int which = (rows == 2 ? 0 : 3) + (split == 1 ? 0 : split == 2 ? 1 : 2);
             const int tile_rows = (4 / split) * rows;
             gi.tiles_x = (d.nx + kGatherTX - 1) / kGatherTX;
             gi.tiles_y = (d.ny + tile_rows - 1) / tile_rows;
             gi.mode = bc.mode;
+            gi.psplit = 1;
+            if (bc.psplit > 1) {
+                if (bc.subset < 0) return fail(PS_EINVAL, "projector partials given to an all-angle gather");
+                gi.psplit = bc.psplit;
+                gi.pb = static_cast<const T *>(bc.pb);
+                const size_t pstride = static_cast<size_t>(d.nz) * gi.na * d.n_bins * sizeof(T);
+                if (pstride * bc.psplit >= (static_cast<size_t>(1) << 32))
+                    return fail(PS_EUNSUPPORTED, "projector partials beyond 4 GiB given to the gather");
+                gi.pbytes = static_cast<uint32_t>(pstride);
+                gi.n_angles = d.n_angles;
+                which += 6;
+            }
             const long blocks = static_cast<long>(gi.tiles_x) * gi.tiles_y * d.nz;
             if (blocks > (1L << 30)) return fail(PS_EUNSUPPORTED, "backprojector grid too large");
             gl[which].add(gi, static_cast<int>(blocks));
             if (gl[which].full()) PS_TRY(flush_gather(which));
             continue;
         }
+        if (bc.psplit > 1) return fail(PS_EINVAL, "projector partials given to the scatter backprojector");
         const BackPlan bp = back_plan(g, bc.subset);
         const size_t need = back_workspace(g, bc.subset);
         if (!bc.ws || bc.ws_bytes < need)
@@ -990,7 +1084,7 @@ static ps_status backproject_many_t(const BackCall *calls, int n, hipStream_t st
         PS_LAUNCHED("k_backproject_combine");
         timer_mark(KC_BP_COMBINE, st, false);
     }
-    for (int which = 0; which < 6; ++which) PS_TRY(flush_gather(which));
+    for (int which = 0; which < 12; ++which) PS_TRY(flush_gather(which));
     return PS_OK;
 }
 

@@ -226,7 +226,8 @@ struct ProjCall {
     void *y, *ws;
     size_t ws_bytes;
     const void *sig = nullptr;   // PDHG dual step: y = (y + sig (A x - b)) / (1 + sig), per ray
-    bool first_pass_only = false;   // skip the split-ray sum (kernel timing: the partials stay)
+    bool first_pass_only = false;   // skip the split-ray sum: the partials stay in ws (kernel
+                                    // timing, or a gather that adds them itself)
 };
 ps_status launch_project_many(const ProjCall *calls, int n, hipStream_t st);
 ps_status launch_project(const ps_geometry *g, int subset, const void *x, const void *xs,
@@ -267,6 +268,9 @@ enum BackMethod { BP_SCATTER = 1, BP_GATHER = 2 };
 int back_method(const ps_geometry *g, int subset);   // BP_SCATTER or BP_GATHER
 int gather_rows(const ps_geometry *g, int subset);   // rows per wave of the gather tiles: 2 or 4
 int gather_split(const ps_geometry *g, int subset);  // waves sharing a gather tile's rows: 1, 2 or 4
+// Does a solver iteration hand subset `subset`'s projector partials straight to the gather?
+// (the gather backprojects subsets, the projector splits rays, and the plan allows it)
+bool gather_fused(const ps_geometry *g, int subset);
 struct BackCall {
     const ps_geometry *g;
     int subset;
@@ -277,6 +281,10 @@ struct BackCall {
     void *ws;
     size_t ws_bytes;
     bool partials_only = false;     // scatter: skip the combine pass (kernel timing)
+    // gather of a subset only: y holds the projector's psplit (> 1) partial sums, added during
+    // staging as the projector's reduction pass would (minus pb when pb is not null)
+    int psplit = 0;
+    const void *pb = nullptr;
 };
 ps_status launch_backproject_many(const BackCall *calls, int n, hipStream_t st);
 ps_status launch_backproject(const ps_geometry *g, int subset, const void *y, void *out, int mode,

@@ -360,8 +360,10 @@ __global__ __launch_bounds__(kBlock) void k_project_reduce(WorkList<ReduceItem<T
 #pragma unroll
             for (int q = 0; q < 8; ++q) acc = s0 + q < split ? acc + v[q] : acc;
         }
-        T val = acc * it.inv[k];
-        if (b) val -= b[(static_cast<size_t>(z) * it.n_angles + k) * nbins + u];
+        // one rounding with b (an explicit FMA, so that no contraction choice of the compiler
+        // decides the bits: the subset gather that adds the partials itself repeats this form)
+        T val = b ? fma(acc, it.inv[k], -b[(static_cast<size_t>(z) * it.n_angles + k) * nbins + u])
+                  : acc * it.inv[k];
         if (it.sig) {
             const T sg = it.sig[e];
             val = (y[e] + sg * val) / (T(1) + sg);

@@ -394,6 +394,17 @@ static ps_status saga_fill_t(ps_solver *s, hipStream_t st) {
     return PS_OK;
 }
 
+// A subset's projection and gather backprojection with the projector's reduction pass left to
+// the gather (when the plan fuses them): the projector keeps its partial sums in its workspace
+// and the gather reads them there.
+static void fuse_pair(ProjCall &pc, BackCall &bc, const void *b) {
+    if (!gather_fused(pc.g, pc.subset)) return;
+    pc.first_pass_only = true;
+    bc.y = pc.ws;
+    bc.psplit = proj_plan(pc.g, subset_count(pc.g, pc.subset)).split;
+    bc.pb = b;
+}
+
 // Does iteration s->k take the snapshot branch (xs = x, full gradient)?
 static bool snapshot_now(const ps_solver *s, int t) {
     const int est = s->prm.estimator;
@@ -462,6 +473,7 @@ static ps_status run_step(const std::vector<ps_solver *> &hs, hipStream_t st,
             up.tsum = w + s->L.tsum;
             pc.push_back(ProjCall{g, i, s->x, nullptr, s->b, w + s->L.sino, w + s->L.pws, s->L.pws_bytes});
             bc.push_back(BackCall{g, i, w + s->L.sino, nullptr, BP_SAGA, up, w + s->L.bws, s->L.bws_bytes});
+            fuse_pair(pc.back(), bc.back(), s->b);
         } else if (snap) {
             // r = A xs - b over all angles, then gs = A^T r fused with the step (G = gs)
             pc.push_back(ProjCall{g, -1, w + s->L.xs, nullptr, s->b, w + s->L.sino, w + s->L.pws, s->L.pws_bytes});
@@ -472,6 +484,7 @@ static ps_status run_step(const std::vector<ps_solver *> &hs, hipStream_t st,
             else
                 pc.push_back(ProjCall{g, i, s->x, w + s->L.xs, nullptr, w + s->L.sino, w + s->L.pws, s->L.pws_bytes});
             bc.push_back(BackCall{g, i, w + s->L.sino, nullptr, BP_SVRG, up, w + s->L.bws, s->L.bws_bytes});
+            fuse_pair(pc.back(), bc.back(), nullptr);
         }
         if (prox) {
             FgpOut fo{};

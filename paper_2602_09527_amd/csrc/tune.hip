@@ -2,8 +2,9 @@
 // plans on the device and keeps the fastest.
 //
 // What is tuned: the projector's ray split (partial sums over S workgroups per ray, then a fixed
-// order reduction), the backprojector's angle groups G and strip height R, and the number of FGP
-// inner iterations per 2D launch (temporal blocking depth).  None of them changes what is
+// order reduction), the backprojector's method, angle groups G and strip height R (or the
+// gather's tile), whether a subset gather adds the projector's partials itself, and the FGP
+// tiles and inner iterations per launch (temporal blocking depth).  None of them changes what is
 // computed; split and grouping change the order of floating-point sums.
 #include <algorithm>
 #include <array>
@@ -139,6 +140,7 @@ extern "C" ps_status geometry_get_plan(const ps_geometry *g, ps_plan *out) {
     out->bp_gather_rows = gather_rows(g, 0);
     out->bp_gather_split = gather_split(g, 0);
     out->fgp_cols = fgp_cols_of(g);
+    out->bp_gather_fused = gather_fused(g, 0) ? 2 : 1;
     out->fgp3d_chunk = fgp3d_chunk_of(g);
     fgp_tile_of(g, &out->fgp_waves, &out->fgp_rows);
     out->fgp3d_form = fgp3d_form_of(g);
@@ -166,6 +168,8 @@ extern "C" ps_status geometry_set_plan(ps_geometry *g, const ps_plan *p) {
     if (p->bp_gather_split != 0 && p->bp_gather_split != 1 && p->bp_gather_split != 2 && p->bp_gather_split != 4)
         return fail(PS_EINVAL, "bp_gather_split must be 0, 1, 2 or 4");
     if (p->fgp_cols < 0 || p->fgp_cols > 2) return fail(PS_EINVAL, "fgp_cols must be 0, 1 or 2");
+    if (p->bp_gather_fused < 0 || p->bp_gather_fused > 2)
+        return fail(PS_EINVAL, "bp_gather_fused must be 0, 1 or 2");
     if (p->fgp3d_chunk < 0 || p->fgp3d_chunk > 256) return fail(PS_EINVAL, "fgp3d_chunk must be in [0, 256]");
     if (p->fgp3d_form < 0 || p->fgp3d_form > kF3Forms) return fail(PS_EINVAL, "fgp3d_form must be in [0, %d]", kF3Forms);
     if (!(p->fgp_waves == 0 && p->fgp_rows == 0) && !fgp_tile_ok(p->fgp_waves, p->fgp_rows))
@@ -337,6 +341,78 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
                 best.bp_gather_split = pick[2];
             }
         }
+    }
+
+    // a subset's projection and gather backprojection as a solver iteration runs them, with the
+    // reduction pass or (split > 1) with the gather adding the partials itself: first every
+    // projector split with the gather tile chosen above, then every gather tile (rows per wave,
+    // angle split) with the split chosen.  The plan chosen so far is timed first and is the one
+    // to beat; the pairs are short, so each is timed over enough calls to fill about 5 ms
+    g->plan = best;
+    if (back_method(g, 0) == BP_GATHER) {
+        // {projector split, fused, gather rows, gather angle split}
+        using Pair = std::array<int, 4>;
+        auto time_pair = [&](const Pair &k, int r, float *ms) -> ps_status {
+            ps_plan trial = best;
+            trial.proj_split_subset = k[0];
+            trial.bp_gather_fused = k[1];
+            trial.bp_gather_rows = k[2];
+            trial.bp_gather_split = k[3];
+            g->plan = trial;
+            ProjCall pc{g, 0, w + L.x, nullptr, nullptr, w + L.y, w + L.pws, L.pws_bytes};
+            BackCall bc{};
+            bc.g = g;
+            bc.subset = 0;
+            bc.y = w + L.y;
+            bc.out = w + L.img;
+            bc.mode = BP_OVERWRITE;
+            bc.ws = w + L.bws;
+            bc.ws_bytes = L.bws_bytes;
+            if (gather_fused(g, 0)) {
+                pc.first_pass_only = true;
+                bc.y = w + L.pws;
+                bc.psplit = proj_plan(g, subset_count(g, 0)).split;
+            }
+            return time_calls([&] {
+                PS_TRY(launch_project_many(&pc, 1, st));
+                return launch_backproject_many(&bc, 1, st);
+            }, r, st, tm, ms);
+        };
+        const Pair first{proj_plan(g, max_subset_count(g)).split, gather_fused(g, 0) ? 2 : 1,
+                         gather_rows(g, 0), gather_split(g, 0)};
+        float est = 0.f;
+        PS_TRY(restore_on_error(time_pair(first, reps, &est)));
+        const int r = std::max(reps, std::min(100, static_cast<int>(5.0f / std::max(est, 1e-3f))));
+        float best_ms = 0.f;
+        Pair pick = first;
+        PS_TRY(restore_on_error(time_pair(first, r, &best_ms)));
+        auto consider = [&](const Pair &k) -> ps_status {
+            if (k == first) return PS_OK;
+            ps_plan trial = best;
+            trial.proj_split_subset = k[0];
+            g->plan = trial;
+            if (proj_plan(g, max_subset_count(g)).split != k[0]) return PS_OK;   // clamped
+            float ms = 0.f;
+            PS_TRY(time_pair(k, r, &ms));
+            if (ms < best_ms * (pick == first ? kMinGain : 1.0f)) {
+                best_ms = ms;
+                pick = k;
+            }
+            return PS_OK;
+        };
+        for (int s : splits)
+            for (int f : {1, 2})
+                if (s <= max_split && (f == 1 || s > 1))
+                    PS_TRY(restore_on_error(consider({s, f, first[2], first[3]})));
+        const int split_pick = pick[0];
+        for (int rows : {2, 4})
+            for (int as : {1, 2, 4})
+                for (int f : {1, 2})
+                    if (f == 1 || split_pick > 1) PS_TRY(restore_on_error(consider({split_pick, f, rows, as})));
+        best.proj_split_subset = pick[0];
+        best.bp_gather_fused = pick[1];
+        best.bp_gather_rows = pick[2];
+        best.bp_gather_split = pick[3];
     }
 
     // 2D FGP tile shape and inner iterations per launch: one 50-iteration prox per timed call;

@@ -157,7 +157,8 @@ def test_plan_get_set_and_validation(nat):
                     dict(fgp_iters=17), dict(bp_method_subset=3), dict(fgp_waves=4, fgp_rows=2),
                     dict(fgp_waves=8), dict(fgp_rows=4), dict(fgp_waves=32, fgp_rows=2),
                     dict(fgp3d_form=6), dict(fgp3d_form=-1), dict(fgp3d_chunk=257),
-                    dict(bp_gather_split=3), dict(fgp_cols=3), dict(fgp_cols=-1)):
+                    dict(bp_gather_split=3), dict(fgp_cols=3), dict(fgp_cols=-1),
+                    dict(bp_gather_fused=3), dict(bp_gather_fused=-1)):
             assert lib.geometry_set_plan(h, C.byref(nat.Plan(**bad))) == nat.PS_EINVAL
         # a rejected plan leaves the previous one in place
         assert lib.geometry_get_plan(h, C.byref(got)) == nat.PS_OK and got.fgp_iters == 5
@@ -351,5 +352,52 @@ def test_automatic_3d_form_per_dtype(nat, dtype, form):
         assert lib.geometry_set_plan(h, C.byref(nat.Plan(fgp3d_form=1))) == nat.PS_OK
         assert lib.geometry_get_plan(h, C.byref(got)) == nat.PS_OK
         assert (got.fgp3d_form, got.fgp3d_chunk) == (1, 4)
+    finally:
+        lib.free_geometry(h)
+
+
+def test_gather_fused_plan_rule(nat):
+    # the subset gather adds the projector's partials itself only where both apply: the gather
+    # backprojects subsets and the projector splits rays; automatic up to 8 partials per ray
+    lib = nat.load()
+    got = nat.Plan()
+
+    def fused(h, **plan):
+        assert lib.geometry_set_plan(h, C.byref(nat.Plan(**plan))) == nat.PS_OK
+        assert lib.geometry_get_plan(h, C.byref(got)) == nat.PS_OK
+        return got.bp_gather_fused, got.proj_split_subset
+
+    for ext, split in ((128, 4), (512, 16)):
+        h = C.c_void_p()
+        d = _desc(nat, nx=ext, ny=ext, n_angles=12, n_bins=ext + ext // 2, n_subsets=3)
+        assert lib.make_geometry(C.byref(d), C.byref(h)) == nat.PS_OK
+        try:
+            assert fused(h) == (1, split)                                   # scatter
+            assert fused(h, bp_method_subset=2) == (2 if split <= 8 else 1, split)
+            assert fused(h, bp_method_subset=2, proj_split_subset=4) == (2, 4)
+            assert fused(h, bp_method_subset=2, proj_split_subset=1) == (1, 1)
+            assert fused(h, bp_method_subset=2, bp_gather_fused=1) == (1, split)
+            assert fused(h, bp_method_subset=2, bp_gather_fused=2) == (2, split)
+            assert fused(h, bp_method_subset=1, bp_gather_fused=2) == (1, split)
+        finally:
+            lib.free_geometry(h)
+    # automatic only while the partials take at most 32 MiB: 4 x 256 slices x 20 angles x 768
+    # bins x 4 bytes = 63 MB is not fused unless the plan asks for it
+    h = C.c_void_p()
+    d = _desc(nat, nx=512, ny=512, nz=256, n_angles=60, n_bins=768, n_subsets=3)
+    assert lib.make_geometry(C.byref(d), C.byref(h)) == nat.PS_OK
+    try:
+        assert fused(h, bp_method_subset=2, proj_split_subset=4) == (1, 4)
+        assert fused(h, bp_method_subset=2, proj_split_subset=4, bp_gather_fused=2) == (2, 4)
+        assert lib.geometry_set_plan(h, C.byref(nat.Plan(bp_method_subset=2, proj_split_subset=4))) == nat.PS_OK
+        assert lib.project_workspace_bytes(h, 0) == 4 * 256 * 20 * 768 * 4
+    finally:
+        lib.free_geometry(h)
+    # no gather when bins are closer than a pixel, so never fused
+    h = C.c_void_p()
+    d = _desc(nat, nx=128, ny=128, n_angles=12, n_bins=400, bin_width=0.5, n_subsets=3)
+    assert lib.make_geometry(C.byref(d), C.byref(h)) == nat.PS_OK
+    try:
+        assert fused(h, bp_method_subset=2, bp_gather_fused=2) == (1, 4)
     finally:
         lib.free_geometry(h)

@@ -78,15 +78,18 @@ def test_forced_plans_keep_parity(orc, plan):
 
 
 @pytest.mark.parametrize("dtype,tol", [(torch.float32, 1e-4), (torch.float64, 1e-9)])
-@pytest.mark.parametrize("rows,split", [(2, 2), (4, 4)])
-def test_gather_split_solve_matches_oracle(orc, dtype, tol, rows, split):
+@pytest.mark.parametrize("rows,split,fused", [(2, 2, 1), (4, 4, 1), (2, 2, 2), (4, 4, 2)])
+def test_gather_split_solve_matches_oracle(orc, dtype, tol, rows, split, fused):
     # the 128^2 solve (180 x 128, 10 subsets) with the pixel-driven backprojector whose waves
-    # split the angles (its fused SVRG / ProxSkip update included), 10 epochs
+    # split the angles (its fused SVRG / ProxSkip update included), 10 epochs; the projector's
+    # 4 partial sums per ray added by the reduction pass (fused = 1) or by the gather (2)
     from paper_2602_09527_amd import api, synth, workloads
     w = workloads.SMALL_2D
     prob = synth.make_problem(w.nx, w.ny, w.n_angles, w.n_bins, seed=w.seed, with_phantom=False)
     g = api.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=w.n_subsets, dtype=dtype)
-    g.set_plan(dict(bp_method_full=2, bp_method_subset=2, bp_gather_rows=rows, bp_gather_split=split))
+    g.set_plan(dict(bp_method_full=2, bp_method_subset=2, bp_gather_rows=rows, bp_gather_split=split,
+                    proj_split_subset=4, bp_gather_fused=fused))
+    assert g.get_plan()["bp_gather_fused"] == fused
     o = orc.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=w.n_subsets)
     L = json.load(open(__file__.replace("test_gpu_tune.py", "golden/lipschitz.json")))[w.key]["L"]
     kw = dict(gamma=1.0 / L, p=w.p, alpha=w.alpha, fgp_inner=w.fgp_inner, n_epochs=10,
@@ -95,6 +98,31 @@ def test_gather_split_solve_matches_oracle(orc, dtype, tol, rows, split):
     xo, _, _, so, _ = orc.proxskip_svrg(o, prob.b, **kw)
     assert st["prox_calls"] == so["prox_calls"] > 0
     assert _rel(x.cpu().double().numpy(), xo) <= tol
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("estimator", ["svrg", "lsvrg", "saga"])
+def test_gather_fused_same_bits(dtype, estimator):
+    # the subset gather adding the projector's split partials itself gives the bits of the
+    # reduction pass followed by the gather: uneven subsets (52 angles in 7), an odd split (a
+    # ragged last pair of partials) and an even one, every estimator (SAGA subtracts b there)
+    from paper_2602_09527_amd import api, synth
+    nx, ny, A, B, N = 100, 90, 52, 150, 7
+    prob = synth.make_problem(nx, ny, A, B, seed=3, with_phantom=False)
+    g = api.Geometry(nx, ny, A, B, n_subsets=N, dtype=dtype)
+    b = torch.from_numpy(prob.b).to("cuda", dtype)
+    prm = api.SolverParams(gamma=1e-4, p=0.3, alpha=0.01, fgp_inner=20, n_epochs=3, seed=11,
+                           estimator=estimator)
+    for psplit in (3, 2):
+        out = []
+        for fused in (1, 2):
+            g.set_plan(dict(bp_method_subset=2, proj_split_subset=psplit, bp_gather_fused=fused))
+            assert (g.get_plan()["bp_gather_fused"], g.get_plan()["proj_split_subset"]) == (fused, psplit)
+            x, h, dual, st = api.solve(g, b, prm)
+            assert st["prox_calls"] > 0 and torch.isfinite(x).all()
+            out.append((x, h, dual))
+        for a, c in zip(*out):
+            assert torch.equal(a, c)
 
 
 def test_tuned_solve_matches_oracle(orc):
