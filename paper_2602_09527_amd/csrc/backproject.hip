@@ -114,6 +114,12 @@ int gather_split(const ps_geometry *g, int subset) {
     return tiles < 256 ? 4 : tiles < 1024 ? 2 : 1;
 }
 
+long gather_tiles(const ps_geometry *g, int subset, int rows) {
+    const auto &d = g->desc;
+    const int tile_rows = (4 / gather_split(g, subset)) * rows;
+    return static_cast<long>((d.nx + kGatherTX - 1) / kGatherTX) * ((d.ny + tile_rows - 1) / tile_rows) * d.nz;
+}
+
 // Automatic fusion of the projector's reduction into the subset gather: up to this many partials
 // per ray value (each staged value then costs that many loads instead of one), and while all of
 // them fit in the caches (the 1024^2 x 256 volume's 356 MB of subset partials, re-read from HBM
@@ -974,7 +980,8 @@ static ps_status backproject_many_t(const BackCall *calls, int n, hipStream_t st
             gi.nx = d.nx;
             gi.ny = d.ny;
             gi.nbins = d.n_bins;
-            const int rows = gather_rows(g, bc.subset), split = gather_split(g, bc.subset);
+            const int rows = bc.rows == 2 || bc.rows == 4 ? bc.rows : gather_rows(g, bc.subset);
+            const int split = gather_split(g, bc.subset);
             int which = (rows == 2 ? 0 : 3) + (split == 1 ? 0 : split == 2 ? 1 : 2);
             const int tile_rows = (4 / split) * rows;
             gi.tiles_x = (d.nx + kGatherTX - 1) / kGatherTX;

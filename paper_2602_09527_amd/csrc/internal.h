@@ -271,6 +271,8 @@ int gather_split(const ps_geometry *g, int subset);  // waves sharing a gather t
 // Does a solver iteration hand subset `subset`'s projector partials straight to the gather?
 // (the gather backprojects subsets, the projector splits rays, and the plan allows it)
 bool gather_fused(const ps_geometry *g, int subset);
+// Workgroups of a gather call with `rows` rows per wave (and the plan's angle split).
+long gather_tiles(const ps_geometry *g, int subset, int rows);
 struct BackCall {
     const ps_geometry *g;
     int subset;
@@ -285,6 +287,7 @@ struct BackCall {
     // staging as the projector's reduction pass would (minus pb when pb is not null)
     int psplit = 0;
     const void *pb = nullptr;
+    int rows = 0;   // gather: rows per wave (2 or 4) in place of the plan's; 0 = the plan's
 };
 ps_status launch_backproject_many(const BackCall *calls, int n, hipStream_t st);
 ps_status launch_backproject(const ps_geometry *g, int subset, const void *y, void *out, int mode,

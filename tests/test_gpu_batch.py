@@ -122,3 +122,31 @@ def test_batch_with_different_fgp_tiles_bitwise_equals_alone():
         xa, ha, da, sa = alone[k]
         assert st == sa, (k, st, sa)
         assert torch.equal(x, xa) and torch.equal(h, ha) and torch.equal(d, da), k
+
+
+def test_batch_gather_tall_tiles_bitwise_equals_alone():
+    # a batch whose subset gathers fill the chip between them -- 12 x 128^2 on tiles of 2 rows per
+    # wave with the angles split 4 ways: 12 x 3 x 64 = 2304 workgroups, at least the 2048 that
+    # switch a batch to 4 rows per wave -- still gives every member the bits it gets alone, with
+    # the projector's split partials added by the gather or by the reduction pass, FP32 and FP64
+    from paper_2602_09527_amd import api
+    probs = []
+    for j in range(12):
+        g, b, prm = _problem(128, 128, 180, 128, 10, 40 + j, torch.float64 if j == 5 else torch.float32,
+                             n_epochs=2, p=0.3)
+        g.set_plan(dict(bp_method_subset=2, bp_gather_rows=2, bp_gather_split=4, proj_split_subset=4,
+                        bp_gather_fused=1 + j % 2))
+        assert g.get_plan()["bp_gather_fused"] == 1 + j % 2
+        probs.append((g, b, prm))
+    alone = []
+    for g, b, prm in probs:
+        s = api.Solver(g, b, prm)
+        s.epochs(prm.n_epochs)
+        alone.append(_state(s))
+    solvers = [api.Solver(g, b, prm) for g, b, prm in probs]
+    api.run_epochs(solvers, 2)
+    for k, s in enumerate(solvers):
+        x, h, d, st = _state(s)
+        xa, ha, da, sa = alone[k]
+        assert st == sa, (k, st, sa)
+        assert torch.equal(x, xa) and torch.equal(h, ha) and torch.equal(d, da), k
