@@ -113,7 +113,24 @@ def test_gather_fused_same_bits(dtype, estimator):
     b = torch.from_numpy(prob.b).to("cuda", dtype)
     prm = api.SolverParams(gamma=1e-4, p=0.3, alpha=0.01, fgp_inner=20, n_epochs=3, seed=11,
                            estimator=estimator)
-    for psplit in (3, 2):
+    _fused_against_reduction_pass(api, g, b, prm, (3, 2))
+
+
+@pytest.mark.parametrize("estimator", ["svrg", "saga"])
+def test_gather_fused_same_bits_volume(estimator):
+    # the same on a 3-slice volume with 3D TV: every slice's partials and (SAGA) its rows of b
+    from paper_2602_09527_amd import api
+    nx, ny, nz, A, B, N = 100, 96, 3, 40, 150, 5
+    rng = np.random.default_rng(8)
+    g = api.Geometry(nx, ny, A, B, n_subsets=N, nz=nz)
+    b = torch.from_numpy(rng.random((nz, A, B))).float().cuda()
+    prm = api.SolverParams(gamma=1e-4, p=0.3, alpha=0.01, fgp_inner=10, n_epochs=2, seed=5,
+                           estimator=estimator)
+    _fused_against_reduction_pass(api, g, b, prm, (2, 3))
+
+
+def _fused_against_reduction_pass(api, g, b, prm, splits):
+    for psplit in splits:
         out = []
         for fused in (1, 2):
             g.set_plan(dict(bp_method_subset=2, proj_split_subset=psplit, bp_gather_fused=fused))
