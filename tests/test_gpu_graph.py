@@ -28,9 +28,14 @@ def _state(s):
     return s.x.clone(), s.h.clone(), s.dual.clone(), s.query()
 
 
-def test_graph_replays_equal_eager_each_epoch():
+@pytest.mark.parametrize("plan", [None, dict(bp_method_subset=2, proj_split_subset=4, bp_gather_fused=2)])
+def test_graph_replays_equal_eager_each_epoch(plan):
+    # the automatic plan (scatter subsets), and the subset gather adding the projector's partials
     from paper_2602_09527_amd import api
     g, b, prm = _small(p=0.5)
+    if plan:
+        g.set_plan(plan)
+        assert g.get_plan()["bp_gather_fused"] == 2
     eager = api.Solver(g, b, prm)
     ref = []
     for _ in range(6):
