@@ -14,6 +14,7 @@
 // adds the 2G partials in a fixed order and applies the epilogue (overwrite, accumulate, or the
 // fused SVRG / ProxSkip gradient step).  Results are bitwise reproducible.
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "internal.h"
@@ -675,6 +676,26 @@ __device__ inline void cell_ray(const GatherAngle<T> &ga, int p, T c, int64_t ba
     next = hit ? m : T(0);
 }
 
+// FP32 walk start for cell p at step c / base (as cell_ray): the first ray, in the order of
+// increasing cell, whose cell is >= p.  cell_ray's candidate pair holds it (its lower member for
+// a1 > 0, its upper one for a1 < 0, as the cells then fall with u), or else the next ray in cell
+// order; one exact check of the first decides.  Clamped into [0, nb] + 1 like cell_ray's pair.
+__device__ inline void cell_walk_start(const GatherAngle<float> &ga, int p, float c, int64_t base, int nb,
+                                       int &u, int64_t &Q) {
+    const float us = (static_cast<float>(p) - c) * ga.ia1;
+    const int uf = min(max(static_cast<int>(fmaf(ga.csf, floorf(fmaf(us, ga.cr, 0.015625f)), ga.cof)), 0), nb);
+    const int g = uf - ga.co;                          // co = 0 (a1 > 0) or -1 (a1 < 0)
+    const uint32_t q1lo = static_cast<uint32_t>(static_cast<uint64_t>(ga.q1));
+    const int q1hi = static_cast<int>(ga.q1 >> 32);
+    const uint64_t prod = static_cast<uint64_t>(static_cast<uint32_t>(g)) * q1lo +
+                          (static_cast<uint64_t>(static_cast<uint32_t>(__mul24(g, q1hi))) << 32);
+    const int64_t Qg = static_cast<int64_t>(static_cast<uint64_t>(base) + prod);
+    const bool first = static_cast<int>(Qg >> 32) >= p;
+    const int su = -ga.cs;
+    u = first ? g : g + su;
+    Q = first ? Qg : Qg + (su > 0 ? ga.q1 : -ga.q1);
+}
+
 // AS waves share each block of R rows, each taking every AS-th angle of the chunk; their sums are
 // added in LDS in wave order (a fixed order) before the epilogue.  A tile is 4 / AS blocks of R
 // rows: splitting the angles gives small images more workgroups without shrinking the staged
@@ -813,28 +834,101 @@ __global__ __launch_bounds__(kBlock) void k_backproject_gather(WorkList<GatherIt
             const T *yw = ywin[a];
             if (ga.row) {
                 // interpolation along the row: cell p = j; the ray of cell j - 1 is the left lane's
+                bool walked = false;
+                if constexpr (std::is_same<T, float>::value && kGatherRows >= 4) {
+                    // FP32, 4 rows per wave: one candidate search at the first row, then the
+                    // first ray (in cell order) whose cell is >= j is carried from row to row:
+                    // all cells shift by q2 per row, at most one ray spacing (|a2| <= 1 <= |a1|
+                    // for row-walked angles; checked), so it moves by at most one ray, backwards
+                    // when q2 >= 0.  (With 2 rows the rows' independent searches are faster: the
+                    // walk chains them, and small launches are latency-bound.)
+                    const int su = -ga.cs;
+                    const int64_t sq1 = su > 0 ? ga.q1 : -ga.q1;
+                    const int64_t q2 = ga.q2;
+                    if ((q2 >= 0 ? q2 : -q2) <= sq1) {
+                        walked = true;
+                        int u;
+                        int64_t Q;
+                        cell_walk_start(ga, j, fma(static_cast<T>(i0), ga.a2, ga.a0),
+                                        ga.q0 + static_cast<int64_t>(i0) * q2, B, u, Q);
+                        auto rows = [&](auto backwards) {
+                            constexpr bool kBack = decltype(backwards)::value;
 #pragma unroll
-                for (int r = 0; r < kGatherRows; ++r) {
-                    const int i = i0 + r;
-                    const T c = fma(static_cast<T>(i), ga.a2, ga.a0);
-                    const int64_t base = ga.q0 + static_cast<int64_t>(i) * ga.q2;
-                    T own, next;
-                    cell_ray(ga, j, c, base, yw, ub, B, own, next);
-                    acc[r] += own + lane_from_left(next);
+                            for (int r = 0; r < kGatherRows; ++r) {
+                                if (r > 0) {
+                                    Q += q2;
+                                    if constexpr (kBack) {
+                                        const int64_t Qb = Q - sq1;
+                                        const bool back = static_cast<int>(Qb >> 32) >= j;
+                                        u = back ? u - su : u;
+                                        Q = back ? Qb : Q;
+                                    } else {
+                                        const bool on = static_cast<int>(Q >> 32) < j;
+                                        u = on ? u + su : u;
+                                        Q = on ? Q + sq1 : Q;
+                                    }
+                                }
+                                const bool hit = static_cast<int>(Q >> 32) == j;
+                                const T w = static_cast<T>(static_cast<uint32_t>(Q));
+                                const T y0 = yw[min(max(u - ub, 0), kGatherWin - 1)];
+                                const T m = w * (y0 * T(0x1p-32f));
+                                acc[r] += (hit ? y0 - m : T(0)) + lane_from_left(hit ? m : T(0));
+                            }
+                        };
+                        if (q2 >= 0)
+                            rows(std::true_type{});
+                        else
+                            rows(std::false_type{});
+                    }
+                }
+                if (!walked) {
+#pragma unroll
+                    for (int r = 0; r < kGatherRows; ++r) {
+                        const int i = i0 + r;
+                        const T c = fma(static_cast<T>(i), ga.a2, ga.a0);
+                        const int64_t base = ga.q0 + static_cast<int64_t>(i) * ga.q2;
+                        T own, next;
+                        cell_ray(ga, j, c, base, yw, ub, B, own, next);
+                        acc[r] += own + lane_from_left(next);
+                    }
                 }
             } else {
                 // interpolation along the column: cell p = i; the ray of cell i - 1 is the
                 // previous row's, so each wave also looks up the row above its first
                 const T c = fma(static_cast<T>(j), ga.a2, ga.a0);
                 const int64_t base = ga.q0 + static_cast<int64_t>(j) * ga.q2;
-                T own, prev;
-                cell_ray(ga, i0 - 1, c, base, yw, ub, B, own, prev);
+                if constexpr (std::is_same<T, float>::value) {
+                    // FP32: the column's rays taken in the order of their cells, from the first
+                    // whose cell is >= i0 - 1 (cell_walk_start); after each row the walk moves on
+                    // by one ray exactly when that row's cell held the current one (at most one
+                    // ray per cell), so each row costs one check instead of a candidate search
+                    int u;
+                    int64_t Q;
+                    cell_walk_start(ga, i0 - 1, c, base, B, u, Q);
+                    const int su = -ga.cs;                       // +1: cells grow with u
+                    const int64_t sq1 = su > 0 ? ga.q1 : -ga.q1;   // one ray on, in cell order
+                    T prev = T(0);
 #pragma unroll
-                for (int r = 0; r < kGatherRows; ++r) {
-                    T next;
-                    cell_ray(ga, i0 + r, c, base, yw, ub, B, own, next);
-                    acc[r] += own + prev;
-                    prev = next;
+                    for (int r = -1; r < kGatherRows; ++r) {
+                        const bool hit = static_cast<int>(Q >> 32) == i0 + r;
+                        const T w = static_cast<T>(static_cast<uint32_t>(Q));
+                        const T y0 = yw[min(max(u - ub, 0), kGatherWin - 1)];
+                        const T m = w * (y0 * T(0x1p-32f));
+                        if (r >= 0) acc[r] += (hit ? y0 - m : T(0)) + prev;
+                        prev = hit ? m : T(0);
+                        u += hit ? su : 0;
+                        Q += hit ? sq1 : 0;
+                    }
+                } else {
+                    T own, prev;
+                    cell_ray(ga, i0 - 1, c, base, yw, ub, B, own, prev);
+#pragma unroll
+                    for (int r = 0; r < kGatherRows; ++r) {
+                        T next;
+                        cell_ray(ga, i0 + r, c, base, yw, ub, B, own, next);
+                        acc[r] += own + prev;
+                        prev = next;
+                    }
                 }
             }
         }
