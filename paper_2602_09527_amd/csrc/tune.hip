@@ -58,6 +58,7 @@ static int max_groups(const ps_geometry *g) { return n_image(g) > kBigImage ? 4 
 
 struct TuneLayout {
     size_t x, y, img, pws, bws, fws, dual, total;
+    size_t xs, dx, h, gs, v;   // the other images a solver iteration reads or writes
     size_t pws_bytes, bws_bytes, fws_bytes;
 };
 
@@ -81,8 +82,47 @@ static TuneLayout tune_layout(const ps_geometry *g) {
     L.fws_bytes = fgp_workspace(g);
     L.fws = take(L.fws_bytes);
     L.dual = take(static_cast<size_t>(g->tv_dims) * n * g->elem);
+    L.xs = take(n * g->elem);
+    L.dx = take(n * g->elem);
+    L.h = take(n * g->elem);
+    L.gs = take(n * g->elem);
+    L.v = take(n * g->elem);
     L.total = off;
     return L;
+}
+
+// The projection and backprojection of a solver iteration, on the tuning workspace: a subset's
+// projection reads x and the snapshot xs (or the kept difference image alone, where the solver
+// keeps one) and its backprojection applies the SVRG step; all angles project xs and apply the
+// snapshot step.  Candidates are timed as the solver runs them, epilogue included (the gather
+// applies it in its own launch, the scatter in its combine pass).  x is the image at L.img.
+static ProjCall tune_projection(const ps_geometry *g, int subset, const TuneLayout &L, unsigned char *w) {
+    if (subset < 0) return ProjCall{g, -1, w + L.xs, nullptr, nullptr, w + L.y, w + L.pws, L.pws_bytes};
+    if (solver_reads_one_image(g)) return ProjCall{g, subset, w + L.dx, nullptr, nullptr, w + L.y, w + L.pws, L.pws_bytes};
+    return ProjCall{g, subset, w + L.img, w + L.xs, nullptr, w + L.y, w + L.pws, L.pws_bytes};
+}
+
+static BackCall tune_backprojection(const ps_geometry *g, int subset, const TuneLayout &L, unsigned char *w) {
+    BackCall c{};
+    c.g = g;
+    c.subset = subset;
+    c.y = w + L.y;
+    c.out = w + L.img;
+    c.mode = subset < 0 ? BP_SNAPSHOT : BP_SVRG;
+    c.upd.x = w + L.img;
+    c.upd.h = w + L.h;
+    c.upd.gs = w + L.gs;
+    c.upd.vout = w + L.v;
+    if (solver_reads_one_image(g)) {
+        c.upd.xs = w + L.xs;
+        c.upd.dx = w + L.dx;
+    }
+    c.upd.gamma = 1e-9;          // tiny steps: the repeated calls keep x finite
+    c.upd.gamma_over_p = 1e-8;
+    c.upd.nsub = static_cast<double>(g->desc.n_subsets);
+    c.ws = w + L.bws;
+    c.ws_bytes = L.bws_bytes;
+    return c;
 }
 
 struct Timer {
@@ -201,6 +241,7 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
     PS_HIP(hipEventCreate(&tm.e1));
     PS_TRY(fill(g, w + L.x, n, st));
     PS_TRY(fill(g, w + L.y, static_cast<size_t>(d.nz) * d.n_angles * d.n_bins, st));
+    for (size_t off : {L.img, L.xs, L.dx, L.h, L.gs, L.v}) PS_TRY(fill(g, w + off, n, st));
 
     ps_plan best = g->plan;
     const ps_plan saved = g->plan;
@@ -230,9 +271,8 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
             (full ? trial.proj_split_full : trial.proj_split_subset) = cand[c];
             g->plan = trial;
             float ms = 0.f;
-            PS_TRY(restore_on_error(time_calls([&] {
-                return launch_project(g, subset, w + L.x, nullptr, nullptr, w + L.y, w + L.pws, L.pws_bytes, st);
-            }, r, st, tm, &ms)));
+            const ProjCall pc = tune_projection(g, subset, L, w);
+            PS_TRY(restore_on_error(time_calls([&] { return launch_project_many(&pc, 1, st); }, r, st, tm, &ms)));
             if (!have || ms < best_ms * (best_s == cand[0] ? kMinGain : 1.0f)) {
                 best_ms = ms;
                 best_s = cand[c];
@@ -250,7 +290,10 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
     }
 
     // backprojector: scatter with (strip, groups), or the gather, for all angles (when short)
-    // then subset 0
+    // then subset 0.  For subsets the fastest scatter plan and the fastest gather tile are kept
+    // for the pair stage below, which decides between them.
+    std::array<int, 3> sub_scatter{}, sub_gather{};
+    bool have_scatter = false, have_gather = false;
     for (int full = first_pass; full >= 0; --full) {
         const int subset = full ? -1 : 0;
         g->plan = best;
@@ -296,10 +339,8 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
                 if (back_workspace(g, subset) > L.bws_bytes) continue;
             }
             float ms = 0.f;
-            PS_TRY(restore_on_error(time_calls([&] {
-                return launch_backproject(g, subset, w + L.y, w + L.img, BP_OVERWRITE, nullptr, w + L.bws,
-                                          L.bws_bytes, st);
-            }, r, st, tm, &ms)));
+            const BackCall bc = tune_backprojection(g, subset, L, w);
+            PS_TRY(restore_on_error(time_calls([&] { return launch_backproject_many(&bc, 1, st); }, r, st, tm, &ms)));
             timed.push_back({ms, c});
             if (c == 0 && full && ms > kLongLaunchMs) break;
         }
@@ -325,6 +366,25 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
                 }
             }
         }
+        if (!full) {
+            float sc_ms = 0.f, ga_ms = 0.f;
+            for (const auto &t : timed) {
+                const std::array<int, 3> &k = cand[t.second];
+                if (k[0] == BP_SCATTER && (!have_scatter || t.first < sc_ms)) {
+                    sc_ms = t.first;
+                    sub_scatter = k;
+                    have_scatter = true;
+                } else if (k[0] == BP_GATHER && (!have_gather || t.first < ga_ms)) {
+                    ga_ms = t.first;
+                    sub_gather = k;
+                    have_gather = true;
+                }
+            }
+            for (const auto &t : timed) {   // fewer angle groups within 3%, as above
+                const std::array<int, 3> &k = cand[t.second];
+                if (k[0] == BP_SCATTER && t.first <= sc_ms / kMinGain && k[2] < sub_scatter[2]) sub_scatter = k;
+            }
+        }
         if (full) {
             best.bp_method_full = pick[0];
             if (pick[0] == BP_SCATTER) {
@@ -343,31 +403,35 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
         }
     }
 
-    // a subset's projection and gather backprojection as a solver iteration runs them, with the
-    // reduction pass or (split > 1) with the gather adding the partials itself: first every
-    // projector split with the gather tile chosen above, then every gather tile (rows per wave,
-    // angle split) with the split chosen.  The plan chosen so far is timed first and is the one
-    // to beat; the pairs are short, so each is timed over enough calls to fill about 5 ms
+    // A subset's projection and backprojection as a solver iteration runs them (the pair), which
+    // decides the subset method where the gather applies: the scatter (fastest plan above) at
+    // every projector split, and the gather (fastest tile above) at every split with the
+    // reduction pass or (split > 1) adding the partials itself; then, if the gather wins, every
+    // gather tile (rows per wave, angle split) at the split chosen.  The plan chosen so far is
+    // timed first and is the one to beat; pairs are short, so each is timed over enough calls to
+    // fill about 5 ms.
     g->plan = best;
-    if (back_method(g, 0) == BP_GATHER) {
-        // {projector split, fused, gather rows, gather angle split}
-        using Pair = std::array<int, 4>;
+    if (have_gather) {
+        // {method, projector split, fused, strip or rows, groups or angle split}
+        using Pair = std::array<int, 5>;
+        auto plan_of = [&](const Pair &k) {
+            ps_plan t = best;
+            t.bp_method_subset = k[0];
+            t.proj_split_subset = k[1];
+            t.bp_gather_fused = k[2];
+            if (k[0] == BP_SCATTER) {
+                t.bp_strip_subset = k[3];
+                t.bp_groups_subset = k[4];
+            } else {
+                t.bp_gather_rows = k[3];
+                t.bp_gather_split = k[4];
+            }
+            return t;
+        };
         auto time_pair = [&](const Pair &k, int r, float *ms) -> ps_status {
-            ps_plan trial = best;
-            trial.proj_split_subset = k[0];
-            trial.bp_gather_fused = k[1];
-            trial.bp_gather_rows = k[2];
-            trial.bp_gather_split = k[3];
-            g->plan = trial;
-            ProjCall pc{g, 0, w + L.x, nullptr, nullptr, w + L.y, w + L.pws, L.pws_bytes};
-            BackCall bc{};
-            bc.g = g;
-            bc.subset = 0;
-            bc.y = w + L.y;
-            bc.out = w + L.img;
-            bc.mode = BP_OVERWRITE;
-            bc.ws = w + L.bws;
-            bc.ws_bytes = L.bws_bytes;
+            g->plan = plan_of(k);
+            ProjCall pc = tune_projection(g, 0, L, w);
+            BackCall bc = tune_backprojection(g, 0, L, w);
             if (gather_fused(g, 0)) {
                 pc.first_pass_only = true;
                 bc.y = w + L.pws;
@@ -378,8 +442,11 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
                 return launch_backproject_many(&bc, 1, st);
             }, r, st, tm, ms);
         };
-        const Pair first{proj_plan(g, max_subset_count(g)).split, gather_fused(g, 0) ? 2 : 1,
-                         gather_rows(g, 0), gather_split(g, 0)};
+        const int m0 = back_method(g, 0);
+        const BackPlan bp0 = back_plan(g, 0);
+        const Pair first{m0, proj_plan(g, max_subset_count(g)).split, gather_fused(g, 0) ? 2 : 1,
+                         m0 == BP_SCATTER ? bp0.strip : gather_rows(g, 0),
+                         m0 == BP_SCATTER ? bp0.groups : gather_split(g, 0)};
         float est = 0.f;
         PS_TRY(restore_on_error(time_pair(first, reps, &est)));
         const int r = std::max(reps, std::min(100, static_cast<int>(5.0f / std::max(est, 1e-3f))));
@@ -388,10 +455,10 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
         PS_TRY(restore_on_error(time_pair(first, r, &best_ms)));
         auto consider = [&](const Pair &k) -> ps_status {
             if (k == first) return PS_OK;
-            ps_plan trial = best;
-            trial.proj_split_subset = k[0];
-            g->plan = trial;
-            if (proj_plan(g, max_subset_count(g)).split != k[0]) return PS_OK;   // clamped
+            g->plan = plan_of(k);
+            if (proj_plan(g, max_subset_count(g)).split != k[1]) return PS_OK;   // clamped
+            if (back_method(g, 0) != k[0]) return PS_OK;
+            if (k[0] == BP_SCATTER && back_workspace(g, 0) > L.bws_bytes) return PS_OK;
             float ms = 0.f;
             PS_TRY(time_pair(k, r, &ms));
             if (ms < best_ms * (pick == first ? kMinGain : 1.0f)) {
@@ -400,19 +467,23 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
             }
             return PS_OK;
         };
-        for (int s : splits)
+        for (int s : splits) {
+            if (s > max_split) continue;
+            if (have_scatter)
+                PS_TRY(restore_on_error(consider({BP_SCATTER, s, 1, sub_scatter[1], sub_scatter[2]})));
             for (int f : {1, 2})
-                if (s <= max_split && (f == 1 || s > 1))
-                    PS_TRY(restore_on_error(consider({s, f, first[2], first[3]})));
-        const int split_pick = pick[0];
-        for (int rows : {2, 4})
-            for (int as : {1, 2, 4})
-                for (int f : {1, 2})
-                    if (f == 1 || split_pick > 1) PS_TRY(restore_on_error(consider({split_pick, f, rows, as})));
-        best.proj_split_subset = pick[0];
-        best.bp_gather_fused = pick[1];
-        best.bp_gather_rows = pick[2];
-        best.bp_gather_split = pick[3];
+                if (f == 1 || s > 1)
+                    PS_TRY(restore_on_error(consider({BP_GATHER, s, f, sub_gather[1], sub_gather[2]})));
+        }
+        if (pick[0] == BP_GATHER) {
+            const int split_pick = pick[1];
+            for (int rows : {2, 4})
+                for (int as : {1, 2, 4})
+                    for (int f : {1, 2})
+                        if (f == 1 || split_pick > 1)
+                            PS_TRY(restore_on_error(consider({BP_GATHER, split_pick, f, rows, as})));
+        }
+        best = plan_of(pick);
     }
 
     // 2D FGP tile shape and inner iterations per launch: one 50-iteration prox per timed call;
