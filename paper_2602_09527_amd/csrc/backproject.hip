@@ -534,7 +534,9 @@ __global__ __launch_bounds__(kBlock) void k_backproject_combine(WorkList<Combine
 //   among the two integers around u* = (p - a0 - s a2) / a1 (each checked exactly).  Each
 //   lane finds the ray of its own cell; the ray of cell p - 1 is its neighbour's: the lane to the
 //   left for row-walked angles (a DPP lane shift; lane 0 is a halo column that only supplies
-//   this), the lane's previous row for column-walked ones (one extra lookup per wave).
+//   this), the lane's previous row for column-walked ones (one extra lookup per wave).  In FP32
+//   the search runs once per angle and the lane then walks its rays in cell order from row to
+//   row (cell_walk_start), which takes the same rays and gives the same bits.
 //   The rays an angle can send into the tile form a window of at most kGatherWin consecutive
 //   bins; the windows of up to kGatherChunk angles (y / |.|, zero outside [0, B)) are staged in
 //   LDS at a time.
