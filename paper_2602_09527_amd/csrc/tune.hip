@@ -65,7 +65,8 @@ struct TuneLayout {
 static TuneLayout tune_layout(const ps_geometry *g) {
     const auto &d = g->desc;
     const size_t n = n_image(g);
-    const int a_tuned = tune_full(g) ? d.n_angles : max_subset_count(g);
+    // all angles when they are tuned, or when the all-angle method is chosen (gather allowed)
+    const int a_tuned = tune_full(g) || g->gather_ok ? d.n_angles : max_subset_count(g);
     const size_t m = static_cast<size_t>(d.nz) * a_tuned * d.n_bins;
     TuneLayout L{};
     size_t off = 0;
@@ -294,6 +295,7 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
     // for the pair stage below, which decides between them.
     std::array<int, 3> sub_scatter{}, sub_gather{};
     bool have_scatter = false, have_gather = false;
+    bool full_untuned = !tune_full(g);   // all-angle candidates not timed (too long)
     for (int full = first_pass; full >= 0; --full) {
         const int subset = full ? -1 : 0;
         g->plan = best;
@@ -342,7 +344,10 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
             const BackCall bc = tune_backprojection(g, subset, L, w);
             PS_TRY(restore_on_error(time_calls([&] { return launch_backproject_many(&bc, 1, st); }, r, st, tm, &ms)));
             timed.push_back({ms, c});
-            if (c == 0 && full && ms > kLongLaunchMs) break;
+            if (c == 0 && full && ms > kLongLaunchMs) {
+                full_untuned = true;
+                break;
+            }
         }
         // the method and plan: the automatic one unless another is 3% faster, else the fastest
         for (const auto &t : timed) {
@@ -484,6 +489,27 @@ extern "C" ps_status geometry_autotune(ps_geometry *g, void *workspace, size_t w
                             PS_TRY(restore_on_error(consider({BP_GATHER, split_pick, f, rows, as})));
         }
         best = plan_of(pick);
+    }
+
+    // All-angle backprojection too long to tune fully (it runs once per epoch, at the snapshot):
+    // the plan's method against the gather on the tile chosen above, one timed call each.  On the
+    // 1024^2 x 256 volume the gather took 356 ms against the scatter's 414.
+    if (full_untuned && g->gather_ok) {
+        g->plan = best;
+        const int m0 = back_method(g, -1);
+        float ms0 = 0.f, ms1 = 0.f;
+        const BackCall b0 = tune_backprojection(g, -1, L, w);
+        if (m0 == BP_GATHER || back_workspace(g, -1) <= L.bws_bytes) {
+            PS_TRY(restore_on_error(time_calls([&] { return launch_backproject_many(&b0, 1, st); }, 1, st, tm, &ms0)));
+            ps_plan trial = best;
+            trial.bp_method_full = m0 == BP_GATHER ? BP_SCATTER : BP_GATHER;
+            g->plan = trial;
+            if (trial.bp_method_full == BP_GATHER || back_workspace(g, -1) <= L.bws_bytes) {
+                const BackCall b1 = tune_backprojection(g, -1, L, w);
+                PS_TRY(restore_on_error(time_calls([&] { return launch_backproject_many(&b1, 1, st); }, 1, st, tm, &ms1)));
+                if (ms1 < ms0 * kMinGain) best.bp_method_full = trial.bp_method_full;
+            }
+        }
     }
 
     // 2D FGP tile shape and inner iterations per launch: one 50-iteration prox per timed call;
