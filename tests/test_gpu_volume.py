@@ -12,9 +12,11 @@ torch = pytest.importorskip("torch")
 
 @pytest.fixture(scope="module")
 def vol():
-    from paper_2602_09527_amd import api, workloads
+    # the stored MI355X plan, as the solver's runs take it (subsets and all angles by the gather)
+    from paper_2602_09527_amd import api, serve, workloads
     w = workloads.VOLUME_3D
     g = api.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=w.n_subsets, nz=w.nz)
+    api.autotune(g, cache_path=serve.PLANS_FILE, store=False, tune_missing=False)
     gen = torch.Generator(device="cuda").manual_seed(404)
     x = torch.rand(g.image_shape, device="cuda", generator=gen)
     return w, g, x
@@ -33,6 +35,7 @@ def test_full_size_projection_sampled(orc, vol):
         if subset == -1:
             # all 1800 angles on a 2-slice volume of the same 1024^2 x 1448 geometry
             g2 = api.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=w.n_subsets, nz=2)
+            g2.set_plan(g.get_plan())
             xs = x[100:102].contiguous()
             y = api.project(g2, xs, -1)
             zsel = [100, 101]
@@ -60,12 +63,19 @@ def test_full_size_backprojection_sampled(orc, vol):
     w, g, x = vol
     rng = np.random.default_rng(22)
     gen = torch.Generator(device="cuda").manual_seed(5)
-    for subset in (3, 29):
-        y = torch.randn(g.sino_shape(subset), device="cuda", generator=gen)
-        img = api.backproject(g, y, subset)
+    plan = g.get_plan()
+    # both backprojector methods (the stored plan takes the gather where it applies)
+    for method, subset in ((1, 3), (2, 3), (1, 29), (2, 29), (1, -1), (2, -1)):
+        # all 1800 angles on a 2-slice volume of the same geometry
+        gs = g if subset >= 0 else api.Geometry(w.nx, w.ny, w.n_angles, w.n_bins,
+                                               n_subsets=w.n_subsets, nz=2)
+        gs.set_plan(dict(plan, bp_method_subset=method, bp_method_full=method))
+        assert gs.get_plan()["bp_method_subset" if subset >= 0 else "bp_method_full"] == method
+        y = torch.randn(gs.sino_shape(subset), device="cuda", generator=gen)
+        img = api.backproject(gs, y, subset)
         torch.cuda.synchronize()
         n = 200
-        zs = rng.choice(rng.choice(w.nz, 6, replace=False), n)
+        zs = rng.choice(rng.choice(gs.nz, min(6, gs.nz), replace=False), n)
         is_, js = rng.integers(0, w.ny, n), rng.integers(0, w.nx, n)
         got = img[zs, is_, js].double().cpu().numpy()
         uz, pos = _slices(zs)
@@ -73,7 +83,8 @@ def test_full_size_backprojection_sampled(orc, vol):
         o = orc.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=w.n_subsets, nz=len(uz))
         ref = orc.backproject_pixels(o, ysel, np.array([pos[int(z)] for z in zs], dtype=np.int32),
                                      is_, js, subset)
-        assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref), subset
+        assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref), (method, subset)
+    g.set_plan(plan)
 
 
 def test_3d_fgp_subvolume(orc):
