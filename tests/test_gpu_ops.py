@@ -262,3 +262,24 @@ def test_solver_with_device_alloc_workspaces(monkeypatch):
     (xa, ha, za, da, pa), (xb, hb, zb, db, pb) = runs
     assert pa == pb
     assert torch.equal(xa, xb) and torch.equal(ha, hb) and torch.equal(za, zb) and torch.equal(da, db)
+
+
+@pytest.mark.parametrize("shape", [(97, 131, 2, 77, 211, 6, 1.3, 0.45), (200, 70, 1, 45, 260, 5, 1.0, -2.5),
+                                   (300, 300, 1, 361, 500, 19, 1.7, 0.0), (128, 128, 1, 180, 128, 10, 1.0, 0.0)])
+def test_gather_matches_scatter_pixelwise(shape):
+    # the gather's ray search and walks against the scatter, pixel by pixel: a ray missed or
+    # taken twice at one pixel moves that pixel by about |y| / |.|, far beyond the max-norm bar,
+    # while an L2 bar over the image could hide it
+    from paper_2602_09527_amd import api
+    nx, ny, nz, A, B, N, bw, off = shape
+    g = api.Geometry(nx, ny, A, B, n_subsets=N, nz=nz, bin_width=bw, det_offset=off)
+    gen = torch.Generator(device="cuda").manual_seed(nx + A)
+    for subset in (-1, 0, N // 2):
+        y = torch.randn(g.sino_shape(subset), device="cuda", generator=gen)
+        g.set_plan(dict(bp_method_full=1, bp_method_subset=1))
+        ref = api.backproject(g, y, subset).double()
+        for rows in (2, 4):
+            g.set_plan(dict(bp_method_full=2, bp_method_subset=2, bp_gather_rows=rows, bp_gather_split=1))
+            got = api.backproject(g, y, subset).double()
+            err = float((got - ref).abs().max())
+            assert err <= 1e-5 * float(ref.abs().max()), (subset, rows, err)
