@@ -104,6 +104,9 @@ def parse():
     ap.add_argument("--ref-iters", type=int, default=100000,
                     help="PDHG iterations of the reference x* (the paper uses 2e5)")
     ap.add_argument("--eps-passes", type=int, default=200, help="data passes per method at most")
+    ap.add_argument("--subset-sweep", action="store_true",
+                    help="also run ProxSVRGSkip (p = 0.3) against ProxSVRG for N in {10, 50, 100, "
+                         "200, 400} subsets on the time-to-epsilon problem (about a minute)")
     ap.add_argument("--eps-alpha", type=float, default=50.0,
                     help="TV weight of the time-to-epsilon problem: 50 makes 1e-5 reachable in 200 "
                          "data passes; at the workload's 0.005 the problem is nearly unregularised "
@@ -148,13 +151,9 @@ def stored_L(w):
         return None
 
 
-def time_to_eps(api, torch, g, b, w, gamma, ref_iters, passes, alpha):
-    """The paper's protocol (Sec. 2.1): wall time and data passes until the squared relative
-    error ||x - x*||^2 / ||x*||^2 falls below 1e-3 and 1e-5 (at most `passes` data passes; one
-    pass = N subset gradients, or one iteration of a deterministic method), with x* from
-    preconditioned PDHG (the reference method of the data-splitting figure).  Step sizes as in the
-    paper's comparison of all methods (Sec. 3): 1.99/L for ISTA and deterministic ProxSkip, 1/L
-    for FISTA and the SVRG family, 1/(3L) for SAGA; `gamma` is 1/L."""
+def reference_solution(api, torch, g, b, w, ref_iters, alpha):
+    """x* by preconditioned PDHG (the reference method of the data-splitting figure), with the
+    squared relative change over its second half as a convergence check."""
     t0 = time.perf_counter()
     half = ref_iters // 2
     xs, y1, y2 = api.pdhg(g, b, alpha=alpha, n_iters=half, nonneg=w.nonneg)
@@ -167,13 +166,44 @@ def time_to_eps(api, torch, g, b, w, gamma, ref_iters, passes, alpha):
     ref_change = float(((xstar - x_half.double()) ** 2).sum()) / n2
     log(f"bench: reference x*: {ref_iters} PDHG iterations in {t_ref:.1f} s; squared change over "
         f"the last {ref_iters - half}: {ref_change:.2e}")
+    return {"xstar": xstar, "n2": n2, "seconds": t_ref, "change": ref_change, "iterations": ref_iters}
+
+
+def run_to_eps(torch, step, current, ref, passes):
+    """Data passes (calls of `step`) until ||x - x*||^2 / ||x*||^2 < 1e-5, at most `passes`; the
+    passes and seconds (GPU work of the steps only) at which 1e-3 and 1e-5 were first reached."""
+    def err(x):
+        d = x.double() - ref["xstar"]
+        return float((d * d).sum()) / ref["n2"]
+    elapsed, hit, e_now, e = 0.0, {}, None, 0
+    for e in range(1, passes + 1):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        elapsed += time.perf_counter() - t1
+        e_now = err(current())
+        for eps in (1e-3, 1e-5):
+            if eps not in hit and e_now < eps:
+                hit[eps] = (e, elapsed)
+        if 1e-5 in hit:
+            break
+    rec = {"passes": e, "seconds": round(elapsed, 4), "final_sq_rel_err": e_now}
+    for eps, tag in ((1e-3, "1e-3"), (1e-5, "1e-5")):
+        rec[f"passes_to_{tag}"] = hit[eps][0] if eps in hit else None
+        rec[f"seconds_to_{tag}"] = round(hit[eps][1], 4) if eps in hit else None
+    return rec
+
+
+def time_to_eps(api, torch, g, b, w, gamma, ref, passes, alpha):
+    """The paper's protocol (Sec. 2.1): wall time and data passes until the squared relative
+    error ||x - x*||^2 / ||x*||^2 falls below 1e-3 and 1e-5 (at most `passes` data passes; one
+    pass = N subset gradients, or one iteration of a deterministic method), with x* from
+    reference_solution.  Step sizes as in the paper's comparison of all methods (Sec. 3): 1.99/L
+    for ISTA and deterministic ProxSkip, 1/L for FISTA and the SVRG family, 1/(3L) for SAGA;
+    `gamma` is 1/L."""
     g1 = api.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=1, device=g.device)
     api.autotune(g1, reps=3, cache_path=PLANS_FILE, store=False)
-
-    def err(x):
-        d = x.double() - xstar
-        return float((d * d).sum()) / n2
-
     specs = [("ProxSVRGSkip p=0.1", g, dict(p=0.1)),
              ("ProxSVRGSkip p=0.02", g, dict(p=0.02)),
              ("ProxSVRG", g, dict(p=1.0, plain_prox_svrg=True)),
@@ -195,23 +225,7 @@ def time_to_eps(api, torch, g, b, w, gamma, ref_iters, passes, alpha):
             prm.update(kw)
             sv = api.Solver(geom, b, api.SolverParams(**prm))
             step, current = (lambda: sv.epochs(1)), (lambda: sv.x)
-        elapsed, hit, e_now = 0.0, {}, None
-        for e in range(1, passes + 1):
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            step()
-            torch.cuda.synchronize()
-            elapsed += time.perf_counter() - t1
-            e_now = err(current())
-            for eps in (1e-3, 1e-5):
-                if eps not in hit and e_now < eps:
-                    hit[eps] = (e, elapsed)
-            if 1e-5 in hit:
-                break
-        rec = {"method": label, "passes": e, "seconds": round(elapsed, 4), "final_sq_rel_err": e_now}
-        for eps, tag in ((1e-3, "1e-3"), (1e-5, "1e-5")):
-            rec[f"passes_to_{tag}"] = hit[eps][0] if eps in hit else None
-            rec[f"seconds_to_{tag}"] = round(hit[eps][1], 4) if eps in hit else None
+        rec = {"method": label, **run_to_eps(torch, step, current, ref, passes)}
         runs.append(rec)
         log(f"bench: to eps {label}: " + " ".join(f"{k}={v}" for k, v in rec.items() if k != "method"))
     del g1
@@ -225,10 +239,36 @@ def time_to_eps(api, torch, g, b, w, gamma, ref_iters, passes, alpha):
             if base and t:
                 speedup[f"{m} at {tag}"] = round(base / t, 2)
     return {"alpha": alpha, "skip_speedup_vs_ProxSVRG": speedup,
-            "reference": {"method": "preconditioned PDHG", "iterations": ref_iters,
-                          "seconds": round(t_ref, 2), "sq_change_last_half": ref_change},
+            "reference": {"method": "preconditioned PDHG", "iterations": ref["iterations"],
+                          "seconds": round(ref["seconds"], 2), "sq_change_last_half": ref["change"]},
             "criterion": "||x - x*||^2 / ||x*||^2 < eps, at most %d data passes" % passes,
             "runs": runs}
+
+
+def subset_sweep(api, torch, w, b, gamma, ref, passes, alpha, p=0.3, ns=(10, 50, 100, 200, 400)):
+    """ProxSVRGSkip at p = 0.3 against the non-skipped ProxSVRG over the number of subsets N, on
+    the time-to-epsilon problem (the paper varies N at fixed p in its ProxSVRG comparison, Sec.
+    2.1): data passes and seconds to 1e-3 and 1e-5 of the squared relative error, at most
+    `passes` passes.  Each N's geometry is tuned (plans not stored); gamma = 1/L for all N (L
+    does not depend on the split)."""
+    out = []
+    for n in ns:
+        gn = api.Geometry(w.nx, w.ny, w.n_angles, w.n_bins, n_subsets=n)
+        api.autotune(gn, reps=3, cache_path=PLANS_FILE, store=False)
+        row = {"N": n}
+        for label, kw in (("skip", dict(p=p)), ("noskip", dict(p=1.0, plain_prox_svrg=True))):
+            sv = api.Solver(gn, b, api.SolverParams(gamma=gamma, alpha=alpha, fgp_inner=w.fgp_inner,
+                                                    n_epochs=passes, nonneg=w.nonneg, seed=w.seed + 2, **kw))
+            row[label] = run_to_eps(torch, lambda: sv.epochs(1), lambda: sv.x, ref, passes)
+            del sv
+        for tag in ("1e-3", "1e-5"):
+            a, c = row["noskip"][f"seconds_to_{tag}"], row["skip"][f"seconds_to_{tag}"]
+            row[f"skip_speedup_at_{tag}"] = round(a / c, 2) if a and c else None
+        log(f"bench: subset sweep N={n}: {row}")
+        out.append(row)
+        del gn
+    return {"p": p, "alpha": alpha, "criterion": "||x - x*||^2 / ||x*||^2 < eps, at most %d data passes" % passes,
+            "rows": out}
 
 
 def volume_ops():
@@ -900,9 +940,13 @@ def main():
         out["sweep"] = sweep
 
     # ---- time to epsilon against the reference x* ------------------------------------------
-    if not args.no_eps:
-        out["time_to_eps"] = time_to_eps(api, torch, g, b, w, gamma, args.ref_iters, args.eps_passes,
-                                         args.eps_alpha)
+    if not args.no_eps or args.subset_sweep:
+        ref = reference_solution(api, torch, g, b, w, args.ref_iters, args.eps_alpha)
+        if not args.no_eps:
+            out["time_to_eps"] = time_to_eps(api, torch, g, b, w, gamma, ref, args.eps_passes, args.eps_alpha)
+        if args.subset_sweep:
+            out["subset_sweep"] = subset_sweep(api, torch, w, b, gamma, ref, args.eps_passes, args.eps_alpha)
+        del ref
 
     # ---- batched independent slices: 64 solves of 128^2 (180 x 128, N = 10) ----------------
     if not args.no_batch:
