@@ -879,6 +879,7 @@ def main():
     # ---- differentiable projector on a batch of 64 images of 256^2 (360 x 384, all angles) ---
     wa = workloads.AUTOGRAD_BATCH
     ga = api.Geometry(wa.nx, wa.ny, wa.n_angles, wa.n_bins, nz=wa.nz, device=dev)
+    api.autotune(ga, cache_path=PLANS_FILE, store=False, tune_missing=False)   # its stored plan
     xa = torch.rand(ga.image_shape, device=dev)
     ya = torch.empty(ga.sino_shape(-1), device=dev)
     ta_f = event_time(lambda: api.project(ga, xa, -1, out=ya), reps=10)
