@@ -882,8 +882,10 @@ def main():
     api.autotune(ga, cache_path=PLANS_FILE, store=False, tune_missing=False)   # its stored plan
     xa = torch.rand(ga.image_shape, device=dev)
     ya = torch.empty(ga.sino_shape(-1), device=dev)
-    ta_f = event_time(lambda: api.project(ga, xa, -1, out=ya), reps=10)
-    ta_b = event_time(lambda: api.backproject(ga, ya, -1, out=xa), reps=10)
+    # the median of three rounds of 10 calls, after the warm-up call: the first round of a fresh
+    # geometry's buffers ran up to 13% slower than later ones
+    ta_f = sorted(event_time(lambda: api.project(ga, xa, -1, out=ya), reps=10) for _ in range(3))[1]
+    ta_b = sorted(event_time(lambda: api.backproject(ga, ya, -1, out=xa), reps=10) for _ in range(3))[1]
     out["autograd_batch"] = {"workload": wa.name, "forward_images_per_s": round(wa.nz / ta_f, 1),
                              "backward_images_per_s": round(wa.nz / ta_b, 1),
                              "forward_ms": round(ta_f * 1e3, 3), "backward_ms": round(ta_b * 1e3, 3)}
